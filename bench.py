@@ -1,0 +1,203 @@
+"""Throughput of the fluctuating D3Q19 LB step with bead coupling on one MI355X.
+
+One step = one full LB step of every §-path stage: the chain's MD substeps in
+the frozen fluid with trilinear interpolation and impulse spreading, the
+fused collide+stream of every node, the re-collision of the impulse nodes.
+Inputs are seeded and synthetic (lbinputs.py) and resident in HBM before the
+timed region.  Prints one JSON line.
+
+Default workload: a single 256^3 box (16.8 M nodes, FP32 deviation storage),
+chain N = 1024, kT = 1e-4, the box whose step is bound by HBM bandwidth.
+Also reported: the 64^3 single box, the 256-box batched sweep against the
+same boxes launched box by box, and the dominant kernel against the HBM
+roofline.  The oracle is timed on the host cores on a bounded sample.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0        # MI355X HBM3E
+BYTES_PER_NODE = {0: 304, 1: 152}   # 19 reads + 19 writes of 8 or 4 bytes
+
+
+def log(*a):
+    print("[bench]", *a, file=sys.stderr, flush=True)
+
+
+def make_system(preset, precision=None, n_boxes=None):
+    import lbinputs
+    import paper_0903_5067_amd as lbm
+    P = lbinputs.PRESETS[preset]
+    prec = precision if precision is not None else (lbm.FP64 if P["precision"] == "fp64" else lbm.FP32_DEV)
+    if preset == "batched256":
+        table = lbinputs.batched_table(n_boxes or P["n_boxes"], P["seed"])
+        boxes = [lbinputs.box_params(preset, L=L, N=N, box_id=i) for i, (L, N) in enumerate(table)]
+    else:
+        boxes = [lbinputs.box_params(preset)]
+    xs = [lbinputs.saw_chain(b["N"], b["L"], b["seed"] + 7919 * b["box_id"]) for b in boxes]
+    x0 = np.concatenate([x for x in xs if len(x)], axis=0) if any(len(x) for x in xs) else None
+    s = lbm.LBSystem(boxes, precision=prec, bead_x0=x0)
+    nodes = sum(int(b["L"]) ** 3 for b in boxes)
+    return s, boxes, nodes, prec
+
+
+def time_steps(s, steps, warmup):
+    import torch
+    s.step(warmup)
+    s.synchronize()
+    torch.cuda.synchronize()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    t0 = time.perf_counter()
+    e0.record(s.stream)
+    s.step(steps)
+    e1.record(s.stream)
+    s.synchronize()
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    return e0.elapsed_time(e1) / 1e3, wall
+
+
+def time_collide(s, n):
+    """Average duration of the fused collide+stream kernel, HIP events on the
+    stream the library launches it on."""
+    import torch
+    s.collide_only(3)
+    s.synchronize()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record(s.stream)
+    s.collide_only(n)
+    e1.record(s.stream)
+    s.synchronize()
+    return e0.elapsed_time(e1) / 1e3 / n
+
+
+def cpu_baseline(preset, budget_s=20.0):
+    """The oracle (FP64 C, OpenMP) on the host cores: whole LB steps of the
+    same box and chain, as many as fit a ~20 s budget (at least one)."""
+    import lbinputs
+    import oracle
+    p = lbinputs.box_params(preset)
+    L = int(p["L"])
+    c, w, e, b = oracle.tables()
+    n = np.empty((19, L, L, L))
+    for i in range(19):
+        n[i] = w[i] * p["rho0"]
+    x0 = lbinputs.saw_chain(p["N"], L, p["seed"])
+    st = oracle.State(oracle.make_box(**p), n, x0)
+    t0 = time.perf_counter()
+    st.run(1)
+    t1 = time.perf_counter() - t0
+    steps = 1
+    more = int(max(0, min(50, budget_s / max(t1, 1e-3) - 1)))
+    if more:
+        t0 = time.perf_counter()
+        st.run(more)
+        t1 = time.perf_counter() - t0
+        steps = more
+    mlups = L ** 3 * steps / t1 / 1e6
+    return {"value": round(mlups, 3), "unit": "MLUPS", "cores": oracle.num_threads(), "kind": "oracle",
+            "sample": f"{steps} full LB step(s) of the {L}^3 box with its N={p['N']} chain, FP64 oracle, "
+                      f"{t1:.1f} s"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=2000)
+    ap.add_argument("--warmup", type=int, default=50)
+    ap.add_argument("--workload", default="prec256", choices=["prec256", "single64", "plain16"])
+    ap.add_argument("--no-secondary", action="store_true")
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--graph-steps", type=int, default=0)
+    args = ap.parse_args()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py runs on one GPU only: the path is built and measured for a single MI355X; "
+              "multi-GPU sharding is a design note, not part of this build", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    import lbinputs
+    torch.cuda.init()
+    log("workload", args.workload)
+    s, boxes, nodes, prec = make_system(args.workload)
+    if args.graph_steps:
+        s.set_launch(batched=True, graph_steps=args.graph_steps)
+    obs0 = s.observables()[0]
+    t_ev, t_wall = time_steps(s, args.steps, args.warmup)
+    obs1 = s.observables()[0]
+    ms = 1e3 * t_ev / args.steps
+    mlups = nodes * args.steps / t_ev / 1e6
+    log(f"{args.steps} steps: {t_ev:.4f} s (events), {t_wall:.4f} s (wall), {mlups:.1f} MLUPS")
+    n_coll = max(20, min(500, int(2.0 / max(ms / 1e3, 1e-6) / 4)))
+    t_k = time_collide(s, n_coll)
+    achieved = BYTES_PER_NODE[prec] * nodes / t_k / 1e9
+    log(f"collide kernel: {t_k * 1e6:.1f} us avg over {n_coll} launches, {achieved:.0f} GB/s")
+    P = lbinputs.PRESETS[args.workload]
+    result = {
+        "metric": "LB node updates/s (MLUPS) + % HBM peak",
+        "value": round(mlups, 2),
+        "unit": "MLUPS",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms, 5),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32" if prec == 1 else "f64",
+        "data": "synthetic",
+        "config": {"workload": f"{args.workload}: single {P['L']}^3 periodic box, chain N={P['N']}, "
+                               f"kT={P['kT']}, {'FP32 deviation' if prec == 1 else 'FP64'} populations, "
+                               f"{P['md_substeps']} MD substeps per LB step",
+                   "nodes": nodes, "beads": int(P["N"]), "precision": "fp32_dev" if prec == 1 else "fp64"},
+        "pct_hbm_peak_step": round(100.0 * BYTES_PER_NODE[prec] * nodes * args.steps / t_ev / 1e9 / HBM_PEAK_GBS, 2),
+        "roofline": {"bound": "hbm", "kernel": "k_collide (fused collide+stream)",
+                     "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+                     "bytes_per_launch": BYTES_PER_NODE[prec] * nodes,
+                     "avg_launch_us": round(t_k * 1e6, 2)},
+        "invariants": {"mass_rel_drift": abs(obs1["mass"] - obs0["mass"]) / obs0["mass"],
+                       "p_total_drift": float(np.max(np.abs(obs1["p_total"] - obs0["p_total"]))),
+                       "health": obs1["health"]},
+    }
+    s.close()
+    del s
+    torch.cuda.empty_cache()
+
+    if not args.no_secondary:
+        sec = {}
+        s64, b64, n64, p64 = make_system("single64")
+        t64, _ = time_steps(s64, 2000, 50)
+        sec["single64"] = {"mlups": round(n64 * 2000 / t64 / 1e6, 1), "ms_per_step": round(1e3 * t64 / 2000, 4),
+                           "collide_us": round(1e6 * time_collide(s64, 200), 2)}
+        s64.close()
+        sb, bb, nb, pb = make_system("batched256")
+        tb, _ = time_steps(sb, 500, 20)
+        sb.set_launch(batched=False)
+        tp, _ = time_steps(sb, 100, 5)
+        sec["batched256"] = {"boxes": len(bb), "nodes": nb, "beads": int(sum(b["N"] for b in bb)),
+                             "batched_mlups": round(nb * 500 / tb / 1e6, 1),
+                             "plain_per_box_mlups": round(nb * 100 / tp / 1e6, 1),
+                             "batched_over_plain": round((nb * 500 / tb) / (nb * 100 / tp), 3)}
+        sb.close()
+        result["secondary"] = sec
+        log("secondary", json.dumps(sec))
+    if not args.no_cpu:
+        log("cpu baseline (oracle) ...")
+        result["cpu_baseline"] = cpu_baseline(args.workload)
+    print(json.dumps(result), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,180 @@
+/*
+ * lbmd.h -- C ABI of the MI355X (gfx950) library for the fluctuating D3Q19
+ * lattice-Boltzmann solvent with a dissipatively coupled bead-spring chain
+ * (Pham, Schiller, Prakash, Duenweg, arXiv:0903.5067).
+ *
+ * The problem these calls set up follows the paper's statement of it: one
+ * chain of N beads joined by FENE springs, with the purely repulsive
+ * Lennard-Jones potential between all beads (Sec. II.A, potentials), immersed
+ * in a periodic cubic box of L^3 lattice sites of LB fluid (Sec. II.B LB
+ * equation; Sec. II.E cubic box with periodic boundaries) with density rho0,
+ * relaxation rates and temperature kT, coupled by friction zeta_bare and a
+ * Langevin force whose momentum is taken from the fluid (Sec. II.B, coupling
+ * paragraph), advanced in MD steps md_dt and LB steps tau_lb
+ * (Sec. II.E, time steps), and observed through mass, momentum and the chain's
+ * R_g^2 and R_e^2 (Sec. III.A).  Several independent boxes (the finite-size
+ * study of Sec. II.E / Sec. III.C) can be advanced together.
+ *
+ * Units: the chain in Lennard-Jones units (sigma = m = eps = 1); lattice
+ * spacing 1 sigma; the LB step tau_lb in LJ time; rho0 in m / sigma^3; kT in
+ * eps.  Relaxation rates omega are per LB step, omega = 1 - gamma.
+ *
+ * Conventions
+ *  - Every call returns lb_status; nothing aborts or throws across the ABI.
+ *    lb_last_error() gives a message for the last failing call on a handle
+ *    (or, with NULL, the last failure of lb_query_sizes / lb_init in the
+ *    calling thread).
+ *  - Ownership: d_state and d_scratch are device memory owned by the caller
+ *    (for example torch tensors), sized by lb_query_sizes, aligned to 256
+ *    bytes, and must outlive the handle.  The handle owns only host metadata,
+ *    captured graphs and, if the caller passes stream == NULL, a stream it
+ *    creates.  lb_free never frees caller memory.
+ *  - Streams: all device work is enqueued on the stream given to lb_init
+ *    (a hipStream_t passed as void*).  lb_couple and lb_step return without
+ *    synchronising; numeric failures are recorded in a device health word and
+ *    reported by the next lb_observables / lb_export_state as LB_ENUMERIC.
+ *  - Host buffers (bead_x0, export/import buffers, lb_obs arrays) are plain
+ *    host memory owned by the caller.
+ */
+#ifndef LBMD_H
+#define LBMD_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct lb_handle lb_handle;
+
+typedef enum {
+    LB_OK = 0,
+    LB_EINVAL = -1,    /* invalid argument or parameter set */
+    LB_ENOMEM = -2,    /* caller buffer too small */
+    LB_EDEVICE = -3,   /* a HIP runtime call failed */
+    LB_ENUMERIC = -4,  /* device health word set (see LB_HEALTH_*) */
+    LB_ESTATE = -5     /* call not valid in the handle's current state */
+} lb_status;
+
+typedef enum { LB_FP64 = 0, LB_FP32_DEV = 1 } lb_precision;
+/* thermalization of the non-conserved modes (Sec. II.B): none, the six
+ * stress modes only (the original scheme), or all fifteen */
+typedef enum { LB_THERM_OFF = 0, LB_THERM_STRESS = 1, LB_THERM_ALL = 2 } lb_thermalize;
+
+/* health bits reported in lb_obs.health */
+#define LB_HEALTH_DENSITY 0x1u  /* rho <= 0 or NaN at some node */
+#define LB_HEALTH_MACH 0x2u     /* |u| > 0.3 lattice units (or NaN) at some node */
+#define LB_HEALTH_FENE 0x4u     /* a bond reached R0 */
+#define LB_HEALTH_TABLE 0x8u    /* node-impulse table overflow */
+#define LB_HEALTH_FIXED 0x10u   /* node impulse outside the fixed-point range */
+
+/* One box.  An array of these is a batch of independent boxes. */
+typedef struct {
+    int32_t L;            /* sites per edge, 2 <= L <= 1625; cubic, periodic, spacing 1 */
+    int32_t n_beads;      /* N, 0 <= N <= min(1024, L^3); 0 = pure fluid */
+    double rho0;          /* fluid density, > 0 */
+    double omega_shear;   /* shear-mode relaxation rate, in (0, 2) */
+    double omega_bulk;    /* bulk-mode relaxation rate, in (0, 2) */
+    double omega_ghost;   /* rate of the nine ghost modes, in (0, 2) */
+    double kT;            /* temperature (eps), >= 0 */
+    int32_t thermalize;   /* lb_thermalize */
+    double tau_lb;        /* LB step in LJ time; must equal md_substeps * md_dt */
+    double md_dt;         /* MD step, > 0 */
+    int32_t md_substeps;  /* MD steps per LB step, >= 1 */
+    double bead_mass;     /* > 0 */
+    double zeta;          /* bare friction coefficient, >= 0 */
+    double k_fene;        /* FENE spring constant, >= 0 */
+    double r0_fene;       /* FENE maximum extension, > 0 */
+    double eps_wca;       /* LJ energy, >= 0 */
+    double sigma_wca;     /* LJ length, > 0; cut and shifted at 2^(1/6) sigma */
+    uint32_t seed;        /* Philox key word 0 */
+    uint32_t box_id;      /* Philox key word 1 */
+} lb_box_desc;
+
+/* Observables of one box, FP64 sums in a fixed order. */
+typedef struct {
+    double mass;          /* sum over nodes of rho (lattice mass units = m) */
+    double j_lat[3];      /* fluid momentum, lattice units */
+    double p_fluid[3];    /* fluid momentum, LJ units (j_lat / tau_lb) */
+    double p_beads[3];    /* sum of m v over beads */
+    double p_total[3];    /* p_fluid + p_beads + (md_dt/2) sum of the beads'
+                             last coupling forces: conserved at LB-step boundaries */
+    double com[3];        /* chain centre of mass (unwrapped coordinates) */
+    double rg2;           /* radius of gyration squared */
+    double re2;           /* end-to-end distance squared */
+    double neg_count;     /* number of populations n_i < 0 */
+    double mode_sq[19];   /* sum over nodes of (m_k - rho0 delta_k0)^2 */
+    uint32_t health;      /* LB_HEALTH_* bits accumulated since init (sticky) */
+    uint32_t pad;
+    uint64_t step;        /* LB steps taken since init */
+} lb_obs;
+
+/* Device bytes the caller must provide.  hist_steps >= 0: depth of the ring
+ * of bead velocities kept at the end of each LB step (0 = none).  Fails with
+ * LB_EINVAL on an invalid box description. */
+lb_status lb_query_sizes(const lb_box_desc* boxes, int32_t n_boxes, int32_t precision,
+                         int32_t hist_steps, size_t* state_bytes, size_t* scratch_bytes);
+
+/* Set up the boxes: fluid at rest at n_i = w_i rho0 (deviations zero), beads
+ * at bead_x0 (host, [sum N][3] FP64, boxes in order, unwrapped coordinates),
+ * velocities zero, last force = conservative force.  bead_x0 may be NULL only
+ * when every box has N = 0.  LB_EINVAL if any initial bond is >= R0.
+ * stream: hipStream_t as void*, NULL = the library creates one. */
+lb_status lb_init(const lb_box_desc* boxes, int32_t n_boxes, int32_t precision, int32_t hist_steps,
+                  const double* bead_x0, void* d_state, void* d_scratch, void* stream,
+                  lb_handle** out);
+
+/* Run the md_substeps MD steps of the current LB step in the fluid frozen at
+ * the current (pre-collision) state and accumulate the node impulses; the
+ * fluid is not updated.  The next lb_step consumes these impulses instead of
+ * coupling again.  LB_ESTATE if called twice without an lb_step between. */
+lb_status lb_couple(lb_handle* h);
+
+/* n_steps full LB steps: [couple ; collide with the impulses ; stream] each.
+ * Asynchronous on the handle's stream. */
+lb_status lb_step(lb_handle* h, int64_t n_steps);
+
+/* Compute observables of every box into out[n_boxes] (host); synchronises the
+ * stream.  Returns LB_ENUMERIC (and still fills out) if a health bit is set. */
+lb_status lb_observables(lb_handle* h, lb_obs* out);
+
+/* Canonical state as FP64 host data, per box in order: 19 planes of L^3 full
+ * populations n_i (plane-major, node r = x + L (y + L z)), then N x 3 each of
+ * bead x, v, last total force, last coupling force; preceded by one uint64 step
+ * count.  lb_state_host_bytes gives the size.  Synchronises the stream. */
+size_t lb_state_host_bytes(const lb_handle* h);
+lb_status lb_export_state(lb_handle* h, void* host_buf, size_t bytes);
+lb_status lb_import_state(lb_handle* h, const void* host_buf, size_t bytes);
+
+/* Node impulses pending after lb_couple, scattered into dense host arrays
+ * [3][L^3] (lattice units) per box in order; zero where no bead acted. */
+lb_status lb_pending_impulse(lb_handle* h, double* host_dense, size_t bytes);
+
+/* Bead velocities stored at the end of LB step `step` (0-based), [sum N][3]
+ * FP64 host.  LB_EINVAL if that step is no longer in the ring. */
+lb_status lb_velocity_history(lb_handle* h, int64_t step, double* host_out, size_t bytes);
+
+/* Launch structure: batched = 1 advances every box with one launch per kernel
+ * (the default); batched = 0 launches per box (the plain form).
+ * graph_steps > 0 records that many LB steps (rounded up to even) in a HIP
+ * graph and replays it; 0 launches kernels directly. */
+lb_status lb_set_launch(lb_handle* h, int32_t batched, int32_t graph_steps);
+
+/* Benchmark aid: enqueue n launches of the fused collide+stream kernel of
+ * every box from the current state into the other buffer, with no impulses
+ * and without advancing the state (the other buffer is overwritten by the
+ * next step anyway).  Lets a caller time the dominant kernel with events on
+ * the handle's stream. */
+lb_status lb_collide_only(lb_handle* h, int32_t n);
+
+/* The stream the handle enqueues on (hipStream_t as void*). */
+void* lb_stream(const lb_handle* h);
+
+void lb_free(lb_handle* h);
+const char* lb_last_error(const lb_handle* h);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* LBMD_H */

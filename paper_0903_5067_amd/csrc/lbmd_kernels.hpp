@@ -1,0 +1,45 @@
+// Launch interface between the host runtime and the HIP kernels.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "lbmd_device.hpp"
+
+namespace lbd {
+
+// Device pointers and sizes every launcher needs; filled by the runtime.
+struct LaunchCtx {
+    hipStream_t stream;
+    const BoxDev* boxes;
+    int n_boxes;
+    const void* ccs;               // CollideConst<R>[n_boxes]
+    const uint32_t* tile_box;      // box index of every collide tile
+    Ctrl* ctrl;
+    uint32_t* keys;                // impulse table keys (1 + local node, 0 = empty)
+    unsigned long long* vals;      // impulse table values, 3 per slot, fixed point 2^-48
+    const uint32_t* tab_off;       // first slot of each box's table
+    const uint32_t* tab_cap;       // slots of each box's table (power of two)
+    double *x, *v, *f, *fc;        // beads [total][3]
+    int32_t* nl_cnt; int32_t* nl_idx; double* nl_x0; int nl_cap;
+    double* vhist; int hist_len; uint64_t total_beads;
+};
+
+template <typename R>
+hipError_t launch_collide(const LaunchCtx& c, const void* A, void* B, int fixed_box, uint32_t tile0,
+                          uint32_t n_tiles, uint32_t s_off);
+template <typename R>
+hipError_t launch_fixup(const LaunchCtx& c, const void* A, void* B, int fixed_box, uint32_t slot0,
+                        uint32_t n_slots, uint32_t s_off);
+template <typename R>
+hipError_t launch_couple(const LaunchCtx& c, const void* A, const int32_t* list, int n_list, int block,
+                         uint32_t s_off);
+hipError_t launch_advance(const LaunchCtx& c, uint32_t n);
+hipError_t launch_init_forces(const LaunchCtx& c, const int32_t* list, int n_list, int block);
+template <typename R>
+hipError_t launch_stats(const LaunchCtx& c, const void* A, uint32_t total_tiles, double* part, double* out);
+hipError_t launch_chain_obs(const LaunchCtx& c, double* out);
+
+constexpr int NSTAT_REC = 24;
+constexpr int NCHAIN_REC = 11;
+
+}  // namespace lbd

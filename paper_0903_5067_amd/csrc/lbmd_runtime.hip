@@ -1,0 +1,665 @@
+// Host runtime and C ABI of the fluctuating D3Q19 LB library (include/lbmd.h).
+//
+// Lays out the caller-owned device buffers, validates the box descriptions,
+// prepares the per-box constants the kernels read, orders the launches of one
+// LB step (couple -> collide -> fixup, Sec. II.B: the coupling hands the
+// beads' momentum to the fluid, then the LB equation collides and streams),
+// records them into HIP graphs on request, and moves observables and state
+// across the host boundary.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdlib>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "../../include/lbmd.h"
+#include "lbmd_kernels.hpp"
+
+using namespace lbd;
+
+namespace {
+
+thread_local std::string g_err;
+
+size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
+uint64_t round_up(uint64_t x, uint64_t m) { return (x + m - 1) / m * m; }
+uint32_t next_pow2(uint32_t x)
+{
+    uint32_t p = 1;
+    while (p < x) p <<= 1;
+    return p;
+}
+
+constexpr int NL_CAP = 48;      // neighbour-list entries per bead
+constexpr double MODE_B[19] = {1, 1. / 3, 1. / 3, 1. / 3, 2. / 3, 4. / 3, 4. / 9, 1. / 9, 1. / 9, 1. / 9,
+                               2. / 3, 2. / 3, 2. / 3, 2. / 9, 2. / 9, 2. / 9, 2, 4. / 3, 4. / 9};
+
+struct Layout {
+    size_t esz = 8;
+    std::vector<uint64_t> pop_off, ps, bead_off, V;
+    std::vector<uint32_t> tile_begin, n_tiles, tab_off, tab_cap;
+    uint64_t pop_elems = 0, total_tiles = 0, total_beads = 0, total_slots = 0;
+    size_t st_popA = 0, st_popB = 0, st_x = 0, st_v = 0, st_f = 0, st_fc = 0, state_bytes = 0;
+    size_t sc_ctrl = 0, sc_boxes = 0, sc_ccs = 0, sc_tilebox = 0, sc_couple = 0, sc_taboff = 0,
+           sc_tabcap = 0, sc_keys = 0, sc_vals = 0, sc_nlcnt = 0, sc_nlidx = 0, sc_nlx0 = 0,
+           sc_part = 0, sc_stat = 0, sc_chain = 0, sc_vhist = 0, scratch_bytes = 0;
+    int max_N = 0;
+};
+
+bool validate(const lb_box_desc* b, int32_t n, int32_t prec, int32_t hist, std::string& err)
+{
+    if (!b || n <= 0) { err = "need at least one box"; return false; }
+    if (prec != LB_FP64 && prec != LB_FP32_DEV) { err = "precision must be LB_FP64 or LB_FP32_DEV"; return false; }
+    if (hist < 0) { err = "hist_steps must be >= 0"; return false; }
+    for (int i = 0; i < n; ++i) {
+        const lb_box_desc& d = b[i];
+        auto bad = [&](const char* what) { err = "box " + std::to_string(i) + ": " + what; return false; };
+        if (d.L < 2 || d.L > 1625) return bad("L must be in [2, 1625]");
+        const uint64_t V = (uint64_t)d.L * d.L * d.L;
+        if (d.n_beads < 0 || d.n_beads > 1024 || (uint64_t)d.n_beads > V) return bad("N must be in [0, min(1024, L^3)]");
+        if (!(d.rho0 > 0)) return bad("rho0 must be > 0");
+        for (double w : {d.omega_shear, d.omega_bulk, d.omega_ghost})
+            if (!(w > 0 && w < 2)) return bad("relaxation rates must be in (0, 2)");
+        if (!(d.kT >= 0)) return bad("kT must be >= 0");
+        if (d.thermalize < 0 || d.thermalize > 2) return bad("thermalize must be 0, 1 or 2");
+        if (!(d.md_dt > 0) || d.md_substeps < 1) return bad("md_dt > 0 and md_substeps >= 1 required");
+        if (!(std::fabs(d.md_substeps * d.md_dt - d.tau_lb) <= 1e-12 * d.tau_lb) || !(d.tau_lb > 0))
+            return bad("tau_lb must equal md_substeps * md_dt");
+        if (!(d.bead_mass > 0) || !(d.zeta >= 0) || !(d.k_fene >= 0) || !(d.r0_fene > 0) ||
+            !(d.eps_wca >= 0) || !(d.sigma_wca > 0))
+            return bad("chain parameters out of range");
+    }
+    return true;
+}
+
+Layout make_layout(const lb_box_desc* b, int32_t n, int32_t prec, int32_t hist)
+{
+    Layout Lo;
+    Lo.esz = prec == LB_FP64 ? 8 : 4;
+    const uint64_t align_el = 256 / Lo.esz;
+    uint64_t pad = align_el;
+    if (const char* e = std::getenv("LBMD_PLANE_PAD")) pad = round_up(std::strtoull(e, nullptr, 10), align_el);
+    uint64_t pop = 0, tiles = 0, beads = 0;
+    uint32_t slots = 0;
+    for (int i = 0; i < n; ++i) {
+        const uint64_t V = (uint64_t)b[i].L * b[i].L * b[i].L;
+        const uint64_t ps = round_up(V, align_el) + pad;
+        Lo.V.push_back(V);
+        Lo.ps.push_back(ps);
+        Lo.pop_off.push_back(pop);
+        pop += 19 * ps;
+        Lo.tile_begin.push_back((uint32_t)tiles);
+        Lo.n_tiles.push_back((uint32_t)((V + 255) / 256));
+        tiles += (V + 255) / 256;
+        Lo.bead_off.push_back(beads);
+        beads += b[i].n_beads;
+        const uint32_t cap = b[i].n_beads > 0 ? next_pow2(std::max<uint32_t>(64u, 32u * (uint32_t)b[i].n_beads)) : 0u;
+        Lo.tab_off.push_back(slots);
+        Lo.tab_cap.push_back(cap);
+        slots += cap;
+        Lo.max_N = std::max(Lo.max_N, b[i].n_beads);
+    }
+    Lo.pop_elems = pop;
+    Lo.total_tiles = tiles;
+    Lo.total_beads = beads;
+    Lo.total_slots = slots;
+    size_t o = 0;
+    Lo.st_popA = o; o = align256(o + pop * Lo.esz);
+    Lo.st_popB = o; o = align256(o + pop * Lo.esz);
+    const size_t bb = std::max<uint64_t>(beads, 1) * 3 * sizeof(double);
+    Lo.st_x = o; o = align256(o + bb);
+    Lo.st_v = o; o = align256(o + bb);
+    Lo.st_f = o; o = align256(o + bb);
+    Lo.st_fc = o; o = align256(o + bb);
+    Lo.state_bytes = o;
+    o = 0;
+    const size_t ccsz = prec == LB_FP64 ? sizeof(CollideConst<double>) : sizeof(CollideConst<float>);
+    Lo.sc_ctrl = o; o = align256(o + sizeof(Ctrl));
+    Lo.sc_boxes = o; o = align256(o + n * sizeof(BoxDev));
+    Lo.sc_ccs = o; o = align256(o + n * ccsz);
+    Lo.sc_tilebox = o; o = align256(o + tiles * sizeof(uint32_t));
+    Lo.sc_couple = o; o = align256(o + n * sizeof(int32_t));
+    Lo.sc_taboff = o; o = align256(o + n * sizeof(uint32_t));
+    Lo.sc_tabcap = o; o = align256(o + n * sizeof(uint32_t));
+    Lo.sc_keys = o; o = align256(o + std::max<uint64_t>(slots, 1) * sizeof(uint32_t));
+    Lo.sc_vals = o; o = align256(o + std::max<uint64_t>(slots, 1) * 3 * sizeof(unsigned long long));
+    Lo.sc_nlcnt = o; o = align256(o + std::max<uint64_t>(beads, 1) * sizeof(int32_t));
+    Lo.sc_nlidx = o; o = align256(o + std::max<uint64_t>(beads, 1) * NL_CAP * sizeof(int32_t));
+    Lo.sc_nlx0 = o; o = align256(o + std::max<uint64_t>(beads, 1) * 3 * sizeof(double));
+    Lo.sc_part = o; o = align256(o + tiles * NSTAT_REC * sizeof(double));
+    Lo.sc_stat = o; o = align256(o + n * NSTAT_REC * sizeof(double));
+    Lo.sc_chain = o; o = align256(o + n * NCHAIN_REC * sizeof(double));
+    Lo.sc_vhist = o; o = align256(o + (size_t)hist * std::max<uint64_t>(beads, 1) * 3 * sizeof(double));
+    Lo.scratch_bytes = o;
+    return Lo;
+}
+
+template <typename R>
+CollideConst<R> collide_const(const lb_box_desc& d)
+{
+    CollideConst<R> c;
+    const double gb = 1 - d.omega_bulk, gs = 1 - d.omega_shear, gg = 1 - d.omega_ghost;
+    c.rho0 = (R)d.rho0;
+    c.gb = (R)gb; c.gs = (R)gs; c.gg = (R)gg;
+    c.hb = (R)(0.5 * (1 + gb)); c.hs = (R)(0.5 * (1 + gs));
+    // mu = kT_lat / c_s^2, kT_lat = kT tau_lb^2 (lattice spacing and mass unit 1)
+    c.mu = (R)(3.0 * d.kT * d.tau_lb * d.tau_lb);
+    c.therm = d.thermalize;
+    for (int k = 0; k < 19; ++k) {
+        const double g = k == 4 ? gb : (k < 10 ? gs : gg);
+        c.q[k] = k < 4 ? (R)0 : (R)std::sqrt((1 - g * g) / MODE_B[k]);
+    }
+    return c;
+}
+
+}  // namespace
+
+struct lb_handle {
+    int n_boxes = 0;
+    int prec = LB_FP32_DEV;
+    int hist = 0;
+    std::vector<lb_box_desc> desc;
+    Layout lo;
+    char* state = nullptr;
+    char* scratch = nullptr;
+    hipStream_t stream = nullptr;
+    bool own_stream = false;
+    LaunchCtx ctx{};
+    int32_t* couple_list = nullptr;   // device
+    std::vector<int32_t> couple_host; // box indices with beads
+    int couple_block = 64;
+    int cur = 0;                      // 0: buffer A holds the current state
+    uint64_t step = 0;                // host mirror of the device step counter
+    bool pending = false;             // lb_couple done, impulses not yet consumed
+    int batched = 1;
+    int graph_steps = 0;
+    hipGraphExec_t gexec[2] = {nullptr, nullptr};
+    hipGraph_t graph[2] = {nullptr, nullptr};
+    std::string err;
+
+    void* pop(int which) { return state + (which == 0 ? lo.st_popA : lo.st_popB); }
+};
+
+namespace {
+
+lb_status fail(lb_handle* h, lb_status s, const std::string& msg)
+{
+    if (h) h->err = msg; else g_err = msg;
+    return s;
+}
+
+#define HIPCHK(h, call)                                                                         \
+    do {                                                                                        \
+        hipError_t e_ = (call);                                                                 \
+        if (e_ != hipSuccess)                                                                   \
+            return fail(h, LB_EDEVICE, std::string(#call) + ": " + hipGetErrorString(e_));     \
+    } while (0)
+
+// one LB step's launches with relative step offset s_off, from buffer `from`
+lb_status enqueue_step(lb_handle* h, int from, uint32_t s_off, bool couple)
+{
+    const void* A = h->pop(from);
+    void* B = h->pop(1 - from);
+    const bool f64 = h->prec == LB_FP64;
+    const LaunchCtx& c = h->ctx;
+    const int nc = (int)h->couple_host.size();
+    if (h->batched) {
+        if (couple && nc)
+            HIPCHK(h, f64 ? launch_couple<double>(c, A, h->couple_list, nc, h->couple_block, s_off)
+                          : launch_couple<float>(c, A, h->couple_list, nc, h->couple_block, s_off));
+        HIPCHK(h, f64 ? launch_collide<double>(c, A, B, -1, 0, (uint32_t)h->lo.total_tiles, s_off)
+                      : launch_collide<float>(c, A, B, -1, 0, (uint32_t)h->lo.total_tiles, s_off));
+        if (h->lo.total_slots)
+            HIPCHK(h, f64 ? launch_fixup<double>(c, A, B, -1, 0, (uint32_t)h->lo.total_slots, s_off)
+                          : launch_fixup<float>(c, A, B, -1, 0, (uint32_t)h->lo.total_slots, s_off));
+    } else {
+        for (int i = 0; i < nc; ++i) {
+            if (!couple) break;
+            HIPCHK(h, f64 ? launch_couple<double>(c, A, h->couple_list + i, 1, h->couple_block, s_off)
+                          : launch_couple<float>(c, A, h->couple_list + i, 1, h->couple_block, s_off));
+        }
+        for (int b = 0; b < h->n_boxes; ++b) {
+            HIPCHK(h, f64 ? launch_collide<double>(c, A, B, b, h->lo.tile_begin[b], h->lo.n_tiles[b], s_off)
+                          : launch_collide<float>(c, A, B, b, h->lo.tile_begin[b], h->lo.n_tiles[b], s_off));
+            if (h->lo.tab_cap[b])
+                HIPCHK(h, f64 ? launch_fixup<double>(c, A, B, b, h->lo.tab_off[b], h->lo.tab_cap[b], s_off)
+                              : launch_fixup<float>(c, A, B, b, h->lo.tab_off[b], h->lo.tab_cap[b], s_off));
+        }
+    }
+    return LB_OK;
+}
+
+void drop_graphs(lb_handle* h)
+{
+    for (int p = 0; p < 2; ++p) {
+        if (h->gexec[p]) (void)hipGraphExecDestroy(h->gexec[p]);
+        if (h->graph[p]) (void)hipGraphDestroy(h->graph[p]);
+        h->gexec[p] = nullptr;
+        h->graph[p] = nullptr;
+    }
+}
+
+lb_status build_graph(lb_handle* h, int parity)
+{
+    HIPCHK(h, hipStreamBeginCapture(h->stream, hipStreamCaptureModeThreadLocal));
+    lb_status st = LB_OK;
+    for (int k = 0; k < h->graph_steps && st == LB_OK; ++k) st = enqueue_step(h, parity ^ (k & 1), (uint32_t)k, true);
+    if (st == LB_OK && launch_advance(h->ctx, (uint32_t)h->graph_steps) != hipSuccess) st = LB_EDEVICE;
+    hipGraph_t g = nullptr;
+    hipError_t e = hipStreamEndCapture(h->stream, &g);
+    if (st != LB_OK) { if (g) (void)hipGraphDestroy(g); return st; }
+    if (e != hipSuccess) return fail(h, LB_EDEVICE, std::string("graph capture: ") + hipGetErrorString(e));
+    h->graph[parity] = g;
+    HIPCHK(h, hipGraphInstantiate(&h->gexec[parity], g, nullptr, nullptr, 0));
+    return LB_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+lb_status lb_query_sizes(const lb_box_desc* boxes, int32_t n_boxes, int32_t precision, int32_t hist_steps,
+                         size_t* state_bytes, size_t* scratch_bytes)
+{
+    std::string err;
+    if (!validate(boxes, n_boxes, precision, hist_steps, err)) return fail(nullptr, LB_EINVAL, err);
+    if (!state_bytes || !scratch_bytes) return fail(nullptr, LB_EINVAL, "null size pointer");
+    Layout lo = make_layout(boxes, n_boxes, precision, hist_steps);
+    *state_bytes = lo.state_bytes;
+    *scratch_bytes = lo.scratch_bytes;
+    return LB_OK;
+}
+
+lb_status lb_init(const lb_box_desc* boxes, int32_t n_boxes, int32_t precision, int32_t hist_steps,
+                  const double* bead_x0, void* d_state, void* d_scratch, void* stream, lb_handle** out)
+{
+    std::string err;
+    if (!out) return fail(nullptr, LB_EINVAL, "null handle pointer");
+    *out = nullptr;
+    if (!validate(boxes, n_boxes, precision, hist_steps, err)) return fail(nullptr, LB_EINVAL, err);
+    if (!d_state || !d_scratch) return fail(nullptr, LB_EINVAL, "null device buffer");
+    if (((uintptr_t)d_state & 255) || ((uintptr_t)d_scratch & 255))
+        return fail(nullptr, LB_EINVAL, "device buffers must be 256-byte aligned");
+    Layout lo = make_layout(boxes, n_boxes, precision, hist_steps);
+    uint64_t nb = lo.total_beads;
+    if (nb > 0 && !bead_x0) return fail(nullptr, LB_EINVAL, "bead_x0 is NULL but boxes have beads");
+    // initial bonds must be shorter than R0
+    for (int i = 0; i < n_boxes; ++i)
+        for (int bd = 0; bd + 1 < boxes[i].n_beads; ++bd) {
+            const double* p = bead_x0 + 3 * (lo.bead_off[i] + bd);
+            double r2 = 0;
+            for (int c = 0; c < 3; ++c) r2 += (p[3 + c] - p[c]) * (p[3 + c] - p[c]);
+            if (!(r2 < boxes[i].r0_fene * boxes[i].r0_fene))
+                return fail(nullptr, LB_EINVAL, "box " + std::to_string(i) + ": initial bond >= R0");
+        }
+
+    lb_handle* h = new lb_handle();
+    h->n_boxes = n_boxes;
+    h->prec = precision;
+    h->hist = hist_steps;
+    h->desc.assign(boxes, boxes + n_boxes);
+    h->lo = lo;
+    h->state = (char*)d_state;
+    h->scratch = (char*)d_scratch;
+    if (stream) {
+        h->stream = (hipStream_t)stream;
+    } else {
+        hipError_t e = hipStreamCreateWithFlags(&h->stream, hipStreamNonBlocking);
+        if (e != hipSuccess) { delete h; return fail(nullptr, LB_EDEVICE, std::string("stream: ") + hipGetErrorString(e)); }
+        h->own_stream = true;
+    }
+    auto sc = [&](size_t off) { return h->scratch + off; };
+    auto stp = [&](size_t off) { return h->state + off; };
+
+    std::vector<BoxDev> bd(n_boxes);
+    for (int i = 0; i < n_boxes; ++i) {
+        const lb_box_desc& d = boxes[i];
+        BoxDev& b = bd[i];
+        std::memset(&b, 0, sizeof b);
+        b.L = d.L; b.N = d.n_beads; b.seed = d.seed; b.box_id = d.box_id;
+        b.node_off = 0; b.pop_off = lo.pop_off[i]; b.ps = lo.ps[i]; b.bead_off = lo.bead_off[i];
+        b.tile_begin = lo.tile_begin[i]; b.n_tiles = lo.n_tiles[i];
+        b.therm = d.thermalize; b.substeps = d.md_substeps;
+        b.rho0 = d.rho0; b.gam_b = 1 - d.omega_bulk; b.gam_s = 1 - d.omega_shear; b.gam_g = 1 - d.omega_ghost;
+        b.mu = 3.0 * d.kT * d.tau_lb * d.tau_lb;
+        b.tau_lb = d.tau_lb; b.dt = d.md_dt; b.mass = d.bead_mass; b.zeta = d.zeta; b.k_fene = d.k_fene;
+        b.r0sq = d.r0_fene * d.r0_fene; b.eps = d.eps_wca; b.sigsq = d.sigma_wca * d.sigma_wca;
+        b.rc2 = std::pow(2.0, 1.0 / 3.0) * b.sigsq;
+        b.bead_noise = std::sqrt(2.0 * d.kT * d.zeta / d.md_dt);
+        b.inv_L = 1.0 / d.L;
+    }
+    std::vector<uint32_t> tile_box(lo.total_tiles);
+    for (int i = 0; i < n_boxes; ++i)
+        for (uint32_t t = 0; t < lo.n_tiles[i]; ++t) tile_box[lo.tile_begin[i] + t] = (uint32_t)i;
+    for (int i = 0; i < n_boxes; ++i)
+        if (boxes[i].n_beads > 0) h->couple_host.push_back(i);
+    h->couple_block = std::max(64, (lo.max_N + 63) / 64 * 64);
+    std::vector<int32_t> nlcnt(std::max<uint64_t>(nb, 1), -2);
+
+    auto up = [&](size_t off, const void* src, size_t bytes) {
+        return bytes ? hipMemcpy(h->scratch + off, src, bytes, hipMemcpyHostToDevice) : hipSuccess;
+    };
+    hipError_t e = hipSuccess;
+    auto chk = [&](hipError_t x) { if (e == hipSuccess) e = x; };
+    chk(hipMemsetAsync(h->scratch, 0, lo.scratch_bytes, h->stream));
+    chk(hipMemsetAsync(h->state, 0, lo.state_bytes, h->stream));
+    chk(hipStreamSynchronize(h->stream));
+    chk(up(lo.sc_boxes, bd.data(), n_boxes * sizeof(BoxDev)));
+    if (precision == LB_FP64) {
+        std::vector<CollideConst<double>> cc(n_boxes);
+        for (int i = 0; i < n_boxes; ++i) cc[i] = collide_const<double>(boxes[i]);
+        chk(up(lo.sc_ccs, cc.data(), n_boxes * sizeof(cc[0])));
+    } else {
+        std::vector<CollideConst<float>> cc(n_boxes);
+        for (int i = 0; i < n_boxes; ++i) cc[i] = collide_const<float>(boxes[i]);
+        chk(up(lo.sc_ccs, cc.data(), n_boxes * sizeof(cc[0])));
+    }
+    chk(up(lo.sc_tilebox, tile_box.data(), tile_box.size() * sizeof(uint32_t)));
+    chk(up(lo.sc_couple, h->couple_host.data(), h->couple_host.size() * sizeof(int32_t)));
+    chk(up(lo.sc_taboff, lo.tab_off.data(), n_boxes * sizeof(uint32_t)));
+    chk(up(lo.sc_tabcap, lo.tab_cap.data(), n_boxes * sizeof(uint32_t)));
+    chk(up(lo.sc_nlcnt, nlcnt.data(), nlcnt.size() * sizeof(int32_t)));
+    if (nb) chk(hipMemcpy(stp(lo.st_x), bead_x0, nb * 3 * sizeof(double), hipMemcpyHostToDevice));
+    if (e != hipSuccess) {
+        std::string msg = std::string("init upload: ") + hipGetErrorString(e);
+        lb_free(h);
+        return fail(nullptr, LB_EDEVICE, msg);
+    }
+
+    LaunchCtx& c = h->ctx;
+    c.stream = h->stream;
+    c.boxes = (const BoxDev*)sc(lo.sc_boxes);
+    c.n_boxes = n_boxes;
+    c.ccs = sc(lo.sc_ccs);
+    c.tile_box = (const uint32_t*)sc(lo.sc_tilebox);
+    c.ctrl = (Ctrl*)sc(lo.sc_ctrl);
+    c.keys = (uint32_t*)sc(lo.sc_keys);
+    c.vals = (unsigned long long*)sc(lo.sc_vals);
+    c.tab_off = (const uint32_t*)sc(lo.sc_taboff);
+    c.tab_cap = (const uint32_t*)sc(lo.sc_tabcap);
+    c.x = (double*)stp(lo.st_x); c.v = (double*)stp(lo.st_v); c.f = (double*)stp(lo.st_f); c.fc = (double*)stp(lo.st_fc);
+    c.nl_cnt = (int32_t*)sc(lo.sc_nlcnt); c.nl_idx = (int32_t*)sc(lo.sc_nlidx); c.nl_x0 = (double*)sc(lo.sc_nlx0);
+    c.nl_cap = NL_CAP;
+    c.vhist = hist_steps > 0 ? (double*)sc(lo.sc_vhist) : nullptr;
+    c.hist_len = hist_steps > 0 ? hist_steps : 1;
+    c.total_beads = nb;
+    h->couple_list = (int32_t*)sc(lo.sc_couple);
+
+    e = launch_init_forces(c, h->couple_list, (int)h->couple_host.size(), h->couple_block);
+    if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
+    if (e != hipSuccess) {
+        std::string msg = std::string("initial forces: ") + hipGetErrorString(e);
+        lb_free(h);
+        return fail(nullptr, LB_EDEVICE, msg);
+    }
+    *out = h;
+    return LB_OK;
+}
+
+lb_status lb_couple(lb_handle* h)
+{
+    if (!h) return fail(nullptr, LB_EINVAL, "null handle");
+    if (h->pending) return fail(h, LB_ESTATE, "lb_couple called twice without lb_step");
+    if (!h->couple_host.empty()) {
+        const void* A = h->pop(h->cur);
+        const LaunchCtx& c = h->ctx;
+        const int nc = (int)h->couple_host.size();
+        if (h->prec == LB_FP64)
+            HIPCHK(h, launch_couple<double>(c, A, h->couple_list, nc, h->couple_block, 0));
+        else
+            HIPCHK(h, launch_couple<float>(c, A, h->couple_list, nc, h->couple_block, 0));
+    }
+    h->pending = true;
+    return LB_OK;
+}
+
+lb_status lb_step(lb_handle* h, int64_t n_steps)
+{
+    if (!h) return fail(nullptr, LB_EINVAL, "null handle");
+    if (n_steps < 0) return fail(h, LB_EINVAL, "n_steps must be >= 0");
+    int64_t left = n_steps;
+    if (left > 0 && h->pending) {
+        lb_status s = enqueue_step(h, h->cur, 0, false);
+        if (s != LB_OK) return s;
+        HIPCHK(h, launch_advance(h->ctx, 1));
+        h->cur ^= 1;
+        h->step += 1;
+        h->pending = false;
+        left -= 1;
+    }
+    if (h->graph_steps > 0) {
+        while (left >= h->graph_steps) {
+            if (!h->gexec[h->cur]) {
+                lb_status s = build_graph(h, h->cur);
+                if (s != LB_OK) return s;
+            }
+            HIPCHK(h, hipGraphLaunch(h->gexec[h->cur], h->stream));
+            left -= h->graph_steps;
+            h->step += h->graph_steps;
+        }
+    }
+    if (left > 0) {
+        for (int64_t k = 0; k < left; ++k) {
+            lb_status s = enqueue_step(h, h->cur ^ (int)(k & 1), (uint32_t)k, true);
+            if (s != LB_OK) return s;
+        }
+        HIPCHK(h, launch_advance(h->ctx, (uint32_t)left));
+        if (left & 1) h->cur ^= 1;
+        h->step += left;
+    }
+    return LB_OK;
+}
+
+lb_status lb_observables(lb_handle* h, lb_obs* out)
+{
+    if (!h || !out) return fail(h, LB_EINVAL, "null argument");
+    const Layout& lo = h->lo;
+    double* part = (double*)(h->scratch + lo.sc_part);
+    double* stat = (double*)(h->scratch + lo.sc_stat);
+    double* chain = (double*)(h->scratch + lo.sc_chain);
+    const void* A = h->pop(h->cur);
+    if (h->prec == LB_FP64)
+        HIPCHK(h, launch_stats<double>(h->ctx, A, (uint32_t)lo.total_tiles, part, stat));
+    else
+        HIPCHK(h, launch_stats<float>(h->ctx, A, (uint32_t)lo.total_tiles, part, stat));
+    HIPCHK(h, launch_chain_obs(h->ctx, chain));
+    std::vector<double> st(h->n_boxes * NSTAT_REC), ch(h->n_boxes * NCHAIN_REC);
+    Ctrl ctrl;
+    HIPCHK(h, hipMemcpyAsync(st.data(), stat, st.size() * sizeof(double), hipMemcpyDeviceToHost, h->stream));
+    HIPCHK(h, hipMemcpyAsync(ch.data(), chain, ch.size() * sizeof(double), hipMemcpyDeviceToHost, h->stream));
+    HIPCHK(h, hipMemcpyAsync(&ctrl, h->scratch + lo.sc_ctrl, sizeof ctrl, hipMemcpyDeviceToHost, h->stream));
+    HIPCHK(h, hipStreamSynchronize(h->stream));
+    for (int i = 0; i < h->n_boxes; ++i) {
+        const lb_box_desc& d = h->desc[i];
+        const double* s = &st[i * NSTAT_REC];
+        const double* c = &ch[i * NCHAIN_REC];
+        lb_obs& o = out[i];
+        std::memset(&o, 0, sizeof o);
+        o.mass = (double)lo.V[i] * d.rho0 + s[0];
+        for (int a = 0; a < 3; ++a) {
+            o.j_lat[a] = s[1 + a];
+            o.p_fluid[a] = s[1 + a] / d.tau_lb;
+            o.p_beads[a] = c[3 + a];
+            o.p_total[a] = o.p_fluid[a] + o.p_beads[a] + 0.5 * d.md_dt * c[6 + a];
+            o.com[a] = d.n_beads > 0 ? c[a] / d.n_beads : 0.0;
+        }
+        o.rg2 = d.n_beads > 0 ? c[10] / d.n_beads : 0.0;
+        o.re2 = c[9];
+        o.neg_count = s[4];
+        for (int k = 0; k < 19; ++k) o.mode_sq[k] = s[5 + k];
+        o.health = ctrl.health;
+        o.step = ctrl.step;
+    }
+    if (ctrl.health) return fail(h, LB_ENUMERIC, "device health flags set: " + std::to_string(ctrl.health));
+    return LB_OK;
+}
+
+size_t lb_state_host_bytes(const lb_handle* h)
+{
+    if (!h) return 0;
+    size_t n = sizeof(uint64_t);
+    for (int i = 0; i < h->n_boxes; ++i) n += (19 * h->lo.V[i] + 12 * (uint64_t)h->desc[i].n_beads) * sizeof(double);
+    return n;
+}
+
+lb_status lb_export_state(lb_handle* h, void* host_buf, size_t bytes)
+{
+    if (!h || !host_buf) return fail(h, LB_EINVAL, "null argument");
+    if (bytes < lb_state_host_bytes(h)) return fail(h, LB_ENOMEM, "host buffer too small");
+    const Layout& lo = h->lo;
+    HIPCHK(h, hipStreamSynchronize(h->stream));
+    Ctrl ctrl;
+    HIPCHK(h, hipMemcpy(&ctrl, h->scratch + lo.sc_ctrl, sizeof ctrl, hipMemcpyDeviceToHost));
+    char* o = (char*)host_buf;
+    uint64_t stepv = ctrl.step;
+    std::memcpy(o, &stepv, sizeof stepv);
+    o += sizeof stepv;
+    const char* P = (const char*)h->pop(h->cur);
+    for (int i = 0; i < h->n_boxes; ++i) {
+        const uint64_t V = lo.V[i];
+        double* n = (double*)o;
+        std::vector<char> raw(V * lo.esz);
+        for (int q = 0; q < 19; ++q) {
+            HIPCHK(h, hipMemcpy(raw.data(), P + (lo.pop_off[i] + q * lo.ps[i]) * lo.esz, V * lo.esz, hipMemcpyDeviceToHost));
+            const double base = wv(q) * h->desc[i].rho0;
+            if (lo.esz == 8) { const double* r = (const double*)raw.data(); for (uint64_t k = 0; k < V; ++k) n[q * V + k] = base + r[k]; }
+            else { const float* r = (const float*)raw.data(); for (uint64_t k = 0; k < V; ++k) n[q * V + k] = base + (double)r[k]; }
+        }
+        o += 19 * V * sizeof(double);
+        const size_t nbb = (size_t)h->desc[i].n_beads * 3 * sizeof(double);
+        const size_t goff = lo.bead_off[i] * 3 * sizeof(double);
+        for (size_t arr : {lo.st_x, lo.st_v, lo.st_f, lo.st_fc}) {
+            if (nbb) HIPCHK(h, hipMemcpy(o, h->state + arr + goff, nbb, hipMemcpyDeviceToHost));
+            o += nbb;
+        }
+    }
+    if (ctrl.health) return fail(h, LB_ENUMERIC, "device health flags set: " + std::to_string(ctrl.health));
+    return LB_OK;
+}
+
+lb_status lb_import_state(lb_handle* h, const void* host_buf, size_t bytes)
+{
+    if (!h || !host_buf) return fail(h, LB_EINVAL, "null argument");
+    if (bytes < lb_state_host_bytes(h)) return fail(h, LB_ENOMEM, "host buffer too small");
+    if (h->pending) return fail(h, LB_ESTATE, "impulses pending from lb_couple");
+    const Layout& lo = h->lo;
+    HIPCHK(h, hipStreamSynchronize(h->stream));
+    const char* o = (const char*)host_buf;
+    uint64_t stepv;
+    std::memcpy(&stepv, o, sizeof stepv);
+    o += sizeof stepv;
+    char* P = (char*)h->pop(h->cur);
+    for (int i = 0; i < h->n_boxes; ++i) {
+        const uint64_t V = lo.V[i];
+        const double* n = (const double*)o;
+        std::vector<char> raw(V * lo.esz);
+        for (int q = 0; q < 19; ++q) {
+            const double base = wv(q) * h->desc[i].rho0;
+            if (lo.esz == 8) { double* r = (double*)raw.data(); for (uint64_t k = 0; k < V; ++k) r[k] = n[q * V + k] - base; }
+            else { float* r = (float*)raw.data(); for (uint64_t k = 0; k < V; ++k) r[k] = (float)(n[q * V + k] - base); }
+            HIPCHK(h, hipMemcpy(P + (lo.pop_off[i] + q * lo.ps[i]) * lo.esz, raw.data(), V * lo.esz, hipMemcpyHostToDevice));
+        }
+        o += 19 * V * sizeof(double);
+        const size_t nbb = (size_t)h->desc[i].n_beads * 3 * sizeof(double);
+        const size_t goff = lo.bead_off[i] * 3 * sizeof(double);
+        for (size_t arr : {lo.st_x, lo.st_v, lo.st_f, lo.st_fc}) {
+            if (nbb) HIPCHK(h, hipMemcpy(h->state + arr + goff, o, nbb, hipMemcpyHostToDevice));
+            o += nbb;
+        }
+    }
+    Ctrl ctrl;
+    HIPCHK(h, hipMemcpy(&ctrl, h->scratch + lo.sc_ctrl, sizeof ctrl, hipMemcpyDeviceToHost));
+    ctrl.step = (uint32_t)stepv;
+    HIPCHK(h, hipMemcpy(h->scratch + lo.sc_ctrl, &ctrl, sizeof ctrl, hipMemcpyHostToDevice));
+    std::vector<int32_t> nlcnt(std::max<uint64_t>(lo.total_beads, 1), -2);
+    HIPCHK(h, hipMemcpy(h->scratch + lo.sc_nlcnt, nlcnt.data(), nlcnt.size() * sizeof(int32_t), hipMemcpyHostToDevice));
+    h->step = stepv;
+    return LB_OK;
+}
+
+lb_status lb_pending_impulse(lb_handle* h, double* host_dense, size_t bytes)
+{
+    if (!h || !host_dense) return fail(h, LB_EINVAL, "null argument");
+    const Layout& lo = h->lo;
+    size_t need = 0;
+    for (int i = 0; i < h->n_boxes; ++i) need += 3 * lo.V[i] * sizeof(double);
+    if (bytes < need) return fail(h, LB_ENOMEM, "host buffer too small");
+    std::memset(host_dense, 0, need);
+    if (!lo.total_slots) return LB_OK;
+    std::vector<uint32_t> keys(lo.total_slots);
+    std::vector<unsigned long long> vals(3 * lo.total_slots);
+    HIPCHK(h, hipStreamSynchronize(h->stream));
+    HIPCHK(h, hipMemcpy(keys.data(), h->scratch + lo.sc_keys, keys.size() * 4, hipMemcpyDeviceToHost));
+    HIPCHK(h, hipMemcpy(vals.data(), h->scratch + lo.sc_vals, vals.size() * 8, hipMemcpyDeviceToHost));
+    size_t base = 0;
+    for (int i = 0; i < h->n_boxes; ++i) {
+        for (uint32_t s = 0; s < lo.tab_cap[i]; ++s) {
+            const uint32_t slot = lo.tab_off[i] + s;
+            if (!keys[slot]) continue;
+            const uint64_t r = keys[slot] - 1;
+            for (int c = 0; c < 3; ++c)
+                host_dense[base + c * lo.V[i] + r] = (double)(long long)vals[3 * (size_t)slot + c] * IMP_INV_SCALE;
+        }
+        base += 3 * lo.V[i];
+    }
+    return LB_OK;
+}
+
+lb_status lb_velocity_history(lb_handle* h, int64_t step, double* host_out, size_t bytes)
+{
+    if (!h || !host_out) return fail(h, LB_EINVAL, "null argument");
+    if (h->hist <= 0) return fail(h, LB_ESTATE, "no velocity history was requested at init");
+    const uint64_t nb = h->lo.total_beads;
+    if (bytes < nb * 3 * sizeof(double)) return fail(h, LB_ENOMEM, "host buffer too small");
+    const int64_t now = (int64_t)h->step;
+    if (step < 0 || step >= now || step < now - h->hist) return fail(h, LB_EINVAL, "step not in the history ring");
+    HIPCHK(h, hipStreamSynchronize(h->stream));
+    const size_t off = h->lo.sc_vhist + (size_t)(step % h->hist) * nb * 3 * sizeof(double);
+    HIPCHK(h, hipMemcpy(host_out, h->scratch + off, nb * 3 * sizeof(double), hipMemcpyDeviceToHost));
+    return LB_OK;
+}
+
+lb_status lb_set_launch(lb_handle* h, int32_t batched, int32_t graph_steps)
+{
+    if (!h) return fail(nullptr, LB_EINVAL, "null handle");
+    if (graph_steps < 0) return fail(h, LB_EINVAL, "graph_steps must be >= 0");
+    if (h->pending) return fail(h, LB_ESTATE, "impulses pending from lb_couple");
+    HIPCHK(h, hipStreamSynchronize(h->stream));
+    drop_graphs(h);
+    h->batched = batched ? 1 : 0;
+    h->graph_steps = graph_steps + (graph_steps & 1);
+    return LB_OK;
+}
+
+lb_status lb_collide_only(lb_handle* h, int32_t n)
+{
+    if (!h) return fail(nullptr, LB_EINVAL, "null handle");
+    if (n < 0) return fail(h, LB_EINVAL, "n must be >= 0");
+    const void* A = h->pop(h->cur);
+    void* B = h->pop(1 - h->cur);
+    for (int32_t k = 0; k < n; ++k) {
+        if (h->prec == LB_FP64)
+            HIPCHK(h, launch_collide<double>(h->ctx, A, B, -1, 0, (uint32_t)h->lo.total_tiles, 0));
+        else
+            HIPCHK(h, launch_collide<float>(h->ctx, A, B, -1, 0, (uint32_t)h->lo.total_tiles, 0));
+    }
+    return LB_OK;
+}
+
+void* lb_stream(const lb_handle* h) { return h ? (void*)h->stream : nullptr; }
+
+void lb_free(lb_handle* h)
+{
+    if (!h) return;
+    if (h->stream) (void)hipStreamSynchronize(h->stream);
+    drop_graphs(h);
+    if (h->own_stream && h->stream) (void)hipStreamDestroy(h->stream);
+    delete h;
+}
+
+const char* lb_last_error(const lb_handle* h) { return h ? h->err.c_str() : g_err.c_str(); }
+
+}  // extern "C"

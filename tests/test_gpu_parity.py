@@ -1,0 +1,253 @@
+"""GPU parity: the HIP library (through its C ABI) against the FP64 oracle on
+the same seeded inputs.  Bars: FP64 populations within 1e-12 absolute; FP32
+deviation storage within 1e-5 of w_i rho0 (relative) per population; bitwise
+equality where the computation is the same (batch vs single box, graph vs
+direct launches, repeated runs, export/import resume)."""
+from __future__ import annotations
+
+import numpy as np
+import pytest
+
+from lbtest import chain, gpu_system, initial_pops, max_rel_pop_err, oracle_state, params, say
+
+pytestmark = pytest.mark.gpu
+
+FP64, FP32 = 0, 1
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    torch = pytest.importorskip("torch")
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_0903_5067_amd as lbm
+    lbm.lib()
+
+
+# ---------------------------------------------------------------- fluid only
+@pytest.mark.parametrize("L", [3, 7, 16])
+@pytest.mark.parametrize("therm", [2, 1, 0])
+def test_fluid_fp64_matches_oracle(orc, L, therm):
+    """Collide+stream of every node, ragged last tile (7^3 = 343 nodes), tiny
+    periodic lattice (3^3), non-unit rates, all thermalization modes."""
+    say("fluid fp64", L, therm)
+    p = params(L=L, N=0, kT=0.05, omega_s=1.3, omega_b=0.7, omega_g=1.6, therm=therm, seed=9, box_id=4)
+    n0 = initial_pops(orc, p, amp=0.05, seed=L)
+    s = gpu_system([p], FP64, pops=[n0])
+    s.step(20)
+    ng = s.export_state()["boxes"][0]["n"]
+    o = oracle_state(orc, p, n0)
+    o.run(20)
+    assert np.max(np.abs(ng - o.n)) < 1e-12
+
+
+@pytest.mark.parametrize("L", [7, 16])
+def test_fluid_fp32dev_matches_oracle(orc, L):
+    say("fluid fp32", L)
+    p = params(L=L, N=0, kT=1e-3, omega_s=1.3, omega_b=0.7, omega_g=1.6, seed=3, box_id=1)
+    n0 = initial_pops(orc, p, amp=0.01, seed=L)
+    s = gpu_system([p], FP32, pops=[n0])
+    s.step(100)
+    ng = s.export_state()["boxes"][0]["n"]
+    o = oracle_state(orc, p, n0)
+    o.run(100)
+    assert max_rel_pop_err(ng, o.n, orc) < 1e-5
+
+
+# ------------------------------------------------------------------ coupling
+@pytest.mark.parametrize("prec", [FP64, FP32])
+def test_couple_matches_oracle(orc, prec):
+    """One LB step of MD substeps in the frozen fluid: node impulses, bead
+    positions, velocities and forces against the oracle."""
+    say("couple", prec)
+    p = params(L=12, N=16, kT=1e-2)
+    x0 = chain(p)
+    n0 = initial_pops(orc, p, amp=0.02, seed=5)
+    s = gpu_system([p], prec, xs=[x0], pops=[n0])
+    s.couple()
+    dp_g = s.pending_impulse()[0]
+    bg = s.export_state()["boxes"][0]
+    o = oracle_state(orc, p, n0, x0)
+    dp_o = o.couple()
+    tol = 1e-13 if prec == FP64 else 1e-9
+    assert np.max(np.abs(dp_g - dp_o)) < tol
+    assert np.count_nonzero(dp_o[0]) == np.count_nonzero(dp_g[0]) > 0
+    for k, ref in (("x", o.x), ("v", o.v), ("f", o.f), ("fc", o.fc)):
+        assert np.max(np.abs(bg[k] - ref)) < (1e-11 if prec == FP64 else 1e-6), k
+    # the pending impulses are consumed by the next step: continue both sides
+    s.step(1)
+    o.collide_stream(dp_o)
+    ng = s.export_state()["boxes"][0]["n"]
+    assert max_rel_pop_err(ng, o.n, orc) < (1e-12 if prec == FP64 else 1e-5)
+
+
+def test_plain16_fp64_full_run(orc):
+    """16^3, FP64, chain N=16, kT=1e-4, 1000 LB steps of 10 substeps."""
+    say("plain16 fp64 1000")
+    p = params("plain16")
+    x0 = chain(p)
+    n0 = initial_pops(orc, p)
+    s = gpu_system([p], FP64, xs=[x0])
+    s.step(1000)
+    st = s.export_state()["boxes"][0]
+    o = oracle_state(orc, p, n0, x0)
+    o.run(1000)
+    assert np.max(np.abs(st["n"] - o.n)) < 1e-12
+    assert np.max(np.abs(st["x"] - o.x)) < 1e-9
+    assert np.max(np.abs(st["v"] - o.v)) < 1e-9
+    og = s.observables()[0]
+    oo = o.observables()
+    # the oracle stores full populations and its FP64 mass drifts by round-off
+    # (~3e-13 relative over 4M node updates); the GPU stores deviations
+    assert og["mass"] == pytest.approx(oo[0], rel=1e-12)
+    np.testing.assert_allclose(og["p_total"], oo[10:13], atol=1e-12)
+    assert og["rg2"] == pytest.approx(oo[16], rel=1e-10)
+    assert og["re2"] == pytest.approx(oo[17], rel=1e-10)
+    np.testing.assert_allclose(og["com"], oo[13:16], rtol=1e-12)
+    np.testing.assert_allclose(og["mode_sq"], oo[19:38], rtol=1e-9, atol=1e-20)
+
+
+def test_plain16_fp32dev_full_run(orc):
+    say("plain16 fp32 1000")
+    p = params("plain16")
+    x0 = chain(p)
+    n0 = initial_pops(orc, p)
+    s = gpu_system([p], FP32, xs=[x0])
+    s.step(1000)
+    st = s.export_state()["boxes"][0]
+    o = oracle_state(orc, p, n0, x0)
+    o.run(1000)
+    assert max_rel_pop_err(st["n"], o.n, orc) < 1e-5
+    assert np.max(np.abs(st["x"] - o.x)) < 1e-5
+
+
+def test_velocity_history_and_vacf(orc):
+    """Bead velocities recorded at the end of each LB step; VACF of the first
+    steps against the oracle's."""
+    say("vhist")
+    p = params(L=16, N=16, kT=1e-3)
+    x0 = chain(p)
+    n0 = initial_pops(orc, p)
+    T = 60
+    s = gpu_system([p], FP32, xs=[x0], hist_steps=T)
+    s.step(T)
+    hg = np.stack([s.velocity_history(t) for t in range(T)])
+    o = oracle_state(orc, p, n0, x0)
+    ho = o.run(T, record_velocities=True)
+    assert np.max(np.abs(hg - ho)) < 1e-6 * max(1.0, np.max(np.abs(ho)))
+
+    def vacf(h, tmax=20):
+        return np.array([np.mean(np.sum(h[: T - k] * h[k:], axis=2)) for k in range(tmax)])
+
+    np.testing.assert_allclose(vacf(hg), vacf(ho), rtol=1e-5, atol=1e-12)
+
+
+# ------------------------------------------------------------- structure
+def _boxes():
+    b0 = params(L=8, N=4, seed=5, box_id=0)
+    b1 = params(L=11, N=8, seed=5, box_id=1, kT=1e-3, omega_s=1.2)
+    b2 = params(L=6, N=0, seed=6, box_id=2)
+    return [b0, b1, b2]
+
+
+def test_batched_equals_single_bitwise(orc):
+    """A box inside a batch evolves bit for bit as the same box alone, and the
+    per-box (plain) launches equal the one-launch batch."""
+    say("batch vs single")
+    boxes = _boxes()
+    xs = [chain(b) for b in boxes]
+    sb = gpu_system(boxes, FP32, xs=xs)
+    sb.step(25)
+    batch = sb.export_state()["boxes"]
+    sp = gpu_system(boxes, FP32, xs=xs)
+    sp.set_launch(batched=False)
+    sp.step(25)
+    plain = sp.export_state()["boxes"]
+    for i, b in enumerate(boxes):
+        si = gpu_system([b], FP32, xs=[xs[i]])
+        si.step(25)
+        single = si.export_state()["boxes"][0]
+        for k in ("n", "x", "v", "f", "fc"):
+            assert np.array_equal(batch[i][k], single[k]), (i, k)
+            assert np.array_equal(plain[i][k], single[k]), (i, k)
+    # and the batch agrees with the oracle box by box
+    for i, b in enumerate(boxes):
+        o = oracle_state(orc, b, initial_pops(orc, b), xs[i] if b["N"] else None)
+        o.run(25)
+        assert max_rel_pop_err(batch[i]["n"], o.n, orc) < 1e-5
+
+
+def test_graph_equals_direct_bitwise():
+    say("graph vs direct")
+    boxes = _boxes()
+    xs = [chain(b) for b in boxes]
+    sd = gpu_system(boxes, FP32, xs=xs)
+    sd.step(13)
+    a = sd.export_state()
+    sg = gpu_system(boxes, FP32, xs=xs)
+    sg.set_launch(batched=True, graph_steps=4)
+    sg.step(13)      # 3 graph replays + 1 direct step
+    b = sg.export_state()
+    assert a["step"] == b["step"] == 13
+    for ba, bb in zip(a["boxes"], b["boxes"]):
+        for k in ba:
+            assert np.array_equal(ba[k], bb[k]), k
+
+
+def test_runs_are_deterministic_and_resumable():
+    """Two runs are bitwise equal (the impulse spreading is order-independent
+    fixed point); export after 10 steps + import + 10 steps equals 20 steps."""
+    say("determinism")
+    boxes = _boxes()
+    xs = [chain(b) for b in boxes]
+    r = []
+    for _ in range(2):
+        s = gpu_system(boxes, FP32, xs=xs)
+        s.step(20)
+        r.append(s.export_state())
+    for ba, bb in zip(r[0]["boxes"], r[1]["boxes"]):
+        for k in ba:
+            assert np.array_equal(ba[k], bb[k])
+    s = gpu_system(boxes, FP32, xs=xs)
+    s.step(10)
+    mid = s.export_state()
+    s2 = gpu_system(boxes, FP32, xs=xs)
+    s2.import_state(mid)
+    s2.step(10)
+    c = s2.export_state()
+    assert c["step"] == 20
+    for ba, bb in zip(r[0]["boxes"], c["boxes"]):
+        for k in ba:
+            assert np.array_equal(ba[k], bb[k]), k
+
+
+def test_conservation_on_gpu(orc):
+    """Mass conserved to round-off; the coupled momentum invariant holds."""
+    say("conservation")
+    p = params(L=16, N=16, kT=1e-2)
+    x0 = chain(p)
+    for prec, tol in ((FP64, 1e-12), (FP32, 1e-6)):
+        s = gpu_system([p], prec, xs=[x0])
+        o0 = s.observables()[0]
+        s.step(200)
+        o1 = s.observables()[0]
+        assert abs(o1["mass"] - o0["mass"]) / o0["mass"] < tol
+        np.testing.assert_allclose(o1["p_total"], o0["p_total"], atol=1e-9 if prec == FP64 else 1e-4)
+        assert np.max(np.abs(o1["p_beads"])) > 0
+
+
+def test_health_flag_from_nan():
+    """A NaN population is reported as a density/Mach health failure."""
+    import paper_0903_5067_amd as lbm
+    say("health")
+    p = params(L=6, N=0)
+    s = gpu_system([p], FP32)
+    st = s.export_state()
+    st["boxes"][0]["n"][3, 1, 2, 3] = np.nan
+    s.import_state(st)
+    s.step(1)
+    with pytest.raises(lbm.LBError) as ei:
+        s.observables()
+    assert ei.value.status == lbm.LB_ENUMERIC
+    o = s.observables(allow_unhealthy=True)[0]
+    assert o["health"] & (lbm.HEALTH["density"] | lbm.HEALTH["mach"])
