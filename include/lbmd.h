@@ -106,7 +106,7 @@ typedef struct {
     double neg_count;     /* number of populations n_i < 0 */
     double mode_sq[19];   /* sum over nodes of (m_k - rho0 delta_k0)^2 */
     uint32_t health;      /* LB_HEALTH_* bits accumulated since init (sticky) */
-    uint32_t pad;
+    uint32_t nlist_builds;/* chain neighbour-list builds since init (diagnostic) */
     uint64_t step;        /* LB steps taken since init */
 } lb_obs;
 

@@ -48,7 +48,7 @@ class Obs(ctypes.Structure):
         ("p_total", ctypes.c_double * 3), ("com", ctypes.c_double * 3),
         ("rg2", ctypes.c_double), ("re2", ctypes.c_double),
         ("neg_count", ctypes.c_double), ("mode_sq", ctypes.c_double * 19),
-        ("health", ctypes.c_uint32), ("pad", ctypes.c_uint32), ("step", ctypes.c_uint64),
+        ("health", ctypes.c_uint32), ("nlist_builds", ctypes.c_uint32), ("step", ctypes.c_uint64),
     ]
 
 
@@ -179,7 +179,8 @@ class LBSystem:
             res.append({"mass": o.mass, "j_lat": np.array(o.j_lat), "p_fluid": np.array(o.p_fluid),
                         "p_beads": np.array(o.p_beads), "p_total": np.array(o.p_total),
                         "com": np.array(o.com), "rg2": o.rg2, "re2": o.re2, "neg": o.neg_count,
-                        "mode_sq": np.array(o.mode_sq), "health": o.health, "step": o.step})
+                        "mode_sq": np.array(o.mode_sq), "health": o.health, "step": o.step,
+                        "nlist_builds": o.nlist_builds})
         return res
 
     def export_state(self) -> dict:

@@ -26,7 +26,7 @@ struct BoxDev {
     int32_t substeps;
     double rho0, gam_b, gam_s, gam_g, mu;
     double tau_lb, dt, mass, zeta, k_fene, r0sq, eps, sigsq, rc2, bead_noise;
-    double inv_L;
+    double inv_L, inv_r0sq;
 };
 
 // control block in device memory: step index read by every kernel so that a
@@ -46,10 +46,12 @@ enum : uint32_t {
     H_NLIST = 1u << 5,     // neighbour list overflow
 };
 
-// fixed-point scale of the node impulse accumulator (lattice momentum units)
-constexpr double IMP_SCALE = 281474976710656.0;          // 2^48
-constexpr double IMP_INV_SCALE = 1.0 / 281474976710656.0;
-constexpr double IMP_MAX = 16384.0;                       // |impulse| bound, 2^14
+// fixed-point scale of the node impulse accumulator (lattice momentum units):
+// resolution 2^-52, range +-2^11 per node (a lattice momentum of 1 per node
+// is already far beyond the Mach limit)
+constexpr double IMP_SCALE = 4503599627370496.0;          // 2^52
+constexpr double IMP_INV_SCALE = 1.0 / 4503599627370496.0;
+constexpr double IMP_MAX = 1024.0;                        // |impulse| bound per contribution
 
 // ----------------------------------------------------------------- Philox
 struct U4 { uint32_t x, y, z, w; };

@@ -1,15 +1,22 @@
 // HIP kernels of the fluctuating D3Q19 LB step with a dissipatively coupled
 // bead-spring chain, for gfx950 (MI355X).
 //
-//   k_couple      one workgroup per chain: velocity-Verlet substeps in the
-//                 fluid velocity field frozen at the pre-collision state,
-//                 trilinear interpolation, friction + Langevin force, and the
-//                 impulse handed back to the stencil nodes (Sec. II.B,
-//                 coupling paragraph; potentials of Sec. II.A)
-//   k_collide     fused collide + push-stream of every node, no impulse
-//                 (Sec. II.B, LB equation), thread per node, SoA planes
-//   k_fixup       re-collides the few nodes that received an impulse and
-//                 overwrites their streamed outputs
+//   k_couple      one workgroup per chain (T lanes per bead): velocity-Verlet
+//                 substeps in the fluid velocity field frozen at the
+//                 pre-collision state, trilinear interpolation, friction +
+//                 Langevin force, and the impulse handed back to the stencil
+//                 nodes (Sec. II.B, coupling paragraph; potentials of
+//                 Sec. II.A).  Impulses go into a dense fixed-point field by
+//                 atomic adds that nothing waits on (order-independent, hence
+//                 bitwise reproducible); each bead lists the nodes it touched.
+//   k_collide     fused stream + collide of every node, no impulse
+//                 (Sec. II.B, LB equation), thread per node, SoA planes.
+//                 Pull form: a buffer holds post-collision populations p,
+//                 the pre-collision population of node r is n_i(r) =
+//                 p_i(r - c_i); reads are gathered, writes aligned and
+//                 non-temporal.
+//   k_fixup       re-collides the nodes the beads touched, with their
+//                 impulse, and overwrites their outputs
 //   k_stats*      FP64 conserved sums, mode variances, negative-population
 //                 count; k_chain_obs: centre of mass, R_g^2, R_e^2 (Sec. III.A)
 #include "lbmd_device.hpp"
@@ -25,6 +32,36 @@ __device__ __forceinline__ uint32_t div_L(uint32_t r, int L, double inv_L, uint3
     else if (rr >= L) { q += 1; rr -= L; }
     *rem = (uint32_t)rr;
     return q;
+}
+
+// Index of the node r - c_i for every direction i (periodic), from the node's
+// coordinates: the source of the population that arrives at r.
+struct Upwind {
+    uint32_t X[3], Y[3], Z[3];
+    __device__ __forceinline__ Upwind(uint32_t x, uint32_t y, uint32_t z, uint32_t L)
+    {
+        const uint32_t LL = L * L;
+        X[0] = x + 1 == L ? 0 : x + 1; X[1] = x; X[2] = x == 0 ? L - 1 : x - 1;
+        Y[0] = (y + 1 == L ? 0 : y + 1) * L; Y[1] = y * L; Y[2] = (y == 0 ? L - 1 : y - 1) * L;
+        Z[0] = (z + 1 == L ? 0 : z + 1) * LL; Z[1] = z * LL; Z[2] = (z == 0 ? L - 1 : z - 1) * LL;
+    }
+    // slot 0 holds coordinate + 1, slot 2 coordinate - 1: r - c_i uses slot c_i + 1
+    __device__ __forceinline__ uint32_t src(int i) const { return X[cxv(i) + 1] + Y[cyv(i) + 1] + Z[czv(i) + 1]; }
+};
+
+template <typename R, bool NT>
+__device__ __forceinline__ void gather_pre(const R* __restrict__ a, uint64_t ps, const Upwind& up, R d[19])
+{
+#pragma unroll
+    for (int i = 0; i < 19; ++i) d[i] = NT ? __builtin_nontemporal_load(a + i * ps + up.src(i)) : a[i * ps + up.src(i)];
+}
+
+__device__ __forceinline__ Upwind upwind_of(uint32_t r, int L, double inv_L)
+{
+    uint32_t x, y;
+    const uint32_t q = div_L(r, L, inv_L, &x);
+    const uint32_t z = div_L(q, L, inv_L, &y);
+    return Upwind(x, y, z, (uint32_t)L);
 }
 
 // -------------------------------------------------------------- collide
@@ -46,191 +83,131 @@ __global__ __launch_bounds__(256) void k_collide(const BoxDev* __restrict__ boxe
     const uint32_t t = ctrl->step + s_off;
     const CollideConst<R> cc = ccs[bi];
     const uint64_t ps = bx.ps;
-    const R* a = A + bx.pop_off + r;
+    const Upwind up = upwind_of(r, L, bx.inv_L);
     R d[19];
-#pragma unroll
-    for (int i = 0; i < 19; ++i) d[i] = a[i * ps];
+    gather_pre<R, false>(A + bx.pop_off, ps, up, d);
     R o[19];
-    uint32_t h = collide<R>(d, o, (R)0, (R)0, (R)0, cc, r, t, bx.seed, bx.box_id);
-    uint32_t x, y, z;
-    uint32_t q = div_L(r, L, bx.inv_L, &x);
-    z = div_L(q, L, bx.inv_L, &y);
-    const uint32_t xm = x == 0 ? L - 1 : x - 1, xp = x + 1 == (uint32_t)L ? 0 : x + 1;
-    const uint32_t ym = y == 0 ? L - 1 : y - 1, yp = y + 1 == (uint32_t)L ? 0 : y + 1;
-    const uint32_t zm = z == 0 ? L - 1 : z - 1, zp = z + 1 == (uint32_t)L ? 0 : z + 1;
-    const uint32_t X[3] = {xm, x, xp};
-    const uint32_t Y[3] = {ym * L, y * L, yp * L};
-    const uint32_t LL = (uint32_t)L * L;
-    const uint32_t Z[3] = {zm * LL, z * LL, zp * LL};
-    R* b = B + bx.pop_off;
+    const uint32_t h = collide<R>(d, o, (R)0, (R)0, (R)0, cc, r, t, bx.seed, bx.box_id);
+    R* b = B + bx.pop_off + r;
 #pragma unroll
-    for (int i = 0; i < 19; ++i) {
-        const uint32_t dst = X[cxv(i) + 1] + Y[cyv(i) + 1] + Z[czv(i) + 1];
-        b[i * ps + dst] = o[i];
-    }
-    if (h) atomicOr(&ctrl->health, h);
-}
-
-// ---------------------------------------------------------------- fixup
-// One thread per impulse-table slot of the launched boxes.  The slot's key is
-// 1 + local node index (0 = empty); values are fixed-point impulses.
-template <typename R>
-__global__ __launch_bounds__(256) void k_fixup(const BoxDev* __restrict__ boxes, int n_boxes,
-                                               const CollideConst<R>* __restrict__ ccs,
-                                               const uint32_t* __restrict__ tab_off,
-                                               uint32_t slot0, uint32_t n_slots, int fixed_box,
-                                               uint32_t* __restrict__ keys,
-                                               unsigned long long* __restrict__ vals,
-                                               const R* __restrict__ A, R* __restrict__ B,
-                                               Ctrl* __restrict__ ctrl, uint32_t s_off)
-{
-    const uint32_t sidx = blockIdx.x * 256u + threadIdx.x;
-    if (sidx >= n_slots) return;
-    const uint32_t slot = slot0 + sidx;
-    const uint32_t key = keys[slot];
-    if (key == 0) return;
-    int bi = fixed_box;
-    if (bi < 0) {   // last box whose table starts at or before the slot
-        int lo = 0, hi = n_boxes - 1;
-        while (lo < hi) {
-            int mid = (lo + hi + 1) >> 1;
-            if (tab_off[mid] <= slot) lo = mid; else hi = mid - 1;
-        }
-        bi = lo;
-    }
-    const BoxDev& bx = boxes[bi];
-    const uint32_t r = key - 1;
-    const int L = bx.L;
-    const uint32_t t = ctrl->step + s_off;
-    const CollideConst<R> cc = ccs[bi];
-    const uint64_t ps = bx.ps;
-    const R* a = A + bx.pop_off + r;
-    R d[19];
-#pragma unroll
-    for (int i = 0; i < 19; ++i) d[i] = a[i * ps];
-    R f[3];
-#pragma unroll
-    for (int c = 0; c < 3; ++c) {
-        f[c] = (R)((double)(long long)vals[3 * (uint64_t)slot + c] * IMP_INV_SCALE);
-        vals[3 * (uint64_t)slot + c] = 0ull;
-    }
-    keys[slot] = 0u;
-    R o[19];
-    uint32_t h = collide<R>(d, o, f[0], f[1], f[2], cc, r, t, bx.seed, bx.box_id);
-    uint32_t x, y, z;
-    uint32_t q = div_L(r, L, bx.inv_L, &x);
-    z = div_L(q, L, bx.inv_L, &y);
-    const uint32_t xm = x == 0 ? L - 1 : x - 1, xp = x + 1 == (uint32_t)L ? 0 : x + 1;
-    const uint32_t ym = y == 0 ? L - 1 : y - 1, yp = y + 1 == (uint32_t)L ? 0 : y + 1;
-    const uint32_t zm = z == 0 ? L - 1 : z - 1, zp = z + 1 == (uint32_t)L ? 0 : z + 1;
-    const uint32_t X[3] = {xm, x, xp};
-    const uint32_t Y[3] = {ym * L, y * L, yp * L};
-    const uint32_t LL = (uint32_t)L * L;
-    const uint32_t Z[3] = {zm * LL, z * LL, zp * LL};
-    R* b = B + bx.pop_off;
-#pragma unroll
-    for (int i = 0; i < 19; ++i) b[i * ps + X[cxv(i) + 1] + Y[cyv(i) + 1] + Z[czv(i) + 1]] = o[i];
+    for (int i = 0; i < 19; ++i) __builtin_nontemporal_store(o[i], b + i * ps);
     if (h) atomicOr(&ctrl->health, h);
 }
 
 // --------------------------------------------------------------- couple
 struct ChainArgs {
     double* x; double* v; double* f; double* fc;   // [total beads][3]
-    int32_t* nl_cnt; int32_t* nl_idx; double* nl_x0; int nl_cap;
-    uint32_t* keys; unsigned long long* vals; const uint32_t* tab_off; const uint32_t* tab_cap;
+    int32_t* nl_cnt; uint16_t* nl_idx; double* nl_x0; int nl_cap;
+    unsigned long long* imp;   // dense impulse field, 3 per node (global node index), fixed point
+    uint32_t* touched;         // per bead: local nodes it handed impulse to this step
+    int32_t* touched_cnt;
+    int touch_cap;             // slots per bead: 8 x (substeps + 1), one stencil change per substep at most
+    uint32_t* nl_rebuilds;     // per box: neighbour-list builds so far (diagnostic)
     double* vhist; int hist_len; uint64_t total_beads;
 };
 
-__device__ __forceinline__ uint32_t hash_node(uint32_t k)
+// node velocities (MD units) of the 8 stencil nodes from the frozen populations;
+// ALL_AT_ONCE issues every load before any use (for the register-rich variant)
+template <typename R, typename U, bool ALL_AT_ONCE>
+__device__ __forceinline__ void stencil_velocities(const R* __restrict__ a, uint64_t ps, const int i0[3], int L,
+                                                   double rho0, double inv_tau, U u[8][3])
 {
-    k ^= k >> 16; k *= 0x7feb352dU; k ^= k >> 15; k *= 0x846ca68bU; k ^= k >> 16;
-    return k;
-}
-
-// add a lattice-unit impulse (3 components) to local node r of the box's table
-__device__ __forceinline__ uint32_t table_add(uint32_t* keys, unsigned long long* vals, uint32_t off,
-                                              uint32_t cap, uint32_t r, const double p[3])
-{
-    uint32_t hbits = 0;
-    unsigned long long q[3];
+    constexpr int NB = ALL_AT_ONCE ? 8 : 1;
 #pragma unroll
-    for (int c = 0; c < 3; ++c) {
-        double v = p[c];
-        if (!(fabs(v) < IMP_MAX)) { hbits |= H_FIXED; v = v > 0 ? IMP_MAX : -IMP_MAX; if (v != v) v = 0; }
-        q[c] = (unsigned long long)(long long)llrint(v * IMP_SCALE);
-    }
-    const uint32_t key = r + 1;
-    uint32_t s = hash_node(key) & (cap - 1);
-    for (uint32_t probe = 0; probe < cap; ++probe) {
-        uint32_t prev = atomicCAS(&keys[off + s], 0u, key);
-        if (prev == 0u || prev == key) {
+    for (int k0 = 0; k0 < 8; k0 += NB) {
+        R d[NB][19];
 #pragma unroll
-            for (int c = 0; c < 3; ++c) atomicAdd(&vals[3 * (uint64_t)(off + s) + c], q[c]);
-            return hbits;
+        for (int k = 0; k < NB; ++k) {
+            const int kk = k0 + k;
+            const int ix = i0[0] + (kk & 1), iy = i0[1] + ((kk >> 1) & 1), iz = i0[2] + ((kk >> 2) & 1);
+            const Upwind up((uint32_t)(ix >= L ? ix - L : ix), (uint32_t)(iy >= L ? iy - L : iy),
+                            (uint32_t)(iz >= L ? iz - L : iz), (uint32_t)L);
+            gather_pre<R, false>(a, ps, up, d[k]);
         }
-        s = (s + 1) & (cap - 1);
-    }
-    return hbits | H_TABLE;
-}
-
-template <typename R>
-__device__ __forceinline__ void node_velocity(const R* __restrict__ a, uint64_t ps, uint32_t r, double rho0,
-                                              double inv_tau, double u[3])
-{
-    double rho = 0.0, jx = 0.0, jy = 0.0, jz = 0.0;
 #pragma unroll
-    for (int i = 0; i < 19; ++i) {
-        const double di = (double)a[i * ps + r];
-        rho += di;
-        if (cxv(i)) jx += cxv(i) * di;
-        if (cyv(i)) jy += cyv(i) * di;
-        if (czv(i)) jz += czv(i) * di;
+        for (int k = 0; k < NB; ++k) {
+            double rho = 0.0, jx = 0.0, jy = 0.0, jz = 0.0;
+#pragma unroll
+            for (int i = 0; i < 19; ++i) {
+                const double di = (double)d[k][i];
+                rho += di;
+                if (cxv(i)) jx += cxv(i) * di;
+                if (cyv(i)) jy += cyv(i) * di;
+                if (czv(i)) jz += czv(i) * di;
+            }
+            rho += rho0;
+            u[k0 + k][0] = (U)(jx / rho * inv_tau);
+            u[k0 + k][1] = (U)(jy / rho * inv_tau);
+            u[k0 + k][2] = (U)(jz / rho * inv_tau);
+        }
     }
-    rho += rho0;
-    u[0] = jx / rho * inv_tau;
-    u[1] = jy / rho * inv_tau;
-    u[2] = jz / rho * inv_tau;
 }
 
 constexpr int MAXB = 1024;
 constexpr double NL_SKIN = 0.5;
 
-// Conservative force on bead b (Sec. II.A): FENE to the bonded neighbours
-// (unwrapped separations), purely repulsive LJ to every other bead within the
-// cut-off (minimum image).  xs: positions of all beads of the chain (LDS).
-// nl: ascending list of candidate partners (cnt >= 0) or NULL for all beads.
-__device__ __forceinline__ uint32_t cons_force(const BoxDev& bx, int b, int N, const double x[3],
-                                               const double* xs, int cnt, const int32_t* nl, double F[3])
+// FENE force on bead b from its bonded neighbours (Sec. II.A), unwrapped separations
+__device__ __forceinline__ uint32_t fene_force(const BoxDev& bx, int b, int N, const double x[3],
+                                               const double* xs, double F[3])
 {
-    const double Ld = (double)bx.L;
     uint32_t hb = 0;
-    F[0] = F[1] = F[2] = 0.0;
 #pragma unroll
     for (int side = 0; side < 2; ++side) {
         const int j = side ? b + 1 : b - 1;
         if (j < 0 || j >= N) continue;
         const double d0 = x[0] - xs[3 * j], d1 = x[1] - xs[3 * j + 1], d2 = x[2] - xs[3 * j + 2];
         const double r2 = d0 * d0 + d1 * d1 + d2 * d2;
-        double den = 1.0 - r2 / bx.r0sq;
+        double den = 1.0 - r2 * bx.inv_r0sq;
         if (!(den > 0.0)) { hb |= H_FENE; den = 1e-12; }
         const double gf = -bx.k_fene / den;
         F[0] += gf * d0; F[1] += gf * d1; F[2] += gf * d2;
     }
-    const int nloop = cnt >= 0 ? cnt : N;
-    for (int jj = 0; jj < nloop; ++jj) {
-        const int j = cnt >= 0 ? nl[jj] : jj;
-        if (j == b) continue;
-        double d0 = x[0] - xs[3 * j], d1 = x[1] - xs[3 * j + 1], d2 = x[2] - xs[3 * j + 2];
-        d0 -= Ld * rint(d0 / Ld); d1 -= Ld * rint(d1 / Ld); d2 -= Ld * rint(d2 / Ld);
-        const double r2 = d0 * d0 + d1 * d1 + d2 * d2;
-        if (r2 < bx.rc2) {
-            const double s2 = bx.sigsq / r2;
+    return hb;
+}
+
+// purely repulsive LJ on bead b from beads j0, j0+T, j0+2T, j0+3T (those < N
+// and != b): the four separations are independent, so their latencies overlap;
+// the forces are added in ascending j.
+template <typename IDX>
+__device__ __forceinline__ void wca_add4(const double x[3], const double* xs, IDX jof, int k0, int kend, int step,
+                                         int b, double Ld, double iL, double rc2, double sigsq, double eps24,
+                                         double F[3])
+{
+    double d[4][3], r2[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+        const int k = k0 + u * step;
+        const int j = k < kend ? jof(k) : b;
+        d[u][0] = x[0] - xs[3 * j]; d[u][1] = x[1] - xs[3 * j + 1]; d[u][2] = x[2] - xs[3 * j + 2];
+        d[u][0] -= Ld * rint(d[u][0] * iL); d[u][1] -= Ld * rint(d[u][1] * iL); d[u][2] -= Ld * rint(d[u][2] * iL);
+        r2[u] = j == b ? rc2 : d[u][0] * d[u][0] + d[u][1] * d[u][1] + d[u][2] * d[u][2];
+    }
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+        if (r2[u] < rc2) {
+            const double ir2 = 1.0 / r2[u];
+            const double s2 = sigsq * ir2;
             const double s6 = s2 * s2 * s2;
-            const double gf = 24.0 * bx.eps * s6 * (2.0 * s6 - 1.0) / r2;
-            F[0] += gf * d0; F[1] += gf * d1; F[2] += gf * d2;
+            const double gf = eps24 * s6 * (2.0 * s6 - 1.0) * ir2;
+            F[0] += gf * d[u][0]; F[1] += gf * d[u][1]; F[2] += gf * d[u][2];
         }
     }
-    return hb;
+}
+
+// purely repulsive LJ on bead b from bead j (minimum image), cut at 2^(1/6) sigma
+__device__ __forceinline__ void wca_add(const double x[3], const double* xs, int j, double Ld, double iL,
+                                        double rc2, double sigsq, double eps24, double F[3])
+{
+    double d0 = x[0] - xs[3 * j], d1 = x[1] - xs[3 * j + 1], d2 = x[2] - xs[3 * j + 2];
+    d0 -= Ld * rint(d0 * iL); d1 -= Ld * rint(d1 * iL); d2 -= Ld * rint(d2 * iL);
+    const double r2 = d0 * d0 + d1 * d1 + d2 * d2;
+    if (r2 < rc2) {
+        const double ir2 = 1.0 / r2;
+        const double s2 = sigsq * ir2;
+        const double s6 = s2 * s2 * s2;
+        const double gf = eps24 * s6 * (2.0 * s6 - 1.0) * ir2;
+        F[0] += gf * d0; F[1] += gf * d1; F[2] += gf * d2;
+    }
 }
 
 // initial last-force of every bead: the conservative force at the start positions
@@ -248,48 +225,93 @@ __global__ __launch_bounds__(1024) void k_init_forces(const BoxDev* __restrict__
         for (int c = 0; c < 3; ++c) { x[c] = xg[3 * g + c]; xs[3 * b + c] = x[c]; }
     __syncthreads();
     if (b < N) {
-        double F[3];
-        uint32_t hb = cons_force(bx, b, N, x, xs, -1, nullptr, F);
-        for (int c = 0; c < 3; ++c) fg[3 * g + c] = F[c];
+        double F[3] = {0, 0, 0};
+        uint32_t hb = fene_force(bx, b, N, x, xs, F);
+        double W[3] = {0, 0, 0};
+        for (int j = 0; j < N; ++j)
+            if (j != b) wca_add(x, xs, j, (double)bx.L, bx.inv_L, bx.rc2, bx.sigsq, 24.0 * bx.eps, W);
+        for (int c = 0; c < 3; ++c) fg[3 * g + c] = F[c] + W[c];
         if (hb) atomicOr(&ctrl->health, hb);
     }
 }
 
-template <typename R>
-__global__ __launch_bounds__(1024) void k_couple(const BoxDev* __restrict__ boxes,
+// hand one stencil's accumulated impulse (MD units) to the dense field and
+// list the nodes; no result is waited on
+__device__ __forceinline__ uint32_t flush_stencil(const ChainArgs& ca, uint64_t node_off, uint64_t g,
+                                                  const uint32_t cnode[8], double acc[8][3], double tau,
+                                                  int& tcnt)
+{
+    uint32_t hb = 0;
+#pragma unroll
+    for (int k = 0; k < 8; ++k) {
+        unsigned long long* dst = ca.imp + 3 * (node_off + cnode[k]);
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            double v = acc[k][c] * tau;      // lattice momentum units
+            if (!(fabs(v) < IMP_MAX)) { hb |= H_FIXED; v = 0.0; }
+            atomicAdd(dst + c, (unsigned long long)(long long)llrint(v * IMP_SCALE));
+        }
+        if (tcnt < ca.touch_cap) ca.touched[g * ca.touch_cap + tcnt] = cnode[k];
+        else hb |= H_TABLE;
+        ++tcnt;
+    }
+    return hb;
+}
+
+// One workgroup per chain; T lanes per bead split the pair loop.  Threads
+// 0..T*Npad-1: bead b = tid / T, lane = tid % T.  All T lanes of a bead
+// compute the same bead update (their force partial sums are combined by a
+// butterfly, which gives every lane the same bits); lane 0 writes.
+template <typename R, int MAXT>
+__global__ __launch_bounds__(MAXT) void k_couple(const BoxDev* __restrict__ boxes,
                                                  const int32_t* __restrict__ couple_list,
-                                                 const R* __restrict__ A, ChainArgs ca,
+                                                 const R* __restrict__ A, ChainArgs ca, int T,
                                                  Ctrl* __restrict__ ctrl, uint32_t s_off)
 {
     __shared__ double xs[3 * MAXB];
+    __shared__ uint16_t nls[MAXT == 1024 ? MAXB * NL_SLOTS : 1];
     const int bi = couple_list[blockIdx.x];
     const BoxDev& bx = boxes[bi];
     const int N = bx.N;
-    const int b = threadIdx.x;
+    const int b = threadIdx.x / T, lane = threadIdx.x % T;
     const bool act = b < N;
+    const bool writer = act && lane == 0;
     const uint64_t g = bx.bead_off + (uint64_t)(act ? b : 0);
     const uint32_t t = ctrl->step + s_off;
     const int L = bx.L;
-    const double Ld = (double)L;
-    const double dt = bx.dt, m = bx.mass, hdt_m = 0.5 * dt / m;
+    const double Ld = (double)L, iL = bx.inv_L;
+    const double dt = bx.dt, hdt_m = 0.5 * dt / bx.mass;
     const double inv_tau = 1.0 / bx.tau_lb;
+    const double eps24 = 24.0 * bx.eps;
     const R* a = A + bx.pop_off;
-    const uint32_t toff = ca.tab_off[bi], tcap = ca.tab_cap[bi];
-    const bool use_nl = N > 64;
+    const bool use_nl = MAXT == 1024 && T == 1 && N > 128;
     const double rl = sqrt(bx.rc2) + NL_SKIN;
     const double rl2 = rl * rl;
+    const int nl_cap = ca.nl_cap;
 
     double x[3] = {0, 0, 0}, v[3] = {0, 0, 0}, f[3] = {0, 0, 0}, fcl[3] = {0, 0, 0};
+    double x0n[3] = {0, 0, 0};    // positions at the last neighbour-list build
+    int nl_n = -2;
     if (act) {
 #pragma unroll
         for (int c = 0; c < 3; ++c) { x[c] = ca.x[3 * g + c]; v[c] = ca.v[3 * g + c]; f[c] = ca.f[3 * g + c]; }
+        if (use_nl) {
+            nl_n = ca.nl_cnt[g];
+#pragma unroll
+            for (int c = 0; c < 3; ++c) x0n[c] = ca.nl_x0[3 * g + c];
+            for (int k = 0; k < (nl_n > 0 ? nl_n : 0); ++k) nls[k * MAXB + b] = ca.nl_idx[g * nl_cap + k];
+        }
     }
+    int rebuilds = 0;
     int cb[3] = {-1, -1, -1};     // base cell of the cached stencil
-    double cu[8][3];              // node velocities of the cached stencil (MD units)
+    // node velocities of the cached stencil (MD units), kept in the storage
+    // precision: FP32 storage carries no more digits than that
+    R cu[8][3];
     double acc[8][3];             // impulse accumulated on the cached stencil (MD units)
     uint32_t cnode[8];
     bool have_acc = false;
     uint32_t hbits = 0;
+    int tcnt = 0;
 
     for (int s = 0; s < bx.substeps; ++s) {
         if (act) {
@@ -297,41 +319,59 @@ __global__ __launch_bounds__(1024) void k_couple(const BoxDev* __restrict__ boxe
             for (int c = 0; c < 3; ++c) {
                 v[c] += f[c] * hdt_m;
                 x[c] += v[c] * dt;
-                xs[3 * b + c] = x[c];
             }
+            if (lane == 0) { xs[3 * b] = x[0]; xs[3 * b + 1] = x[1]; xs[3 * b + 2] = x[2]; }
         }
         bool rebuild = false;
-        if (use_nl && act) {
-            const int cnt = ca.nl_cnt[g];
-            const double dx0 = x[0] - ca.nl_x0[3 * g], dy0 = x[1] - ca.nl_x0[3 * g + 1], dz0 = x[2] - ca.nl_x0[3 * g + 2];
-            rebuild = cnt == -2 || dx0 * dx0 + dy0 * dy0 + dz0 * dz0 > 0.25 * NL_SKIN * NL_SKIN;
+        if (use_nl) {   // uniform over the block: the barrier is taken by all threads or none
+            if (act) {
+                const double dx0 = x[0] - x0n[0], dy0 = x[1] - x0n[1], dz0 = x[2] - x0n[2];
+                rebuild = nl_n == -2 || dx0 * dx0 + dy0 * dy0 + dz0 * dz0 > 0.25 * NL_SKIN * NL_SKIN;
+            }
+            rebuild = __syncthreads_or(rebuild);
+        } else {
+            __syncthreads();
         }
-        rebuild = __syncthreads_or(rebuild);
         if (use_nl && rebuild && act) {
+            ++rebuilds;
             int cnt = 0;
             for (int j = 0; j < N; ++j) {
                 if (j == b) continue;
                 double d0 = x[0] - xs[3 * j], d1 = x[1] - xs[3 * j + 1], d2 = x[2] - xs[3 * j + 2];
-                d0 -= Ld * rint(d0 / Ld); d1 -= Ld * rint(d1 / Ld); d2 -= Ld * rint(d2 / Ld);
+                d0 -= Ld * rint(d0 * iL); d1 -= Ld * rint(d1 * iL); d2 -= Ld * rint(d2 * iL);
                 if (d0 * d0 + d1 * d1 + d2 * d2 < rl2) {
-                    if (cnt < ca.nl_cap) ca.nl_idx[g * ca.nl_cap + cnt] = j;
+                    if (cnt < nl_cap) { nls[cnt * MAXB + b] = (uint16_t)j; ca.nl_idx[g * nl_cap + cnt] = (uint16_t)j; }
                     ++cnt;
                 }
             }
-            ca.nl_cnt[g] = cnt > ca.nl_cap ? -1 : cnt;   // -1: overflow, use the full loop
+            nl_n = cnt > nl_cap ? -1 : cnt;   // -1: overflow, use the full loop
+            ca.nl_cnt[g] = nl_n;
 #pragma unroll
-            for (int c = 0; c < 3; ++c) ca.nl_x0[3 * g + c] = x[c];
+            for (int c = 0; c < 3; ++c) { ca.nl_x0[3 * g + c] = x[c]; x0n[c] = x[c]; }
         }
         if (act) {
-            double F[3];
-            const int cnt = use_nl ? ca.nl_cnt[g] : -1;
-            hbits |= cons_force(bx, b, N, x, xs, cnt, cnt >= 0 ? ca.nl_idx + g * ca.nl_cap : nullptr, F);
+            // repulsive LJ, this lane's share of the partners
+            double W[3] = {0, 0, 0};
+            if (use_nl && nl_n >= 0) {
+                auto jof = [&](int k) { return (int)nls[k * MAXB + b]; };
+                for (int k = 0; k < nl_n; k += 4) wca_add4(x, xs, jof, k, nl_n, 1, b, Ld, iL, bx.rc2, bx.sigsq, eps24, W);
+            } else {
+                auto jof = [](int k) { return k; };
+                for (int j = lane; j < N; j += 4 * T) wca_add4(x, xs, jof, j, N, T, b, Ld, iL, bx.rc2, bx.sigsq, eps24, W);
+            }
+            for (int o = 1; o < T; o <<= 1) {
+#pragma unroll
+                for (int c = 0; c < 3; ++c) W[c] += __shfl_xor(W[c], o, T);
+            }
+            double F[3] = {0, 0, 0};
+            hbits |= fene_force(bx, b, N, x, xs, F);
+            F[0] += W[0]; F[1] += W[1]; F[2] += W[2];
             // stencil of the bead: nodes at integer coordinates, periodic
             int i0[3];
             double fr[3];
 #pragma unroll
             for (int c = 0; c < 3; ++c) {
-                const double xt = x[c] - Ld * floor(x[c] / Ld);
+                const double xt = x[c] - Ld * floor(x[c] * iL);
                 const double fl = floor(xt);
                 fr[c] = xt - fl;
                 int ii = (int)fl;
@@ -340,21 +380,15 @@ __global__ __launch_bounds__(1024) void k_couple(const BoxDev* __restrict__ boxe
                 i0[c] = ii;
             }
             if (i0[0] != cb[0] || i0[1] != cb[1] || i0[2] != cb[2]) {
-                if (have_acc) {
-                    for (int k = 0; k < 8; ++k) {
-                        const double p[3] = {acc[k][0] * bx.tau_lb, acc[k][1] * bx.tau_lb, acc[k][2] * bx.tau_lb};
-                        hbits |= table_add(ca.keys, ca.vals, toff, tcap, cnode[k], p);
-                    }
-                }
+                if (have_acc && lane == 0) hbits |= flush_stencil(ca, bx.node_off, g, cnode, acc, bx.tau_lb, tcnt);
+#pragma unroll
                 for (int k = 0; k < 8; ++k) {
                     const int ix = i0[0] + (k & 1), iy = i0[1] + ((k >> 1) & 1), iz = i0[2] + ((k >> 2) & 1);
-                    const uint32_t rr = (uint32_t)(ix >= L ? ix - L : ix) +
-                                        (uint32_t)L * ((uint32_t)(iy >= L ? iy - L : iy) +
-                                                       (uint32_t)L * (uint32_t)(iz >= L ? iz - L : iz));
-                    cnode[k] = rr;
-                    node_velocity<R>(a, bx.ps, rr, bx.rho0, inv_tau, cu[k]);
+                    cnode[k] = (uint32_t)(ix >= L ? ix - L : ix) +
+                               (uint32_t)L * ((uint32_t)(iy >= L ? iy - L : iy) + (uint32_t)L * (uint32_t)(iz >= L ? iz - L : iz));
                     acc[k][0] = acc[k][1] = acc[k][2] = 0.0;
                 }
+                stencil_velocities<R, R, MAXT <= 256>(a, bx.ps, i0, L, bx.rho0, inv_tau, cu);
                 cb[0] = i0[0]; cb[1] = i0[1]; cb[2] = i0[2];
                 have_acc = true;
             }
@@ -363,7 +397,7 @@ __global__ __launch_bounds__(1024) void k_couple(const BoxDev* __restrict__ boxe
             for (int k = 0; k < 8; ++k) {
                 wt[k] = ((k & 1) ? fr[0] : 1.0 - fr[0]) * (((k >> 1) & 1) ? fr[1] : 1.0 - fr[1]) *
                         (((k >> 2) & 1) ? fr[2] : 1.0 - fr[2]);
-                ub[0] += wt[k] * cu[k][0]; ub[1] += wt[k] * cu[k][1]; ub[2] += wt[k] * cu[k][2];
+                ub[0] += wt[k] * (double)cu[k][0]; ub[1] += wt[k] * (double)cu[k][1]; ub[2] += wt[k] * (double)cu[k][2];
             }
             const U4 w = philox10(U4{(uint32_t)b, t, (1u << 16) | (uint32_t)s, 0u}, bx.seed, bx.box_id);
             const uint32_t ws[3] = {w.x, w.y, w.z};
@@ -384,13 +418,9 @@ __global__ __launch_bounds__(1024) void k_couple(const BoxDev* __restrict__ boxe
         }
         __syncthreads();
     }
-    if (act) {
-        if (have_acc) {
-            for (int k = 0; k < 8; ++k) {
-                const double p[3] = {acc[k][0] * bx.tau_lb, acc[k][1] * bx.tau_lb, acc[k][2] * bx.tau_lb};
-                hbits |= table_add(ca.keys, ca.vals, toff, tcap, cnode[k], p);
-            }
-        }
+    if (writer) {
+        if (have_acc) hbits |= flush_stencil(ca, bx.node_off, g, cnode, acc, bx.tau_lb, tcnt);
+        ca.touched_cnt[g] = tcnt < ca.touch_cap ? tcnt : ca.touch_cap;
 #pragma unroll
         for (int c = 0; c < 3; ++c) {
             ca.x[3 * g + c] = x[c]; ca.v[3 * g + c] = v[c]; ca.f[3 * g + c] = f[c]; ca.fc[3 * g + c] = fcl[c];
@@ -399,8 +429,53 @@ __global__ __launch_bounds__(1024) void k_couple(const BoxDev* __restrict__ boxe
             double* hv = ca.vhist + ((uint64_t)(t % (uint32_t)ca.hist_len) * ca.total_beads + g) * 3;
             hv[0] = v[0]; hv[1] = v[1]; hv[2] = v[2];
         }
-        if (hbits) atomicOr(&ctrl->health, hbits);
     }
+    if (act && hbits) atomicOr(&ctrl->health, hbits);
+    if (b == 0 && lane == 0 && rebuilds) atomicAdd(&ca.nl_rebuilds[bi], (uint32_t)rebuilds);
+}
+
+// ---------------------------------------------------------------- fixup
+// One thread per touched-node slot of the launched beads.  A node touched by
+// several beads is claimed by one thread through a step stamp; that thread
+// takes the node's impulse out of the dense field, collides the node with it
+// and overwrites the node's streamed outputs.
+template <typename R>
+__global__ __launch_bounds__(256) void k_fixup(const BoxDev* __restrict__ boxes,
+                                               const CollideConst<R>* __restrict__ ccs,
+                                               const int32_t* __restrict__ bead_box, uint64_t bead0,
+                                               uint32_t n_entries, ChainArgs ca, uint32_t* __restrict__ claim,
+                                               const R* __restrict__ A, R* __restrict__ B,
+                                               Ctrl* __restrict__ ctrl, uint32_t s_off)
+{
+    const uint32_t e = blockIdx.x * 256u + threadIdx.x;
+    if (e >= n_entries) return;
+    const uint64_t g = bead0 + e / (uint32_t)ca.touch_cap;
+    const int k = (int)(e % (uint32_t)ca.touch_cap);
+    if (k >= ca.touched_cnt[g]) return;
+    const int bi = bead_box[g];
+    const BoxDev& bx = boxes[bi];
+    const uint32_t r = ca.touched[g * ca.touch_cap + k];
+    const uint64_t node = bx.node_off + r;
+    const uint32_t t = ctrl->step + s_off;
+    if (atomicExch(&claim[node], t + 1u) == t + 1u) return;   // another slot took this node
+    const int L = bx.L;
+    const CollideConst<R> cc = ccs[bi];
+    const uint64_t ps = bx.ps;
+    const Upwind up = upwind_of(r, L, bx.inv_L);
+    R d[19];
+    gather_pre<R, false>(A + bx.pop_off, ps, up, d);
+    R fimp[3];
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+        fimp[c] = (R)((double)(long long)ca.imp[3 * node + c] * IMP_INV_SCALE);
+        ca.imp[3 * node + c] = 0ull;
+    }
+    R o[19];
+    const uint32_t h = collide<R>(d, o, fimp[0], fimp[1], fimp[2], cc, r, t, bx.seed, bx.box_id);
+    R* b = B + bx.pop_off + r;
+#pragma unroll
+    for (int i = 0; i < 19; ++i) b[i * ps] = o[i];
+    if (h) atomicOr(&ctrl->health, h);
 }
 
 // --------------------------------------------------------------- advance
@@ -430,11 +505,13 @@ __global__ __launch_bounds__(256) void k_stats(const BoxDev* __restrict__ boxes,
 #pragma unroll
     for (int k = 0; k < NSTAT; ++k) acc[k] = 0.0;
     if (r < V) {
-        const R* a = A + bx.pop_off + r;
+        const Upwind up = upwind_of(r, bx.L, bx.inv_L);
+        R dr[19];
+        gather_pre<R, false>(A + bx.pop_off, bx.ps, up, dr);
         double d[19], m[19];
 #pragma unroll
         for (int i = 0; i < 19; ++i) {
-            d[i] = (double)a[i * bx.ps];
+            d[i] = (double)dr[i];
             if (wv(i) * bx.rho0 + d[i] < 0.0) acc[4] += 1.0;
         }
         to_modes<double>(d, m);
@@ -534,6 +611,12 @@ __global__ __launch_bounds__(256) void k_chain_obs(const BoxDev* __restrict__ bo
 }
 
 // --------------------------------------------------------------- launchers
+static ChainArgs chain_args(const LaunchCtx& c)
+{
+    return ChainArgs{c.x, c.v, c.f, c.fc, c.nl_cnt, c.nl_idx, c.nl_x0, c.nl_cap, c.imp, c.touched,
+                     c.touched_cnt, c.touch_cap, c.nl_rebuilds, c.vhist, c.hist_len, c.total_beads};
+}
+
 template <typename R>
 hipError_t launch_collide(const LaunchCtx& c, const void* A, void* B, int fixed_box, uint32_t tile0,
                           uint32_t n_tiles, uint32_t s_off)
@@ -546,25 +629,28 @@ hipError_t launch_collide(const LaunchCtx& c, const void* A, void* B, int fixed_
 }
 
 template <typename R>
-hipError_t launch_fixup(const LaunchCtx& c, const void* A, void* B, int fixed_box, uint32_t slot0,
-                        uint32_t n_slots, uint32_t s_off)
+hipError_t launch_fixup(const LaunchCtx& c, const void* A, void* B, uint64_t bead0, uint64_t n_beads,
+                        uint32_t s_off)
 {
-    if (n_slots == 0) return hipSuccess;
-    hipLaunchKernelGGL(k_fixup<R>, dim3((n_slots + 255) / 256), dim3(256), 0, c.stream, c.boxes, c.n_boxes,
-                       (const CollideConst<R>*)c.ccs, c.tab_off, slot0, n_slots, fixed_box, c.keys, c.vals,
+    if (n_beads == 0) return hipSuccess;
+    const uint32_t n = (uint32_t)(n_beads * (uint64_t)c.touch_cap);
+    hipLaunchKernelGGL(k_fixup<R>, dim3((n + 255) / 256), dim3(256), 0, c.stream, c.boxes,
+                       (const CollideConst<R>*)c.ccs, c.bead_box, bead0, n, chain_args(c), c.claim,
                        (const R*)A, (R*)B, c.ctrl, s_off);
     return hipGetLastError();
 }
 
 template <typename R>
-hipError_t launch_couple(const LaunchCtx& c, const void* A, const int32_t* list, int n_list, int block,
+hipError_t launch_couple(const LaunchCtx& c, const void* A, const int32_t* list, int n_list, int block, int T,
                          uint32_t s_off)
 {
     if (n_list == 0) return hipSuccess;
-    ChainArgs ca{c.x, c.v, c.f, c.fc, c.nl_cnt, c.nl_idx, c.nl_x0, c.nl_cap, c.keys, c.vals,
-                 c.tab_off, c.tab_cap, c.vhist, c.hist_len, c.total_beads};
-    hipLaunchKernelGGL(k_couple<R>, dim3(n_list), dim3(block), 0, c.stream, c.boxes, list, (const R*)A, ca,
-                       c.ctrl, s_off);
+    if (block <= 256)
+        hipLaunchKernelGGL((k_couple<R, 256>), dim3(n_list), dim3(block), 0, c.stream, c.boxes, list, (const R*)A,
+                           chain_args(c), T, c.ctrl, s_off);
+    else
+        hipLaunchKernelGGL((k_couple<R, 1024>), dim3(n_list), dim3(block), 0, c.stream, c.boxes, list,
+                           (const R*)A, chain_args(c), T, c.ctrl, s_off);
     return hipGetLastError();
 }
 
@@ -592,18 +678,16 @@ hipError_t launch_stats(const LaunchCtx& c, const void* A, uint32_t total_tiles,
 
 hipError_t launch_chain_obs(const LaunchCtx& c, double* out)
 {
-    ChainArgs ca{c.x, c.v, c.f, c.fc, c.nl_cnt, c.nl_idx, c.nl_x0, c.nl_cap, c.keys, c.vals,
-                 c.tab_off, c.tab_cap, c.vhist, c.hist_len, c.total_beads};
-    hipLaunchKernelGGL(k_chain_obs, dim3(c.n_boxes), dim3(256), 0, c.stream, c.boxes, ca, out);
+    hipLaunchKernelGGL(k_chain_obs, dim3(c.n_boxes), dim3(256), 0, c.stream, c.boxes, chain_args(c), out);
     return hipGetLastError();
 }
 
 template hipError_t launch_collide<float>(const LaunchCtx&, const void*, void*, int, uint32_t, uint32_t, uint32_t);
 template hipError_t launch_collide<double>(const LaunchCtx&, const void*, void*, int, uint32_t, uint32_t, uint32_t);
-template hipError_t launch_fixup<float>(const LaunchCtx&, const void*, void*, int, uint32_t, uint32_t, uint32_t);
-template hipError_t launch_fixup<double>(const LaunchCtx&, const void*, void*, int, uint32_t, uint32_t, uint32_t);
-template hipError_t launch_couple<float>(const LaunchCtx&, const void*, const int32_t*, int, int, uint32_t);
-template hipError_t launch_couple<double>(const LaunchCtx&, const void*, const int32_t*, int, int, uint32_t);
+template hipError_t launch_fixup<float>(const LaunchCtx&, const void*, void*, uint64_t, uint64_t, uint32_t);
+template hipError_t launch_fixup<double>(const LaunchCtx&, const void*, void*, uint64_t, uint64_t, uint32_t);
+template hipError_t launch_couple<float>(const LaunchCtx&, const void*, const int32_t*, int, int, int, uint32_t);
+template hipError_t launch_couple<double>(const LaunchCtx&, const void*, const int32_t*, int, int, int, uint32_t);
 template hipError_t launch_stats<float>(const LaunchCtx&, const void*, uint32_t, double*, double*);
 template hipError_t launch_stats<double>(const LaunchCtx&, const void*, uint32_t, double*, double*);
 

@@ -15,12 +15,15 @@ struct LaunchCtx {
     const void* ccs;               // CollideConst<R>[n_boxes]
     const uint32_t* tile_box;      // box index of every collide tile
     Ctrl* ctrl;
-    uint32_t* keys;                // impulse table keys (1 + local node, 0 = empty)
-    unsigned long long* vals;      // impulse table values, 3 per slot, fixed point 2^-48
-    const uint32_t* tab_off;       // first slot of each box's table
-    const uint32_t* tab_cap;       // slots of each box's table (power of two)
+    unsigned long long* imp;       // dense node impulses, 3 per global node, fixed point 2^-52
+    uint32_t* claim;               // per global node: step stamp of the last fix-up
+    uint32_t* touched;             // per bead: touch_cap slots of local node ids
+    int32_t* touched_cnt;          // per bead
+    int touch_cap;                 // touched slots per bead
+    uint32_t* nl_rebuilds;         // per box: neighbour-list builds (diagnostic)
+    const int32_t* bead_box;       // box index of every bead
     double *x, *v, *f, *fc;        // beads [total][3]
-    int32_t* nl_cnt; int32_t* nl_idx; double* nl_x0; int nl_cap;
+    int32_t* nl_cnt; uint16_t* nl_idx; double* nl_x0; int nl_cap;
     double* vhist; int hist_len; uint64_t total_beads;
 };
 
@@ -28,10 +31,10 @@ template <typename R>
 hipError_t launch_collide(const LaunchCtx& c, const void* A, void* B, int fixed_box, uint32_t tile0,
                           uint32_t n_tiles, uint32_t s_off);
 template <typename R>
-hipError_t launch_fixup(const LaunchCtx& c, const void* A, void* B, int fixed_box, uint32_t slot0,
-                        uint32_t n_slots, uint32_t s_off);
+hipError_t launch_fixup(const LaunchCtx& c, const void* A, void* B, uint64_t bead0, uint64_t n_beads,
+                        uint32_t s_off);
 template <typename R>
-hipError_t launch_couple(const LaunchCtx& c, const void* A, const int32_t* list, int n_list, int block,
+hipError_t launch_couple(const LaunchCtx& c, const void* A, const int32_t* list, int n_list, int block, int T,
                          uint32_t s_off);
 hipError_t launch_advance(const LaunchCtx& c, uint32_t n);
 hipError_t launch_init_forces(const LaunchCtx& c, const int32_t* list, int n_list, int block);
@@ -41,5 +44,6 @@ hipError_t launch_chain_obs(const LaunchCtx& c, double* out);
 
 constexpr int NSTAT_REC = 24;
 constexpr int NCHAIN_REC = 11;
+constexpr int NL_SLOTS = 48;
 
 }  // namespace lbd

@@ -33,20 +33,22 @@ uint32_t next_pow2(uint32_t x)
     return p;
 }
 
-constexpr int NL_CAP = 48;      // neighbour-list entries per bead
+constexpr int NL_CAP = NL_SLOTS;   // neighbour-list entries per bead
 constexpr double MODE_B[19] = {1, 1. / 3, 1. / 3, 1. / 3, 2. / 3, 4. / 3, 4. / 9, 1. / 9, 1. / 9, 1. / 9,
                                2. / 3, 2. / 3, 2. / 3, 2. / 9, 2. / 9, 2. / 9, 2, 4. / 3, 4. / 9};
 
 struct Layout {
     size_t esz = 8;
-    std::vector<uint64_t> pop_off, ps, bead_off, V;
-    std::vector<uint32_t> tile_begin, n_tiles, tab_off, tab_cap;
-    uint64_t pop_elems = 0, total_tiles = 0, total_beads = 0, total_slots = 0;
+    std::vector<uint64_t> pop_off, ps, bead_off, V, node_off;
+    std::vector<uint32_t> tile_begin, n_tiles;
+    uint64_t pop_elems = 0, total_tiles = 0, total_beads = 0, total_nodes = 0;
     size_t st_popA = 0, st_popB = 0, st_x = 0, st_v = 0, st_f = 0, st_fc = 0, state_bytes = 0;
-    size_t sc_ctrl = 0, sc_boxes = 0, sc_ccs = 0, sc_tilebox = 0, sc_couple = 0, sc_taboff = 0,
-           sc_tabcap = 0, sc_keys = 0, sc_vals = 0, sc_nlcnt = 0, sc_nlidx = 0, sc_nlx0 = 0,
-           sc_part = 0, sc_stat = 0, sc_chain = 0, sc_vhist = 0, scratch_bytes = 0;
+    size_t sc_ctrl = 0, sc_boxes = 0, sc_ccs = 0, sc_tilebox = 0, sc_couple = 0, sc_imp = 0, sc_claim = 0,
+           sc_touched = 0, sc_tcnt = 0, sc_beadbox = 0, sc_nlcnt = 0, sc_nlidx = 0, sc_nlx0 = 0,
+           sc_part = 0, sc_stat = 0, sc_chain = 0, sc_vhist = 0, sc_nlreb = 0, scratch_bytes = 0;
     int max_N = 0;
+    int couple_T = 1, couple_block = 64;
+    int touch_cap = 8;
 };
 
 bool validate(const lb_box_desc* b, int32_t n, int32_t prec, int32_t hist, std::string& err)
@@ -82,8 +84,10 @@ Layout make_layout(const lb_box_desc* b, int32_t n, int32_t prec, int32_t hist)
     const uint64_t align_el = 256 / Lo.esz;
     uint64_t pad = align_el;
     if (const char* e = std::getenv("LBMD_PLANE_PAD")) pad = round_up(std::strtoull(e, nullptr, 10), align_el);
-    uint64_t pop = 0, tiles = 0, beads = 0;
-    uint32_t slots = 0;
+    uint64_t pop = 0, tiles = 0, beads = 0, nodes = 0;
+    int max_sub = 1;
+    for (int i = 0; i < n; ++i) max_sub = std::max(max_sub, b[i].md_substeps);
+    Lo.touch_cap = 8 * (max_sub + 1);
     for (int i = 0; i < n; ++i) {
         const uint64_t V = (uint64_t)b[i].L * b[i].L * b[i].L;
         const uint64_t ps = round_up(V, align_el) + pad;
@@ -96,16 +100,22 @@ Layout make_layout(const lb_box_desc* b, int32_t n, int32_t prec, int32_t hist)
         tiles += (V + 255) / 256;
         Lo.bead_off.push_back(beads);
         beads += b[i].n_beads;
-        const uint32_t cap = b[i].n_beads > 0 ? next_pow2(std::max<uint32_t>(64u, 32u * (uint32_t)b[i].n_beads)) : 0u;
-        Lo.tab_off.push_back(slots);
-        Lo.tab_cap.push_back(cap);
-        slots += cap;
+        Lo.node_off.push_back(nodes);
+        nodes += V;
         Lo.max_N = std::max(Lo.max_N, b[i].n_beads);
     }
     Lo.pop_elems = pop;
     Lo.total_tiles = tiles;
     Lo.total_beads = beads;
-    Lo.total_slots = slots;
+    Lo.total_nodes = nodes;
+    // lanes per bead in the coupling workgroup: split the pair loop while the
+    // chain is small, one lane per bead (up to 1024) otherwise
+    if (Lo.max_N > 0) {
+        int T = 1;
+        while (T < 16 && 2 * T * Lo.max_N <= 256) T *= 2;
+        Lo.couple_T = T;
+        Lo.couple_block = (int)round_up((uint64_t)T * Lo.max_N, 64);
+    }
     size_t o = 0;
     Lo.st_popA = o; o = align256(o + pop * Lo.esz);
     Lo.st_popB = o; o = align256(o + pop * Lo.esz);
@@ -122,17 +132,21 @@ Layout make_layout(const lb_box_desc* b, int32_t n, int32_t prec, int32_t hist)
     Lo.sc_ccs = o; o = align256(o + n * ccsz);
     Lo.sc_tilebox = o; o = align256(o + tiles * sizeof(uint32_t));
     Lo.sc_couple = o; o = align256(o + n * sizeof(int32_t));
-    Lo.sc_taboff = o; o = align256(o + n * sizeof(uint32_t));
-    Lo.sc_tabcap = o; o = align256(o + n * sizeof(uint32_t));
-    Lo.sc_keys = o; o = align256(o + std::max<uint64_t>(slots, 1) * sizeof(uint32_t));
-    Lo.sc_vals = o; o = align256(o + std::max<uint64_t>(slots, 1) * 3 * sizeof(unsigned long long));
-    Lo.sc_nlcnt = o; o = align256(o + std::max<uint64_t>(beads, 1) * sizeof(int32_t));
-    Lo.sc_nlidx = o; o = align256(o + std::max<uint64_t>(beads, 1) * NL_CAP * sizeof(int32_t));
+    const uint64_t impn = beads ? nodes : 1;   // the impulse field exists only when there are beads
+    Lo.sc_imp = o; o = align256(o + impn * 3 * sizeof(unsigned long long));
+    Lo.sc_claim = o; o = align256(o + impn * sizeof(uint32_t));
+    const uint64_t nbx = std::max<uint64_t>(beads, 1);
+    Lo.sc_touched = o; o = align256(o + nbx * Lo.touch_cap * sizeof(uint32_t));
+    Lo.sc_tcnt = o; o = align256(o + nbx * sizeof(int32_t));
+    Lo.sc_beadbox = o; o = align256(o + nbx * sizeof(int32_t));
+    Lo.sc_nlcnt = o; o = align256(o + nbx * sizeof(int32_t));
+    Lo.sc_nlidx = o; o = align256(o + nbx * NL_CAP * sizeof(uint16_t));
     Lo.sc_nlx0 = o; o = align256(o + std::max<uint64_t>(beads, 1) * 3 * sizeof(double));
     Lo.sc_part = o; o = align256(o + tiles * NSTAT_REC * sizeof(double));
     Lo.sc_stat = o; o = align256(o + n * NSTAT_REC * sizeof(double));
     Lo.sc_chain = o; o = align256(o + n * NCHAIN_REC * sizeof(double));
     Lo.sc_vhist = o; o = align256(o + (size_t)hist * std::max<uint64_t>(beads, 1) * 3 * sizeof(double));
+    Lo.sc_nlreb = o; o = align256(o + n * sizeof(uint32_t));
     Lo.scratch_bytes = o;
     return Lo;
 }
@@ -167,10 +181,14 @@ struct lb_handle {
     char* scratch = nullptr;
     hipStream_t stream = nullptr;
     bool own_stream = false;
+    // the chain coupling runs on a second stream, concurrently with the
+    // collide kernel of the same step (both only read the current state)
+    hipStream_t stream2 = nullptr;
+    hipEvent_t ev_fork = nullptr, ev_join = nullptr;
     LaunchCtx ctx{};
+    LaunchCtx ctx2{};
     int32_t* couple_list = nullptr;   // device
     std::vector<int32_t> couple_host; // box indices with beads
-    int couple_block = 64;
     int cur = 0;                      // 0: buffer A holds the current state
     uint64_t step = 0;                // host mirror of the device step counter
     bool pending = false;             // lb_couple done, impulses not yet consumed
@@ -207,26 +225,34 @@ lb_status enqueue_step(lb_handle* h, int from, uint32_t s_off, bool couple)
     const LaunchCtx& c = h->ctx;
     const int nc = (int)h->couple_host.size();
     if (h->batched) {
-        if (couple && nc)
-            HIPCHK(h, f64 ? launch_couple<double>(c, A, h->couple_list, nc, h->couple_block, s_off)
-                          : launch_couple<float>(c, A, h->couple_list, nc, h->couple_block, s_off));
+        const bool fork = couple && nc;
+        if (fork) {
+            HIPCHK(h, hipEventRecord(h->ev_fork, h->stream));
+            HIPCHK(h, hipStreamWaitEvent(h->stream2, h->ev_fork, 0));
+            const LaunchCtx& c2 = h->ctx2;
+            HIPCHK(h, f64 ? launch_couple<double>(c2, A, h->couple_list, nc, h->lo.couple_block, h->lo.couple_T, s_off)
+                          : launch_couple<float>(c2, A, h->couple_list, nc, h->lo.couple_block, h->lo.couple_T, s_off));
+            HIPCHK(h, hipEventRecord(h->ev_join, h->stream2));
+        }
         HIPCHK(h, f64 ? launch_collide<double>(c, A, B, -1, 0, (uint32_t)h->lo.total_tiles, s_off)
                       : launch_collide<float>(c, A, B, -1, 0, (uint32_t)h->lo.total_tiles, s_off));
-        if (h->lo.total_slots)
-            HIPCHK(h, f64 ? launch_fixup<double>(c, A, B, -1, 0, (uint32_t)h->lo.total_slots, s_off)
-                          : launch_fixup<float>(c, A, B, -1, 0, (uint32_t)h->lo.total_slots, s_off));
+        if (fork) HIPCHK(h, hipStreamWaitEvent(h->stream, h->ev_join, 0));
+        if (h->lo.total_beads)
+            HIPCHK(h, f64 ? launch_fixup<double>(c, A, B, 0, h->lo.total_beads, s_off)
+                          : launch_fixup<float>(c, A, B, 0, h->lo.total_beads, s_off));
     } else {
         for (int i = 0; i < nc; ++i) {
             if (!couple) break;
-            HIPCHK(h, f64 ? launch_couple<double>(c, A, h->couple_list + i, 1, h->couple_block, s_off)
-                          : launch_couple<float>(c, A, h->couple_list + i, 1, h->couple_block, s_off));
+            HIPCHK(h, f64 ? launch_couple<double>(c, A, h->couple_list + i, 1, h->lo.couple_block, h->lo.couple_T, s_off)
+                          : launch_couple<float>(c, A, h->couple_list + i, 1, h->lo.couple_block, h->lo.couple_T, s_off));
         }
         for (int b = 0; b < h->n_boxes; ++b) {
             HIPCHK(h, f64 ? launch_collide<double>(c, A, B, b, h->lo.tile_begin[b], h->lo.n_tiles[b], s_off)
                           : launch_collide<float>(c, A, B, b, h->lo.tile_begin[b], h->lo.n_tiles[b], s_off));
-            if (h->lo.tab_cap[b])
-                HIPCHK(h, f64 ? launch_fixup<double>(c, A, B, b, h->lo.tab_off[b], h->lo.tab_cap[b], s_off)
-                              : launch_fixup<float>(c, A, B, b, h->lo.tab_off[b], h->lo.tab_cap[b], s_off));
+            const uint64_t nb = (uint64_t)h->desc[b].n_beads;
+            if (nb)
+                HIPCHK(h, f64 ? launch_fixup<double>(c, A, B, h->lo.bead_off[b], nb, s_off)
+                              : launch_fixup<float>(c, A, B, h->lo.bead_off[b], nb, s_off));
         }
     }
     return LB_OK;
@@ -320,7 +346,7 @@ lb_status lb_init(const lb_box_desc* boxes, int32_t n_boxes, int32_t precision, 
         BoxDev& b = bd[i];
         std::memset(&b, 0, sizeof b);
         b.L = d.L; b.N = d.n_beads; b.seed = d.seed; b.box_id = d.box_id;
-        b.node_off = 0; b.pop_off = lo.pop_off[i]; b.ps = lo.ps[i]; b.bead_off = lo.bead_off[i];
+        b.node_off = lo.node_off[i]; b.pop_off = lo.pop_off[i]; b.ps = lo.ps[i]; b.bead_off = lo.bead_off[i];
         b.tile_begin = lo.tile_begin[i]; b.n_tiles = lo.n_tiles[i];
         b.therm = d.thermalize; b.substeps = d.md_substeps;
         b.rho0 = d.rho0; b.gam_b = 1 - d.omega_bulk; b.gam_s = 1 - d.omega_shear; b.gam_g = 1 - d.omega_ghost;
@@ -330,14 +356,17 @@ lb_status lb_init(const lb_box_desc* boxes, int32_t n_boxes, int32_t precision, 
         b.rc2 = std::pow(2.0, 1.0 / 3.0) * b.sigsq;
         b.bead_noise = std::sqrt(2.0 * d.kT * d.zeta / d.md_dt);
         b.inv_L = 1.0 / d.L;
+        b.inv_r0sq = 1.0 / b.r0sq;
     }
     std::vector<uint32_t> tile_box(lo.total_tiles);
     for (int i = 0; i < n_boxes; ++i)
         for (uint32_t t = 0; t < lo.n_tiles[i]; ++t) tile_box[lo.tile_begin[i] + t] = (uint32_t)i;
     for (int i = 0; i < n_boxes; ++i)
         if (boxes[i].n_beads > 0) h->couple_host.push_back(i);
-    h->couple_block = std::max(64, (lo.max_N + 63) / 64 * 64);
     std::vector<int32_t> nlcnt(std::max<uint64_t>(nb, 1), -2);
+    std::vector<int32_t> bead_box(std::max<uint64_t>(nb, 1), 0);
+    for (int i = 0; i < n_boxes; ++i)
+        for (int k = 0; k < boxes[i].n_beads; ++k) bead_box[lo.bead_off[i] + k] = i;
 
     auto up = [&](size_t off, const void* src, size_t bytes) {
         return bytes ? hipMemcpy(h->scratch + off, src, bytes, hipMemcpyHostToDevice) : hipSuccess;
@@ -359,8 +388,7 @@ lb_status lb_init(const lb_box_desc* boxes, int32_t n_boxes, int32_t precision, 
     }
     chk(up(lo.sc_tilebox, tile_box.data(), tile_box.size() * sizeof(uint32_t)));
     chk(up(lo.sc_couple, h->couple_host.data(), h->couple_host.size() * sizeof(int32_t)));
-    chk(up(lo.sc_taboff, lo.tab_off.data(), n_boxes * sizeof(uint32_t)));
-    chk(up(lo.sc_tabcap, lo.tab_cap.data(), n_boxes * sizeof(uint32_t)));
+    chk(up(lo.sc_beadbox, bead_box.data(), bead_box.size() * sizeof(int32_t)));
     chk(up(lo.sc_nlcnt, nlcnt.data(), nlcnt.size() * sizeof(int32_t)));
     if (nb) chk(hipMemcpy(stp(lo.st_x), bead_x0, nb * 3 * sizeof(double), hipMemcpyHostToDevice));
     if (e != hipSuccess) {
@@ -376,19 +404,33 @@ lb_status lb_init(const lb_box_desc* boxes, int32_t n_boxes, int32_t precision, 
     c.ccs = sc(lo.sc_ccs);
     c.tile_box = (const uint32_t*)sc(lo.sc_tilebox);
     c.ctrl = (Ctrl*)sc(lo.sc_ctrl);
-    c.keys = (uint32_t*)sc(lo.sc_keys);
-    c.vals = (unsigned long long*)sc(lo.sc_vals);
-    c.tab_off = (const uint32_t*)sc(lo.sc_taboff);
-    c.tab_cap = (const uint32_t*)sc(lo.sc_tabcap);
+    c.imp = (unsigned long long*)sc(lo.sc_imp);
+    c.claim = (uint32_t*)sc(lo.sc_claim);
+    c.touched = (uint32_t*)sc(lo.sc_touched);
+    c.touched_cnt = (int32_t*)sc(lo.sc_tcnt);
+    c.touch_cap = lo.touch_cap;
+    c.nl_rebuilds = (uint32_t*)sc(lo.sc_nlreb);
+    c.bead_box = (const int32_t*)sc(lo.sc_beadbox);
     c.x = (double*)stp(lo.st_x); c.v = (double*)stp(lo.st_v); c.f = (double*)stp(lo.st_f); c.fc = (double*)stp(lo.st_fc);
-    c.nl_cnt = (int32_t*)sc(lo.sc_nlcnt); c.nl_idx = (int32_t*)sc(lo.sc_nlidx); c.nl_x0 = (double*)sc(lo.sc_nlx0);
+    c.nl_cnt = (int32_t*)sc(lo.sc_nlcnt); c.nl_idx = (uint16_t*)sc(lo.sc_nlidx); c.nl_x0 = (double*)sc(lo.sc_nlx0);
     c.nl_cap = NL_CAP;
     c.vhist = hist_steps > 0 ? (double*)sc(lo.sc_vhist) : nullptr;
     c.hist_len = hist_steps > 0 ? hist_steps : 1;
     c.total_beads = nb;
     h->couple_list = (int32_t*)sc(lo.sc_couple);
+    e = hipStreamCreateWithFlags(&h->stream2, hipStreamNonBlocking);
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&h->ev_fork, hipEventDisableTiming);
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&h->ev_join, hipEventDisableTiming);
+    if (e != hipSuccess) {
+        std::string msg = std::string("second stream: ") + hipGetErrorString(e);
+        lb_free(h);
+        return fail(nullptr, LB_EDEVICE, msg);
+    }
+    h->ctx2 = c;
+    h->ctx2.stream = h->stream2;
 
-    e = launch_init_forces(c, h->couple_list, (int)h->couple_host.size(), h->couple_block);
+    e = launch_init_forces(c, h->couple_list, (int)h->couple_host.size(),
+                           std::max(64, (int)round_up((uint64_t)lo.max_N, 64)));
     if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
     if (e != hipSuccess) {
         std::string msg = std::string("initial forces: ") + hipGetErrorString(e);
@@ -408,9 +450,9 @@ lb_status lb_couple(lb_handle* h)
         const LaunchCtx& c = h->ctx;
         const int nc = (int)h->couple_host.size();
         if (h->prec == LB_FP64)
-            HIPCHK(h, launch_couple<double>(c, A, h->couple_list, nc, h->couple_block, 0));
+            HIPCHK(h, launch_couple<double>(c, A, h->couple_list, nc, h->lo.couple_block, h->lo.couple_T, 0));
         else
-            HIPCHK(h, launch_couple<float>(c, A, h->couple_list, nc, h->couple_block, 0));
+            HIPCHK(h, launch_couple<float>(c, A, h->couple_list, nc, h->lo.couple_block, h->lo.couple_T, 0));
     }
     h->pending = true;
     return LB_OK;
@@ -467,7 +509,9 @@ lb_status lb_observables(lb_handle* h, lb_obs* out)
         HIPCHK(h, launch_stats<float>(h->ctx, A, (uint32_t)lo.total_tiles, part, stat));
     HIPCHK(h, launch_chain_obs(h->ctx, chain));
     std::vector<double> st(h->n_boxes * NSTAT_REC), ch(h->n_boxes * NCHAIN_REC);
+    std::vector<uint32_t> reb(h->n_boxes);
     Ctrl ctrl;
+    HIPCHK(h, hipMemcpyAsync(reb.data(), h->scratch + lo.sc_nlreb, reb.size() * sizeof(uint32_t), hipMemcpyDeviceToHost, h->stream));
     HIPCHK(h, hipMemcpyAsync(st.data(), stat, st.size() * sizeof(double), hipMemcpyDeviceToHost, h->stream));
     HIPCHK(h, hipMemcpyAsync(ch.data(), chain, ch.size() * sizeof(double), hipMemcpyDeviceToHost, h->stream));
     HIPCHK(h, hipMemcpyAsync(&ctrl, h->scratch + lo.sc_ctrl, sizeof ctrl, hipMemcpyDeviceToHost, h->stream));
@@ -491,6 +535,7 @@ lb_status lb_observables(lb_handle* h, lb_obs* out)
         o.neg_count = s[4];
         for (int k = 0; k < 19; ++k) o.mode_sq[k] = s[5 + k];
         o.health = ctrl.health;
+        o.nlist_builds = reb[i];
         o.step = ctrl.step;
     }
     if (ctrl.health) return fail(h, LB_ENUMERIC, "device health flags set: " + std::to_string(ctrl.health));
@@ -522,11 +567,20 @@ lb_status lb_export_state(lb_handle* h, void* host_buf, size_t bytes)
         const uint64_t V = lo.V[i];
         double* n = (double*)o;
         std::vector<char> raw(V * lo.esz);
+        const int L = h->desc[i].L;
         for (int q = 0; q < 19; ++q) {
             HIPCHK(h, hipMemcpy(raw.data(), P + (lo.pop_off[i] + q * lo.ps[i]) * lo.esz, V * lo.esz, hipMemcpyDeviceToHost));
             const double base = wv(q) * h->desc[i].rho0;
-            if (lo.esz == 8) { const double* r = (const double*)raw.data(); for (uint64_t k = 0; k < V; ++k) n[q * V + k] = base + r[k]; }
-            else { const float* r = (const float*)raw.data(); for (uint64_t k = 0; k < V; ++k) n[q * V + k] = base + (double)r[k]; }
+            // stored p_q(s) is the population that arrives at s + c_q
+            for (int z = 0; z < L; ++z)
+                for (int y = 0; y < L; ++y)
+                    for (int x = 0; x < L; ++x) {
+                        const uint64_t s = x + (uint64_t)L * (y + (uint64_t)L * z);
+                        const int xd = (x + cxv(q) + L) % L, yd = (y + cyv(q) + L) % L, zd = (z + czv(q) + L) % L;
+                        const uint64_t dd = xd + (uint64_t)L * (yd + (uint64_t)L * zd);
+                        const double dv = lo.esz == 8 ? ((const double*)raw.data())[s] : (double)((const float*)raw.data())[s];
+                        n[q * V + dd] = base + dv;
+                    }
         }
         o += 19 * V * sizeof(double);
         const size_t nbb = (size_t)h->desc[i].n_beads * 3 * sizeof(double);
@@ -556,10 +610,18 @@ lb_status lb_import_state(lb_handle* h, const void* host_buf, size_t bytes)
         const uint64_t V = lo.V[i];
         const double* n = (const double*)o;
         std::vector<char> raw(V * lo.esz);
+        const int L = h->desc[i].L;
         for (int q = 0; q < 19; ++q) {
             const double base = wv(q) * h->desc[i].rho0;
-            if (lo.esz == 8) { double* r = (double*)raw.data(); for (uint64_t k = 0; k < V; ++k) r[k] = n[q * V + k] - base; }
-            else { float* r = (float*)raw.data(); for (uint64_t k = 0; k < V; ++k) r[k] = (float)(n[q * V + k] - base); }
+            for (int z = 0; z < L; ++z)
+                for (int y = 0; y < L; ++y)
+                    for (int x = 0; x < L; ++x) {
+                        const uint64_t s = x + (uint64_t)L * (y + (uint64_t)L * z);
+                        const int xd = (x + cxv(q) + L) % L, yd = (y + cyv(q) + L) % L, zd = (z + czv(q) + L) % L;
+                        const double dv = n[q * V + xd + (uint64_t)L * (yd + (uint64_t)L * zd)] - base;
+                        if (lo.esz == 8) ((double*)raw.data())[s] = dv;
+                        else ((float*)raw.data())[s] = (float)dv;
+                    }
             HIPCHK(h, hipMemcpy(P + (lo.pop_off[i] + q * lo.ps[i]) * lo.esz, raw.data(), V * lo.esz, hipMemcpyHostToDevice));
         }
         o += 19 * V * sizeof(double);
@@ -576,6 +638,8 @@ lb_status lb_import_state(lb_handle* h, const void* host_buf, size_t bytes)
     HIPCHK(h, hipMemcpy(h->scratch + lo.sc_ctrl, &ctrl, sizeof ctrl, hipMemcpyHostToDevice));
     std::vector<int32_t> nlcnt(std::max<uint64_t>(lo.total_beads, 1), -2);
     HIPCHK(h, hipMemcpy(h->scratch + lo.sc_nlcnt, nlcnt.data(), nlcnt.size() * sizeof(int32_t), hipMemcpyHostToDevice));
+    // fix-up claims are step stamps: a restored step count must not meet stale ones
+    if (lo.total_beads) HIPCHK(h, hipMemset(h->scratch + lo.sc_claim, 0, lo.total_nodes * sizeof(uint32_t)));
     h->step = stepv;
     return LB_OK;
 }
@@ -588,22 +652,17 @@ lb_status lb_pending_impulse(lb_handle* h, double* host_dense, size_t bytes)
     for (int i = 0; i < h->n_boxes; ++i) need += 3 * lo.V[i] * sizeof(double);
     if (bytes < need) return fail(h, LB_ENOMEM, "host buffer too small");
     std::memset(host_dense, 0, need);
-    if (!lo.total_slots) return LB_OK;
-    std::vector<uint32_t> keys(lo.total_slots);
-    std::vector<unsigned long long> vals(3 * lo.total_slots);
+    if (!lo.total_beads) return LB_OK;
     HIPCHK(h, hipStreamSynchronize(h->stream));
-    HIPCHK(h, hipMemcpy(keys.data(), h->scratch + lo.sc_keys, keys.size() * 4, hipMemcpyDeviceToHost));
-    HIPCHK(h, hipMemcpy(vals.data(), h->scratch + lo.sc_vals, vals.size() * 8, hipMemcpyDeviceToHost));
     size_t base = 0;
     for (int i = 0; i < h->n_boxes; ++i) {
-        for (uint32_t s = 0; s < lo.tab_cap[i]; ++s) {
-            const uint32_t slot = lo.tab_off[i] + s;
-            if (!keys[slot]) continue;
-            const uint64_t r = keys[slot] - 1;
-            for (int c = 0; c < 3; ++c)
-                host_dense[base + c * lo.V[i] + r] = (double)(long long)vals[3 * (size_t)slot + c] * IMP_INV_SCALE;
-        }
-        base += 3 * lo.V[i];
+        const uint64_t V = lo.V[i];
+        std::vector<unsigned long long> q(3 * V);
+        HIPCHK(h, hipMemcpy(q.data(), h->scratch + lo.sc_imp + 3 * lo.node_off[i] * sizeof(unsigned long long),
+                            q.size() * sizeof(unsigned long long), hipMemcpyDeviceToHost));
+        for (uint64_t r = 0; r < V; ++r)
+            for (int c = 0; c < 3; ++c) host_dense[base + c * V + r] = (double)(long long)q[3 * r + c] * IMP_INV_SCALE;
+        base += 3 * V;
     }
     return LB_OK;
 }
@@ -655,7 +714,11 @@ void lb_free(lb_handle* h)
 {
     if (!h) return;
     if (h->stream) (void)hipStreamSynchronize(h->stream);
+    if (h->stream2) (void)hipStreamSynchronize(h->stream2);
     drop_graphs(h);
+    if (h->ev_fork) (void)hipEventDestroy(h->ev_fork);
+    if (h->ev_join) (void)hipEventDestroy(h->ev_join);
+    if (h->stream2) (void)hipStreamDestroy(h->stream2);
     if (h->own_stream && h->stream) (void)hipStreamDestroy(h->stream);
     delete h;
 }

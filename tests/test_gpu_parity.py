@@ -100,7 +100,9 @@ def test_plain16_fp64_full_run(orc):
     # the oracle stores full populations and its FP64 mass drifts by round-off
     # (~3e-13 relative over 4M node updates); the GPU stores deviations
     assert og["mass"] == pytest.approx(oo[0], rel=1e-12)
-    np.testing.assert_allclose(og["p_total"], oo[10:13], atol=1e-12)
+    # each node impulse is rounded to 2^-52 lattice units when spread: the
+    # invariant then holds to ~1e-13 over 1000 steps instead of exactly
+    np.testing.assert_allclose(og["p_total"], oo[10:13], atol=1e-11)
     assert og["rg2"] == pytest.approx(oo[16], rel=1e-10)
     assert og["re2"] == pytest.approx(oo[17], rel=1e-10)
     np.testing.assert_allclose(og["com"], oo[13:16], rtol=1e-12)
