@@ -119,7 +119,7 @@ def main():
     ap.add_argument("--workload", default="prec256", choices=["prec256", "single64", "plain16"])
     ap.add_argument("--no-secondary", action="store_true")
     ap.add_argument("--no-cpu", action="store_true")
-    ap.add_argument("--graph-steps", type=int, default=0)
+    ap.add_argument("--graph-steps", type=int, default=20)
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py runs on one GPU only: the path is built and measured for a single MI355X; "
@@ -178,11 +178,15 @@ def main():
     if not args.no_secondary:
         sec = {}
         s64, b64, n64, p64 = make_system("single64")
+        if args.graph_steps:
+            s64.set_launch(batched=True, graph_steps=args.graph_steps)
         t64, _ = time_steps(s64, 2000, 50)
         sec["single64"] = {"mlups": round(n64 * 2000 / t64 / 1e6, 1), "ms_per_step": round(1e3 * t64 / 2000, 4),
                            "collide_us": round(1e6 * time_collide(s64, 200), 2)}
         s64.close()
         sb, bb, nb, pb = make_system("batched256")
+        if args.graph_steps:
+            sb.set_launch(batched=True, graph_steps=args.graph_steps)
         tb, _ = time_steps(sb, 500, 20)
         sb.set_launch(batched=False)
         tp, _ = time_steps(sb, 100, 5)

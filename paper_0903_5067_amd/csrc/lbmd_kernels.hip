@@ -65,8 +65,11 @@ __device__ __forceinline__ Upwind upwind_of(uint32_t r, int L, double inv_L)
 }
 
 // -------------------------------------------------------------- collide
+// At most 7 of the 8 wave slots per SIMD: the slot left free lets the short
+// chain kernels running beside this one start at once instead of queueing
+// behind the collide grid.
 template <typename R>
-__global__ __launch_bounds__(256) void k_collide(const BoxDev* __restrict__ boxes,
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 7))) void k_collide(const BoxDev* __restrict__ boxes,
                                                  const CollideConst<R>* __restrict__ ccs,
                                                  const uint32_t* __restrict__ tile_box,
                                                  int fixed_box, uint32_t tile0,
@@ -262,14 +265,15 @@ __device__ __forceinline__ uint32_t flush_stencil(const ChainArgs& ca, uint64_t 
 // 0..T*Npad-1: bead b = tid / T, lane = tid % T.  All T lanes of a bead
 // compute the same bead update (their force partial sums are combined by a
 // butterfly, which gives every lane the same bits); lane 0 writes.
-template <typename R, int MAXT>
+template <typename R, int MAXT = 256>
 __global__ __launch_bounds__(MAXT) void k_couple(const BoxDev* __restrict__ boxes,
                                                  const int32_t* __restrict__ couple_list,
                                                  const R* __restrict__ A, ChainArgs ca, int T,
                                                  Ctrl* __restrict__ ctrl, uint32_t s_off)
 {
     __shared__ double xs[3 * MAXB];
-    __shared__ uint16_t nls[MAXT == 1024 ? MAXB * NL_SLOTS : 1];
+    __shared__ uint16_t nls[1];   // neighbour lists are used on the multi-workgroup path only
+    __builtin_amdgcn_s_setprio(3);   // latency-bound chain beside the bandwidth-bound collide
     const int bi = couple_list[blockIdx.x];
     const BoxDev& bx = boxes[bi];
     const int N = bx.N;
@@ -284,7 +288,7 @@ __global__ __launch_bounds__(MAXT) void k_couple(const BoxDev* __restrict__ boxe
     const double inv_tau = 1.0 / bx.tau_lb;
     const double eps24 = 24.0 * bx.eps;
     const R* a = A + bx.pop_off;
-    const bool use_nl = MAXT == 1024 && T == 1 && N > 128;
+    const bool use_nl = false;   // chains on this path have at most 256 beads
     const double rl = sqrt(bx.rc2) + NL_SKIN;
     const double rl2 = rl * rl;
     const int nl_cap = ca.nl_cap;
@@ -388,7 +392,7 @@ __global__ __launch_bounds__(MAXT) void k_couple(const BoxDev* __restrict__ boxe
                                (uint32_t)L * ((uint32_t)(iy >= L ? iy - L : iy) + (uint32_t)L * (uint32_t)(iz >= L ? iz - L : iz));
                     acc[k][0] = acc[k][1] = acc[k][2] = 0.0;
                 }
-                stencil_velocities<R, R, MAXT <= 256>(a, bx.ps, i0, L, bx.rho0, inv_tau, cu);
+                stencil_velocities<R, R, true>(a, bx.ps, i0, L, bx.rho0, inv_tau, cu);
                 cb[0] = i0[0]; cb[1] = i0[1]; cb[2] = i0[2];
                 have_acc = true;
             }
@@ -432,6 +436,229 @@ __global__ __launch_bounds__(MAXT) void k_couple(const BoxDev* __restrict__ boxe
     }
     if (act && hbits) atomicOr(&ctrl->health, hbits);
     if (b == 0 && lane == 0 && rebuilds) atomicAdd(&ca.nl_rebuilds[bi], (uint32_t)rebuilds);
+}
+
+// ------------------------------------------------- couple, large chains
+// Chains above 256 beads are spread over workgroups of 64 beads, one launch
+// per MD substep (graph nodes), so a chain of 1024 beads uses 16 CUs instead
+// of one.  Between launches each bead's cached stencil (base cell, node
+// velocities, accumulated impulse) lives in global memory, and positions are
+// double-buffered: substep s reads xb[s&1] for the forces and writes the
+// drifted positions of substep s+1 into xb[(s+1)&1].
+struct BigArgs {
+    const int2* blocks;        // (box, first bead of the block within the box)
+    double* xb;                // [2][total beads][3]
+    int32_t* cb;               // [total beads][4]: base cell x,y,z; touched count
+    double* cu;                // [total beads][8][3] node velocities (MD units)
+    double* acc;               // [total beads][8][3] accumulated impulse (MD units)
+    uint32_t* nl_req;          // per box: global substep id that must rebuild the list
+};
+
+// first half kick and drift of substep 0; resets the per-step stencil cache
+// Workgroups are handed to the 8 XCDs round-robin by block index; the chain
+// kernels launch XCD_SPREAD blocks per working block and let only every
+// XCD_SPREAD-th one work, so a chain's blocks share one XCD's L2 and the
+// positions and stencil caches exchanged between substeps stay there.
+constexpr int XCD_SPREAD = 8;
+
+__global__ __launch_bounds__(64) void k_chain_drift(const BoxDev* __restrict__ boxes, ChainArgs ca, BigArgs ba)
+{
+    if (blockIdx.x % XCD_SPREAD) return;
+    __builtin_amdgcn_s_setprio(3);
+    const int2 blk = ba.blocks[blockIdx.x / XCD_SPREAD];
+    const BoxDev& bx = boxes[blk.x];
+    const int b = blk.y + (int)threadIdx.x;
+    if (b >= bx.N) return;
+    const uint64_t g = bx.bead_off + b;
+    const double dt = bx.dt, hdt_m = 0.5 * dt / bx.mass;
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+        const double v = ca.v[3 * g + c] + ca.f[3 * g + c] * hdt_m;
+        ca.v[3 * g + c] = v;
+        ba.xb[3 * g + c] = ca.x[3 * g + c] + v * dt;
+    }
+    ba.cb[4 * g] = -1; ba.cb[4 * g + 1] = -1; ba.cb[4 * g + 2] = -1; ba.cb[4 * g + 3] = 0;
+}
+
+template <typename R>
+__global__ __launch_bounds__(64) void k_chain_sub(const BoxDev* __restrict__ boxes, const R* __restrict__ A,
+                                                  ChainArgs ca, BigArgs ba, int s, Ctrl* __restrict__ ctrl,
+                                                  uint32_t s_off)
+{
+    __shared__ double xs[3 * MAXB];
+    if (blockIdx.x % XCD_SPREAD) return;
+    // the chain is a serial chain of short launches running beside the
+    // bandwidth-bound collide kernel: its waves take issue priority
+    __builtin_amdgcn_s_setprio(3);
+    const int2 blk = ba.blocks[blockIdx.x / XCD_SPREAD];
+    const int bi = blk.x;
+    const BoxDev& bx = boxes[bi];
+    const int N = bx.N;
+    const int b = blk.y + (int)threadIdx.x;
+    const bool act = b < N;
+    const uint64_t g = bx.bead_off + (uint64_t)(act ? b : 0);
+    const uint32_t t = ctrl->step + s_off;
+    const int S = bx.substeps;
+    if (s >= S) return;   // boxes with fewer substeps are done
+    const uint64_t tb = ca.total_beads;
+    const double* xcur = ba.xb + (uint64_t)(s & 1) * 3 * tb + 3 * bx.bead_off;
+    for (int k = threadIdx.x; k < 3 * N; k += 64) xs[k] = xcur[k];
+    __syncthreads();
+    if (!act) return;
+    const int L = bx.L;
+    const double Ld = (double)L, iL = bx.inv_L;
+    const double dt = bx.dt, hdt_m = 0.5 * dt / bx.mass, inv_tau = 1.0 / bx.tau_lb, eps24 = 24.0 * bx.eps;
+    double x[3] = {xs[3 * b], xs[3 * b + 1], xs[3 * b + 2]};
+    double v[3] = {ca.v[3 * g], ca.v[3 * g + 1], ca.v[3 * g + 2]};
+    uint32_t hbits = 0;
+
+    // neighbour list: rebuilt in the substep a previous substep asked for
+    const uint32_t sigma = t * (uint32_t)S + (uint32_t)s + 1u;   // global substep id, never 0
+    int nl_n = ca.nl_cnt[g];
+    const double rl = sqrt(bx.rc2) + NL_SKIN;
+    if (nl_n == -2 || ba.nl_req[bi] == sigma) {
+        int cnt = 0;
+        for (int j = 0; j < N; ++j) {
+            if (j == b) continue;
+            double d0 = x[0] - xs[3 * j], d1 = x[1] - xs[3 * j + 1], d2 = x[2] - xs[3 * j + 2];
+            d0 -= Ld * rint(d0 * iL); d1 -= Ld * rint(d1 * iL); d2 -= Ld * rint(d2 * iL);
+            if (d0 * d0 + d1 * d1 + d2 * d2 < rl * rl) {
+                if (cnt < ca.nl_cap) ca.nl_idx[g * ca.nl_cap + cnt] = (uint16_t)j;
+                ++cnt;
+            }
+        }
+        nl_n = cnt > ca.nl_cap ? -1 : cnt;
+        ca.nl_cnt[g] = nl_n;
+#pragma unroll
+        for (int c = 0; c < 3; ++c) ca.nl_x0[3 * g + c] = x[c];
+        if (b == 0) atomicAdd(&ca.nl_rebuilds[bi], 1u);
+    }
+    double W[3] = {0, 0, 0};
+    if (nl_n >= 0) {
+        const uint16_t* nl = ca.nl_idx + g * ca.nl_cap;
+        auto jof = [&](int k) { return (int)nl[k]; };
+        for (int k = 0; k < nl_n; k += 4) wca_add4(x, xs, jof, k, nl_n, 1, b, Ld, iL, bx.rc2, bx.sigsq, eps24, W);
+    } else {
+        auto jof = [](int k) { return k; };
+        for (int j = 0; j < N; j += 4) wca_add4(x, xs, jof, j, N, 1, b, Ld, iL, bx.rc2, bx.sigsq, eps24, W);
+    }
+    double F[3] = {0, 0, 0};
+    hbits |= fene_force(bx, b, N, x, xs, F);
+    F[0] += W[0]; F[1] += W[1]; F[2] += W[2];
+
+    // stencil and its cache
+    int i0[3];
+    double fr[3];
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+        const double xt = x[c] - Ld * floor(x[c] * iL);
+        const double fl = floor(xt);
+        fr[c] = xt - fl;
+        int ii = (int)fl;
+        if (ii >= L) ii -= L;
+        if (ii < 0) ii += L;
+        i0[c] = ii;
+    }
+    int tcnt = ba.cb[4 * g + 3];
+    double cu[8][3], acc[8][3];
+    uint32_t cnode[8];
+    const bool have = ba.cb[4 * g] >= 0;
+    const bool same = have && ba.cb[4 * g] == i0[0] && ba.cb[4 * g + 1] == i0[1] && ba.cb[4 * g + 2] == i0[2];
+    if (have) {
+        const int cb0 = ba.cb[4 * g], cb1 = ba.cb[4 * g + 1], cb2 = ba.cb[4 * g + 2];
+#pragma unroll
+        for (int k = 0; k < 8; ++k) {
+            const int ix = cb0 + (k & 1), iy = cb1 + ((k >> 1) & 1), iz = cb2 + ((k >> 2) & 1);
+            cnode[k] = (uint32_t)(ix >= L ? ix - L : ix) +
+                       (uint32_t)L * ((uint32_t)(iy >= L ? iy - L : iy) + (uint32_t)L * (uint32_t)(iz >= L ? iz - L : iz));
+#pragma unroll
+            for (int c = 0; c < 3; ++c) { acc[k][c] = ba.acc[24 * g + 3 * k + c]; cu[k][c] = ba.cu[24 * g + 3 * k + c]; }
+        }
+    }
+    if (!same) {
+        if (have) hbits |= flush_stencil(ca, bx.node_off, g, cnode, acc, bx.tau_lb, tcnt);
+#pragma unroll
+        for (int k = 0; k < 8; ++k) {
+            const int ix = i0[0] + (k & 1), iy = i0[1] + ((k >> 1) & 1), iz = i0[2] + ((k >> 2) & 1);
+            cnode[k] = (uint32_t)(ix >= L ? ix - L : ix) +
+                       (uint32_t)L * ((uint32_t)(iy >= L ? iy - L : iy) + (uint32_t)L * (uint32_t)(iz >= L ? iz - L : iz));
+            acc[k][0] = acc[k][1] = acc[k][2] = 0.0;
+        }
+        stencil_velocities<R, double, false>(A + bx.pop_off, bx.ps, i0, L, bx.rho0, inv_tau, cu);
+#pragma unroll
+        for (int k = 0; k < 8; ++k)
+#pragma unroll
+            for (int c = 0; c < 3; ++c) ba.cu[24 * g + 3 * k + c] = cu[k][c];
+        ba.cb[4 * g] = i0[0]; ba.cb[4 * g + 1] = i0[1]; ba.cb[4 * g + 2] = i0[2];
+    }
+    double wt[8], ub[3] = {0, 0, 0};
+#pragma unroll
+    for (int k = 0; k < 8; ++k) {
+        wt[k] = ((k & 1) ? fr[0] : 1.0 - fr[0]) * (((k >> 1) & 1) ? fr[1] : 1.0 - fr[1]) *
+                (((k >> 2) & 1) ? fr[2] : 1.0 - fr[2]);
+        ub[0] += wt[k] * cu[k][0]; ub[1] += wt[k] * cu[k][1]; ub[2] += wt[k] * cu[k][2];
+    }
+    const U4 w = philox10(U4{(uint32_t)b, t, (1u << 16) | (uint32_t)s, 0u}, bx.seed, bx.box_id);
+    const uint32_t ws[3] = {w.x, w.y, w.z};
+    double f[3], fcl[3];
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+        const double ffr = -bx.zeta * (v[c] - ub[c]);
+        const double frn = bx.bead_noise * unit_noise<double>(ws[c]);
+        fcl[c] = ffr + frn;
+        f[c] = F[c] + fcl[c];
+        v[c] += f[c] * hdt_m;
+    }
+#pragma unroll
+    for (int k = 0; k < 8; ++k) {
+        acc[k][0] -= wt[k] * fcl[0] * dt;
+        acc[k][1] -= wt[k] * fcl[1] * dt;
+        acc[k][2] -= wt[k] * fcl[2] * dt;
+    }
+    if (s + 1 < S) {
+        // first half kick and drift of the next substep; ask for a list
+        // rebuild there if this bead moved too far since the last build
+        double* xn = ba.xb + (uint64_t)((s + 1) & 1) * 3 * tb + 3 * g;
+        double dd = 0.0;
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            v[c] += f[c] * hdt_m;
+            const double xn_c = x[c] + v[c] * dt;
+            xn[c] = xn_c;
+            const double e = xn_c - ca.nl_x0[3 * g + c];
+            dd += e * e;
+        }
+        if (dd > 0.25 * NL_SKIN * NL_SKIN) atomicMax(&ba.nl_req[bi], sigma + 1u);
+#pragma unroll
+        for (int k = 0; k < 8; ++k)
+#pragma unroll
+            for (int c = 0; c < 3; ++c) ba.acc[24 * g + 3 * k + c] = acc[k][c];
+        ba.cb[4 * g + 3] = tcnt;
+#pragma unroll
+        for (int c = 0; c < 3; ++c) { ca.v[3 * g + c] = v[c]; ca.f[3 * g + c] = f[c]; }
+    } else {
+        // last substep: hand over the impulse, store the bead state
+        hbits |= flush_stencil(ca, bx.node_off, g, cnode, acc, bx.tau_lb, tcnt);
+        ca.touched_cnt[g] = tcnt < ca.touch_cap ? tcnt : ca.touch_cap;
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            ca.x[3 * g + c] = x[c]; ca.v[3 * g + c] = v[c]; ca.f[3 * g + c] = f[c]; ca.fc[3 * g + c] = fcl[c];
+        }
+        if (ca.vhist) {
+            double* hv = ca.vhist + ((uint64_t)(t % (uint32_t)ca.hist_len) * ca.total_beads + g) * 3;
+            hv[0] = v[0]; hv[1] = v[1]; hv[2] = v[2];
+        }
+        // the drift of the next step's first substep is known already: ask for
+        // a rebuild there if it takes the bead too far from its build position
+        double dd = 0.0;
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            const double e = x[c] + (v[c] + f[c] * hdt_m) * dt - ca.nl_x0[3 * g + c];
+            dd += e * e;
+        }
+        if (dd > 0.25 * NL_SKIN * NL_SKIN) atomicMax(&ba.nl_req[bi], sigma + 1u);
+    }
+    if (hbits) atomicOr(&ctrl->health, hbits);
 }
 
 // ---------------------------------------------------------------- fixup
@@ -645,12 +872,23 @@ hipError_t launch_couple(const LaunchCtx& c, const void* A, const int32_t* list,
                          uint32_t s_off)
 {
     if (n_list == 0) return hipSuccess;
-    if (block <= 256)
-        hipLaunchKernelGGL((k_couple<R, 256>), dim3(n_list), dim3(block), 0, c.stream, c.boxes, list, (const R*)A,
-                           chain_args(c), T, c.ctrl, s_off);
-    else
-        hipLaunchKernelGGL((k_couple<R, 1024>), dim3(n_list), dim3(block), 0, c.stream, c.boxes, list,
-                           (const R*)A, chain_args(c), T, c.ctrl, s_off);
+    if (block > 256) return hipErrorInvalidValue;   // larger chains take the multi-workgroup path
+    hipLaunchKernelGGL((k_couple<R, 256>), dim3(n_list), dim3(block), 0, c.stream, c.boxes, list, (const R*)A,
+                       chain_args(c), T, c.ctrl, s_off);
+    return hipGetLastError();
+}
+
+template <typename R>
+hipError_t launch_couple_big(const LaunchCtx& c, const void* A, int block0, int n_blocks, int substeps,
+                             uint32_t s_off)
+{
+    if (n_blocks == 0) return hipSuccess;
+    BigArgs ba{c.big_blocks + block0, c.xb, c.big_cb, c.big_cu, c.big_acc, c.nl_req};
+    const dim3 grid(n_blocks * XCD_SPREAD);
+    hipLaunchKernelGGL(k_chain_drift, grid, dim3(64), 0, c.stream, c.boxes, chain_args(c), ba);
+    for (int s = 0; s < substeps; ++s)
+        hipLaunchKernelGGL(k_chain_sub<R>, grid, dim3(64), 0, c.stream, c.boxes, (const R*)A, chain_args(c), ba, s,
+                           c.ctrl, s_off);
     return hipGetLastError();
 }
 
@@ -688,6 +926,8 @@ template hipError_t launch_fixup<float>(const LaunchCtx&, const void*, void*, ui
 template hipError_t launch_fixup<double>(const LaunchCtx&, const void*, void*, uint64_t, uint64_t, uint32_t);
 template hipError_t launch_couple<float>(const LaunchCtx&, const void*, const int32_t*, int, int, int, uint32_t);
 template hipError_t launch_couple<double>(const LaunchCtx&, const void*, const int32_t*, int, int, int, uint32_t);
+template hipError_t launch_couple_big<float>(const LaunchCtx&, const void*, int, int, int, uint32_t);
+template hipError_t launch_couple_big<double>(const LaunchCtx&, const void*, int, int, int, uint32_t);
 template hipError_t launch_stats<float>(const LaunchCtx&, const void*, uint32_t, double*, double*);
 template hipError_t launch_stats<double>(const LaunchCtx&, const void*, uint32_t, double*, double*);
 

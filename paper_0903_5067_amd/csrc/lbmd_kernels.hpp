@@ -25,6 +25,13 @@ struct LaunchCtx {
     double *x, *v, *f, *fc;        // beads [total][3]
     int32_t* nl_cnt; uint16_t* nl_idx; double* nl_x0; int nl_cap;
     double* vhist; int hist_len; uint64_t total_beads;
+    // chains above 256 beads: one launch per substep over blocks of 64 beads
+    const int2* big_blocks;        // (box, first bead of the block)
+    double* xb;                    // [2][total beads][3] positions of the current / next substep
+    int32_t* big_cb;               // [total beads][4]
+    double* big_cu;                // [total beads][24]
+    double* big_acc;               // [total beads][24]
+    uint32_t* nl_req;              // per box
 };
 
 template <typename R>
@@ -36,6 +43,10 @@ hipError_t launch_fixup(const LaunchCtx& c, const void* A, void* B, uint64_t bea
 template <typename R>
 hipError_t launch_couple(const LaunchCtx& c, const void* A, const int32_t* list, int n_list, int block, int T,
                          uint32_t s_off);
+template <typename R>
+hipError_t launch_couple_big(const LaunchCtx& c, const void* A, int block0, int n_blocks, int substeps,
+                             uint32_t s_off);
+constexpr int BIG_CHAIN = 256;   // chains above this many beads take the multi-workgroup path
 hipError_t launch_advance(const LaunchCtx& c, uint32_t n);
 hipError_t launch_init_forces(const LaunchCtx& c, const int32_t* list, int n_list, int block);
 template <typename R>

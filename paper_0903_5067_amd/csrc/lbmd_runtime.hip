@@ -45,8 +45,13 @@ struct Layout {
     size_t st_popA = 0, st_popB = 0, st_x = 0, st_v = 0, st_f = 0, st_fc = 0, state_bytes = 0;
     size_t sc_ctrl = 0, sc_boxes = 0, sc_ccs = 0, sc_tilebox = 0, sc_couple = 0, sc_imp = 0, sc_claim = 0,
            sc_touched = 0, sc_tcnt = 0, sc_beadbox = 0, sc_nlcnt = 0, sc_nlidx = 0, sc_nlx0 = 0,
-           sc_part = 0, sc_stat = 0, sc_chain = 0, sc_vhist = 0, sc_nlreb = 0, scratch_bytes = 0;
-    int max_N = 0;
+           sc_part = 0, sc_stat = 0, sc_chain = 0, sc_vhist = 0, sc_nlreb = 0, sc_bigblk = 0, sc_xb = 0,
+           sc_bigcb = 0, sc_bigcu = 0, sc_bigacc = 0, sc_nlreq = 0, scratch_bytes = 0;
+    int max_N = 0;         // largest chain taking the one-workgroup path
+    int big_substeps = 0;  // most substeps among chains taking the multi-workgroup path
+    std::vector<int> big_block_off, big_block_cnt;   // per box
+    std::vector<int32_t> big_blocks;                  // (box, first bead) pairs
+    std::vector<int32_t> small_list;                  // boxes on the one-workgroup path
     int couple_T = 1, couple_block = 64;
     int touch_cap = 8;
 };
@@ -102,7 +107,16 @@ Layout make_layout(const lb_box_desc* b, int32_t n, int32_t prec, int32_t hist)
         beads += b[i].n_beads;
         Lo.node_off.push_back(nodes);
         nodes += V;
-        Lo.max_N = std::max(Lo.max_N, b[i].n_beads);
+        const int N = b[i].n_beads;
+        Lo.big_block_off.push_back((int)Lo.big_blocks.size() / 2);
+        if (N > BIG_CHAIN) {
+            for (int s0 = 0; s0 < N; s0 += 64) { Lo.big_blocks.push_back(i); Lo.big_blocks.push_back(s0); }
+            Lo.big_substeps = std::max(Lo.big_substeps, b[i].md_substeps);
+        } else if (N > 0) {
+            Lo.small_list.push_back(i);
+            Lo.max_N = std::max(Lo.max_N, N);
+        }
+        Lo.big_block_cnt.push_back((int)Lo.big_blocks.size() / 2 - Lo.big_block_off.back());
     }
     Lo.pop_elems = pop;
     Lo.total_tiles = tiles;
@@ -147,6 +161,12 @@ Layout make_layout(const lb_box_desc* b, int32_t n, int32_t prec, int32_t hist)
     Lo.sc_chain = o; o = align256(o + n * NCHAIN_REC * sizeof(double));
     Lo.sc_vhist = o; o = align256(o + (size_t)hist * std::max<uint64_t>(beads, 1) * 3 * sizeof(double));
     Lo.sc_nlreb = o; o = align256(o + n * sizeof(uint32_t));
+    Lo.sc_bigblk = o; o = align256(o + std::max<size_t>(Lo.big_blocks.size(), 2) * sizeof(int32_t));
+    Lo.sc_xb = o; o = align256(o + 2 * nbx * 3 * sizeof(double));
+    Lo.sc_bigcb = o; o = align256(o + nbx * 4 * sizeof(int32_t));
+    Lo.sc_bigcu = o; o = align256(o + nbx * 24 * sizeof(double));
+    Lo.sc_bigacc = o; o = align256(o + nbx * 24 * sizeof(double));
+    Lo.sc_nlreq = o; o = align256(o + n * sizeof(uint32_t));
     Lo.scratch_bytes = o;
     return Lo;
 }
@@ -224,14 +244,20 @@ lb_status enqueue_step(lb_handle* h, int from, uint32_t s_off, bool couple)
     const bool f64 = h->prec == LB_FP64;
     const LaunchCtx& c = h->ctx;
     const int nc = (int)h->couple_host.size();
+    const bool any_beads = h->lo.total_beads > 0;
     if (h->batched) {
-        const bool fork = couple && nc;
+        const bool fork = couple && any_beads;
         if (fork) {
             HIPCHK(h, hipEventRecord(h->ev_fork, h->stream));
             HIPCHK(h, hipStreamWaitEvent(h->stream2, h->ev_fork, 0));
             const LaunchCtx& c2 = h->ctx2;
-            HIPCHK(h, f64 ? launch_couple<double>(c2, A, h->couple_list, nc, h->lo.couple_block, h->lo.couple_T, s_off)
-                          : launch_couple<float>(c2, A, h->couple_list, nc, h->lo.couple_block, h->lo.couple_T, s_off));
+            if (nc)
+                HIPCHK(h, f64 ? launch_couple<double>(c2, A, h->couple_list, nc, h->lo.couple_block, h->lo.couple_T, s_off)
+                              : launch_couple<float>(c2, A, h->couple_list, nc, h->lo.couple_block, h->lo.couple_T, s_off));
+            const int nbig = (int)h->lo.big_blocks.size() / 2;
+            if (nbig)
+                HIPCHK(h, f64 ? launch_couple_big<double>(c2, A, 0, nbig, h->lo.big_substeps, s_off)
+                              : launch_couple_big<float>(c2, A, 0, nbig, h->lo.big_substeps, s_off));
             HIPCHK(h, hipEventRecord(h->ev_join, h->stream2));
         }
         HIPCHK(h, f64 ? launch_collide<double>(c, A, B, -1, 0, (uint32_t)h->lo.total_tiles, s_off)
@@ -245,6 +271,13 @@ lb_status enqueue_step(lb_handle* h, int from, uint32_t s_off, bool couple)
             if (!couple) break;
             HIPCHK(h, f64 ? launch_couple<double>(c, A, h->couple_list + i, 1, h->lo.couple_block, h->lo.couple_T, s_off)
                           : launch_couple<float>(c, A, h->couple_list + i, 1, h->lo.couple_block, h->lo.couple_T, s_off));
+        }
+        for (int b = 0; b < h->n_boxes && couple; ++b) {
+            if (!h->lo.big_block_cnt[b]) continue;
+            HIPCHK(h, f64 ? launch_couple_big<double>(c, A, h->lo.big_block_off[b], h->lo.big_block_cnt[b],
+                                                      h->desc[b].md_substeps, s_off)
+                          : launch_couple_big<float>(c, A, h->lo.big_block_off[b], h->lo.big_block_cnt[b],
+                                                     h->desc[b].md_substeps, s_off));
         }
         for (int b = 0; b < h->n_boxes; ++b) {
             HIPCHK(h, f64 ? launch_collide<double>(c, A, B, b, h->lo.tile_begin[b], h->lo.n_tiles[b], s_off)
@@ -361,8 +394,7 @@ lb_status lb_init(const lb_box_desc* boxes, int32_t n_boxes, int32_t precision, 
     std::vector<uint32_t> tile_box(lo.total_tiles);
     for (int i = 0; i < n_boxes; ++i)
         for (uint32_t t = 0; t < lo.n_tiles[i]; ++t) tile_box[lo.tile_begin[i] + t] = (uint32_t)i;
-    for (int i = 0; i < n_boxes; ++i)
-        if (boxes[i].n_beads > 0) h->couple_host.push_back(i);
+    h->couple_host = lo.small_list;
     std::vector<int32_t> nlcnt(std::max<uint64_t>(nb, 1), -2);
     std::vector<int32_t> bead_box(std::max<uint64_t>(nb, 1), 0);
     for (int i = 0; i < n_boxes; ++i)
@@ -389,6 +421,7 @@ lb_status lb_init(const lb_box_desc* boxes, int32_t n_boxes, int32_t precision, 
     chk(up(lo.sc_tilebox, tile_box.data(), tile_box.size() * sizeof(uint32_t)));
     chk(up(lo.sc_couple, h->couple_host.data(), h->couple_host.size() * sizeof(int32_t)));
     chk(up(lo.sc_beadbox, bead_box.data(), bead_box.size() * sizeof(int32_t)));
+    chk(up(lo.sc_bigblk, lo.big_blocks.data(), lo.big_blocks.size() * sizeof(int32_t)));
     chk(up(lo.sc_nlcnt, nlcnt.data(), nlcnt.size() * sizeof(int32_t)));
     if (nb) chk(hipMemcpy(stp(lo.st_x), bead_x0, nb * 3 * sizeof(double), hipMemcpyHostToDevice));
     if (e != hipSuccess) {
@@ -410,6 +443,12 @@ lb_status lb_init(const lb_box_desc* boxes, int32_t n_boxes, int32_t precision, 
     c.touched_cnt = (int32_t*)sc(lo.sc_tcnt);
     c.touch_cap = lo.touch_cap;
     c.nl_rebuilds = (uint32_t*)sc(lo.sc_nlreb);
+    c.big_blocks = (const int2*)sc(lo.sc_bigblk);
+    c.xb = (double*)sc(lo.sc_xb);
+    c.big_cb = (int32_t*)sc(lo.sc_bigcb);
+    c.big_cu = (double*)sc(lo.sc_bigcu);
+    c.big_acc = (double*)sc(lo.sc_bigacc);
+    c.nl_req = (uint32_t*)sc(lo.sc_nlreq);
     c.bead_box = (const int32_t*)sc(lo.sc_beadbox);
     c.x = (double*)stp(lo.st_x); c.v = (double*)stp(lo.st_v); c.f = (double*)stp(lo.st_f); c.fc = (double*)stp(lo.st_fc);
     c.nl_cnt = (int32_t*)sc(lo.sc_nlcnt); c.nl_idx = (uint16_t*)sc(lo.sc_nlidx); c.nl_x0 = (double*)sc(lo.sc_nlx0);
@@ -429,8 +468,19 @@ lb_status lb_init(const lb_box_desc* boxes, int32_t n_boxes, int32_t precision, 
     h->ctx2 = c;
     h->ctx2.stream = h->stream2;
 
-    e = launch_init_forces(c, h->couple_list, (int)h->couple_host.size(),
-                           std::max(64, (int)round_up((uint64_t)lo.max_N, 64)));
+    {
+        std::vector<int32_t> all;
+        int mx = 0;
+        for (int i = 0; i < n_boxes; ++i)
+            if (boxes[i].n_beads > 0) { all.push_back(i); mx = std::max(mx, boxes[i].n_beads); }
+        // the per-box list of the one-workgroup path is reused as scratch for this launch
+        int32_t* dl = (int32_t*)sc(lo.sc_nlreq);
+        e = all.empty() ? hipSuccess : hipMemcpy(dl, all.data(), all.size() * sizeof(int32_t), hipMemcpyHostToDevice);
+        if (e == hipSuccess)
+            e = launch_init_forces(c, dl, (int)all.size(), std::max(64, (int)round_up((uint64_t)mx, 64)));
+        if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
+        if (e == hipSuccess) e = hipMemset(dl, 0, n_boxes * sizeof(uint32_t));
+    }
     if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
     if (e != hipSuccess) {
         std::string msg = std::string("initial forces: ") + hipGetErrorString(e);
@@ -445,14 +495,23 @@ lb_status lb_couple(lb_handle* h)
 {
     if (!h) return fail(nullptr, LB_EINVAL, "null handle");
     if (h->pending) return fail(h, LB_ESTATE, "lb_couple called twice without lb_step");
-    if (!h->couple_host.empty()) {
+    {
         const void* A = h->pop(h->cur);
         const LaunchCtx& c = h->ctx;
         const int nc = (int)h->couple_host.size();
-        if (h->prec == LB_FP64)
-            HIPCHK(h, launch_couple<double>(c, A, h->couple_list, nc, h->lo.couple_block, h->lo.couple_T, 0));
-        else
-            HIPCHK(h, launch_couple<float>(c, A, h->couple_list, nc, h->lo.couple_block, h->lo.couple_T, 0));
+        const int nbig = (int)h->lo.big_blocks.size() / 2;
+        if (nc) {
+            if (h->prec == LB_FP64)
+                HIPCHK(h, launch_couple<double>(c, A, h->couple_list, nc, h->lo.couple_block, h->lo.couple_T, 0));
+            else
+                HIPCHK(h, launch_couple<float>(c, A, h->couple_list, nc, h->lo.couple_block, h->lo.couple_T, 0));
+        }
+        if (nbig) {
+            if (h->prec == LB_FP64)
+                HIPCHK(h, launch_couple_big<double>(c, A, 0, nbig, h->lo.big_substeps, 0));
+            else
+                HIPCHK(h, launch_couple_big<float>(c, A, 0, nbig, h->lo.big_substeps, 0));
+        }
     }
     h->pending = true;
     return LB_OK;

@@ -253,3 +253,49 @@ def test_health_flag_from_nan():
     assert ei.value.status == lbm.LB_ENUMERIC
     o = s.observables(allow_unhealthy=True)[0]
     assert o["health"] & (lbm.HEALTH["density"] | lbm.HEALTH["mach"])
+
+
+# ------------------------------------------------ chains on the multi-workgroup path
+@pytest.mark.parametrize("prec", [FP64, FP32])
+def test_big_chain_matches_oracle(orc, prec):
+    """A 300-bead chain (above 256 beads the substeps run as one launch each over
+    workgroups of 64 beads, with a neighbour list): one coupling, then 30 full
+    steps, against the oracle."""
+    say("big chain", prec)
+    p = params(L=16, N=300, kT=1e-2)
+    x0 = chain(p)
+    n0 = initial_pops(orc, p, amp=0.01, seed=3)
+    s = gpu_system([p], prec, xs=[x0], pops=[n0])
+    s.couple()
+    dp_g = s.pending_impulse()[0]
+    bg = s.export_state()["boxes"][0]
+    o = oracle_state(orc, p, n0, x0)
+    dp_o = o.couple()
+    assert np.max(np.abs(dp_g - dp_o)) < (1e-13 if prec == FP64 else 1e-9)
+    for k, ref in (("x", o.x), ("v", o.v), ("f", o.f), ("fc", o.fc)):
+        assert np.max(np.abs(bg[k] - ref)) < (1e-11 if prec == FP64 else 1e-6), k
+    s.step(30)
+    o.collide_stream(dp_o)
+    o.run(29)
+    st = s.export_state()["boxes"][0]
+    assert max_rel_pop_err(st["n"], o.n, orc) < (1e-11 if prec == FP64 else 1e-5)
+    assert np.max(np.abs(st["x"] - o.x)) < (1e-9 if prec == FP64 else 1e-5)
+    ob = s.observables()[0]
+    assert ob["nlist_builds"] >= 1
+
+
+def test_big_chain_in_batch_bitwise():
+    """Boxes on both coupling paths in one batch equal the same boxes run alone."""
+    say("big chain batch")
+    boxes = [params(L=12, N=300, seed=2, box_id=0), params(L=8, N=8, seed=2, box_id=1)]
+    xs = [chain(b) for b in boxes]
+    sb = gpu_system(boxes, FP32, xs=xs)
+    sb.set_launch(batched=True, graph_steps=4)
+    sb.step(9)
+    batch = sb.export_state()["boxes"]
+    for i, b in enumerate(boxes):
+        si = gpu_system([b], FP32, xs=[xs[i]])
+        si.step(9)
+        single = si.export_state()["boxes"][0]
+        for k in ("n", "x", "v", "f", "fc"):
+            assert np.array_equal(batch[i][k], single[k]), (i, k)
