@@ -4,8 +4,10 @@ TEST INFRASTRUCTURE ONLY: the test suite, the smoke check and the CPU-baseline
 leg of the benchmark are the only callers.  Nothing in the GPU library imports
 or links this package, and this package imports nothing from the GPU library.
 
-The arithmetic lives in ``lbmd_oracle.c`` (plain C, FP64, no code shared with
-the HIP path); this module builds it with gcc and marshals numpy arrays.
+The arithmetic lives in ``lbmd_oracle.cpp`` (plain C++, FP64, no code shared
+with the HIP path; written once over the scalar type so that a dual-number
+instantiation gives exact forward-mode derivatives with respect to the shear
+and bulk rates and the friction); this module builds it and marshals arrays.
 ``brute.py`` is a second, independent numpy statement of one collide+stream
 step on tiny lattices, used to pin the C oracle.
 
@@ -17,6 +19,8 @@ Parity status per function (what pins it is listed in the test files):
   couple               pinned (force = -grad V, exact linear interpolation,
                                momentum invariant, bead equipartition)
   observables          pinned (closed forms on hand-made states)
+  window_tangent       pinned (central finite differences of the oracle's own
+                               window; values identical to run())
   specific noise realisations / long trajectories: parity unpinned beyond the
   shared generator (any realisation with the right moments is valid).
 """
@@ -29,7 +33,7 @@ import subprocess
 import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-_SRC = os.path.join(_HERE, "lbmd_oracle.c")
+_SRC = os.path.join(_HERE, "lbmd_oracle.cpp")
 _LIB = os.path.join(_HERE, "liblbmd_oracle.so")
 
 OBS_LEN = 38
@@ -41,8 +45,8 @@ OBS = {
 
 
 def build(verbose: bool = False) -> str:
-    """Compile the oracle with gcc (plain -O2, no fast-math, no FMA contraction)."""
-    cmd = ["gcc", "-O2", "-fopenmp", "-ffp-contract=off", "-fPIC", "-shared",
+    """Compile the oracle with g++ (plain -O2, no fast-math, no FMA contraction)."""
+    cmd = ["g++", "-O2", "-std=c++17", "-fopenmp", "-ffp-contract=off", "-fPIC", "-shared",
            "-o", _LIB + ".tmp", _SRC, "-lm"]
     if verbose:
         print(" ".join(cmd))
@@ -88,6 +92,7 @@ def lib():
         _lib.orc_couple.argtypes = [bp, dp, dp, dp, dp, dp, ctypes.c_uint32, dp]
         _lib.orc_run.argtypes = [bp, dp, dp, dp, dp, dp, ctypes.c_uint32, ctypes.c_int32, dp]
         _lib.orc_observables.argtypes = [bp, dp, dp, dp, dp, dp]
+        _lib.orc_window_tangent.argtypes = [bp, dp, dp, dp, dp, dp, ctypes.c_uint32, ctypes.c_int32, dp, dp]
         _lib.orc_num_threads.restype = ctypes.c_int
     return _lib
 
@@ -152,6 +157,18 @@ class State:
                       _p(self.fc), self.t, n_steps, _p(hist))
         self.t += n_steps
         return hist
+
+    def window_tangent(self, n_steps: int):
+        """Advance n_steps like run(); return the bead velocities at the end of
+        each step [T, N, 3] and their derivatives with respect to
+        (omega_shear, omega_bulk, zeta) [T, N, 3, 3] (forward mode, exact)."""
+        N = self.box.N
+        hist = np.zeros((n_steps, N, 3))
+        dh = np.zeros((n_steps, N, 3, 3))
+        lib().orc_window_tangent(ctypes.byref(self.box), _p(self.n), _p(self.x), _p(self.v), _p(self.f),
+                                 _p(self.fc), self.t, n_steps, _p(hist), _p(dh))
+        self.t += n_steps
+        return hist, dh
 
     def couple(self) -> np.ndarray:
         L = self.box.L

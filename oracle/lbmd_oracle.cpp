@@ -31,9 +31,64 @@
 #include <stdlib.h>
 #include <string.h>
 
+#include <vector>
+
 #ifdef _OPENMP
 #include <omp.h>
 #endif
+
+/* The step is written once as templates over the scalar type.  With double it
+ * is the oracle; with D3 (a value and its derivatives with respect to the
+ * three rates omega_shear, omega_bulk and zeta, forward-mode differentiation)
+ * the same arithmetic yields the exact tangent of every quantity, used as the
+ * oracle gradient of the adjoint window.  Integer decisions (stencil cell,
+ * minimum image, LJ cut-off) are taken on values; their derivative is zero. */
+struct D3 {
+    double v;
+    double d[3];
+    D3() : v(0.0), d{0.0, 0.0, 0.0} {}
+    D3(double x) : v(x), d{0.0, 0.0, 0.0} {}
+};
+static inline D3 operator+(const D3& a, const D3& b) { D3 r(a.v + b.v); for (int i = 0; i < 3; i++) r.d[i] = a.d[i] + b.d[i]; return r; }
+static inline D3 operator-(const D3& a, const D3& b) { D3 r(a.v - b.v); for (int i = 0; i < 3; i++) r.d[i] = a.d[i] - b.d[i]; return r; }
+static inline D3 operator-(const D3& a) { D3 r(-a.v); for (int i = 0; i < 3; i++) r.d[i] = -a.d[i]; return r; }
+static inline D3 operator*(const D3& a, const D3& b) { D3 r(a.v * b.v); for (int i = 0; i < 3; i++) r.d[i] = a.d[i] * b.v + a.v * b.d[i]; return r; }
+static inline D3 operator/(const D3& a, const D3& b)
+{
+    D3 r(a.v / b.v);
+    for (int i = 0; i < 3; i++) r.d[i] = (a.d[i] * b.v - a.v * b.d[i]) / (b.v * b.v);
+    return r;
+}
+static inline D3 operator+(const D3& a, double b) { return a + D3(b); }
+static inline D3 operator+(double a, const D3& b) { return D3(a) + b; }
+static inline D3 operator-(const D3& a, double b) { return a - D3(b); }
+static inline D3 operator-(double a, const D3& b) { return D3(a) - b; }
+static inline D3 operator*(const D3& a, double b) { D3 r(a.v * b); for (int i = 0; i < 3; i++) r.d[i] = a.d[i] * b; return r; }
+static inline D3 operator*(double a, const D3& b) { return b * a; }
+static inline D3 operator/(const D3& a, double b) { return a / D3(b); }
+static inline D3 operator/(double a, const D3& b) { return D3(a) / b; }
+static inline D3& operator+=(D3& a, const D3& b) { a = a + b; return a; }
+static inline D3& operator-=(D3& a, const D3& b) { a = a - b; return a; }
+static inline D3& operator*=(D3& a, const D3& b) { a = a * b; return a; }
+static inline D3& operator/=(D3& a, const D3& b) { a = a / b; return a; }
+static inline D3 sqrt(const D3& a)
+{
+    D3 r(sqrt(a.v));
+    for (int i = 0; i < 3; i++) r.d[i] = r.v > 0.0 ? a.d[i] / (2.0 * r.v) : 0.0;
+    return r;
+}
+static inline double val(double a) { return a; }
+static inline double val(const D3& a) { return a.v; }
+
+/* the differentiated parameters, as scalars of the working type */
+template <class T> struct Theta { T omega_s, omega_b, zeta; };
+
+extern "C" {
+void orc_tables(double* c, double* w, double* e, double* b);
+void orc_philox4x32_10(const uint32_t ctr[4], const uint32_t key[2], uint32_t out[4]);
+double orc_unit_noise(uint32_t word);
+int orc_num_threads(void);
+}
 
 typedef struct {
     int32_t L, N;
@@ -44,6 +99,20 @@ typedef struct {
     double mass, zeta, k_fene, r0_fene, eps_wca, sigma_wca;
     uint32_t seed, box_id;
 } orc_box;
+
+extern "C" {
+void orc_collide_stream(const orc_box* p, const double* nin, double* nout, const double* dp, uint32_t t);
+void orc_collide_one(const orc_box* p, const double* n, const double* dp, uint32_t r, uint32_t t, double* nout);
+void orc_initial_forces(const orc_box* p, const double* x, double* f);
+void orc_couple(const orc_box* p, const double* n, double* x, double* v, double* f, double* fc, uint32_t t,
+                double* dp);
+void orc_run(const orc_box* p, double* n, double* x, double* v, double* f, double* fc, uint32_t t0,
+             int32_t n_steps, double* vel_hist);
+void orc_window_tangent(const orc_box* p, double* n, double* x, double* v, double* f, double* fc, uint32_t t0,
+                        int32_t n_steps, double* vel_hist, double* dvel);
+void orc_observables(const orc_box* p, const double* n, const double* x, const double* v, const double* fc,
+                     double* out);
+}
 
 /* ---------------------------------------------------------------- D3Q19 --- */
 /* rest, 6 nearest (|c|=1), 12 next-nearest (|c|=sqrt 2) neighbours; Sec. II.B */
@@ -171,22 +240,23 @@ static uint32_t lb_word(const orc_box* p, uint32_t r, uint32_t t, int q)
 /* One node: populations n[19] (FP64, full n not deviations), lattice-unit
  * impulse dp[3] handed to the fluid this step, node index r, step t.
  * Output: post-collision populations nout[19]. */
-static void collide_node(const orc_box* p, const double n[19], const double dp[3],
-                         uint32_t r, uint32_t t, double nout[19])
+template <class T>
+static void collide_node(const orc_box* p, const Theta<T>& th, const T n[19], const T dp[3],
+                         uint32_t r, uint32_t t, T nout[19])
 {
-    double m[19], ms[19];
+    T m[19], ms[19];
     for (int k = 0; k < 19; k++) {
         m[k] = 0.0;
         for (int i = 0; i < 19; i++) m[k] += E[k][i] * n[i];
     }
-    double rho = m[0];
+    T rho = m[0];
     /* reading: second-order forcing; velocity shifted by half the impulse */
-    double u[3];
+    T u[3];
     for (int a = 0; a < 3; a++) u[a] = (m[1 + a] + 0.5 * dp[a]) / rho;
-    double u2 = u[0] * u[0] + u[1] * u[1] + u[2] * u[2];
+    T u2 = u[0] * u[0] + u[1] * u[1] + u[2] * u[2];
 
     /* equilibrium stress modes: projections of the second-order n^eq */
-    double meq[10];
+    T meq[10];
     meq[4] = rho * u2;
     meq[5] = rho * (2.0 * u[0] * u[0] - u[1] * u[1] - u[2] * u[2]);
     meq[6] = rho * (u[1] * u[1] - u[2] * u[2]);
@@ -194,7 +264,7 @@ static void collide_node(const orc_box* p, const double n[19], const double dp[3
     meq[8] = rho * u[1] * u[2];
     meq[9] = rho * u[0] * u[2];
     /* projections of the source tensor u dp + dp u onto the stress modes */
-    double src[10];
+    T src[10];
     src[4] = 2.0 * (u[0] * dp[0] + u[1] * dp[1] + u[2] * dp[2]);
     src[5] = 2.0 * (2.0 * u[0] * dp[0] - u[1] * dp[1] - u[2] * dp[2]);
     src[6] = 2.0 * (u[1] * dp[1] - u[2] * dp[2]);
@@ -202,10 +272,10 @@ static void collide_node(const orc_box* p, const double n[19], const double dp[3
     src[8] = u[1] * dp[2] + u[2] * dp[1];
     src[9] = u[0] * dp[2] + u[2] * dp[0];
 
-    double gam[19];
+    T gam[19];
     for (int k = 0; k < 19; k++) gam[k] = 0.0;
-    gam[4] = 1.0 - p->omega_b;
-    for (int k = 5; k <= 9; k++) gam[k] = 1.0 - p->omega_s;
+    gam[4] = 1.0 - th.omega_b;
+    for (int k = 5; k <= 9; k++) gam[k] = 1.0 - th.omega_s;
     for (int k = 10; k <= 18; k++) gam[k] = 1.0 - p->omega_g;
 
     /* fluctuation amplitude: mu = kT / c_s^2 in lattice units,
@@ -220,14 +290,25 @@ static void collide_node(const orc_box* p, const double n[19], const double dp[3
         ms[k] = meq[k] + gam[k] * (m[k] - meq[k]) + 0.5 * (1.0 + gam[k]) * src[k];
     for (int k = 10; k <= 18; k++) ms[k] = gam[k] * m[k];
     for (int k = 4; k <= k_last; k++) {
-        double sigma = sqrt(mu * rho * B[k] * (1.0 - gam[k] * gam[k]));
+        T sigma = sqrt(mu * rho * B[k] * (1.0 - gam[k] * gam[k]));
         ms[k] += sigma * orc_unit_noise(lb_word(p, r, t, k - 4));
     }
     for (int i = 0; i < 19; i++) {
-        double s = 0.0;
+        T s = 0.0;
         for (int k = 0; k < 19; k++) s += E[k][i] * ms[k] / B[k];
         nout[i] = W[i] * s;
     }
+}
+
+template <class T> static Theta<T> theta_of(const orc_box* p);
+template <> Theta<double> theta_of<double>(const orc_box* p) { return {p->omega_s, p->omega_b, p->zeta}; }
+template <> Theta<D3> theta_of<D3>(const orc_box* p)
+{
+    Theta<D3> th{D3(p->omega_s), D3(p->omega_b), D3(p->zeta)};
+    th.omega_s.d[0] = 1.0;
+    th.omega_b.d[1] = 1.0;
+    th.zeta.d[2] = 1.0;
+    return th;
 }
 
 static int wrap(int a, int L)
@@ -238,8 +319,8 @@ static int wrap(int a, int L)
 
 /* collide every node with impulse field dp[3*V] (lattice units, NULL = 0),
  * then move each post-collision population to r + c_i (periodic). */
-void orc_collide_stream(const orc_box* p, const double* nin, double* nout,
-                        const double* dp, uint32_t t)
+template <class T>
+static void collide_stream(const orc_box* p, const Theta<T>& th, const T* nin, T* nout, const T* dp, uint32_t t)
 {
     build_tables();
     const int L = p->L;
@@ -249,17 +330,22 @@ void orc_collide_stream(const orc_box* p, const double* nin, double* nout,
         for (int y = 0; y < L; y++)
             for (int x = 0; x < L; x++) {
                 long r = x + (long)L * (y + (long)L * z);
-                double n[19], ns[19], f[3] = {0.0, 0.0, 0.0};
+                T n[19], ns[19], f[3] = {0.0, 0.0, 0.0};
                 for (int i = 0; i < 19; i++) n[i] = nin[i * V + r];
                 if (dp)
                     for (int a = 0; a < 3; a++) f[a] = dp[a * V + r];
-                collide_node(p, n, f, (uint32_t)r, t, ns);
+                collide_node(p, th, n, f, (uint32_t)r, t, ns);
                 for (int i = 0; i < 19; i++) {
                     int xd = wrap(x + C[i][0], L), yd = wrap(y + C[i][1], L),
                         zd = wrap(z + C[i][2], L);
                     nout[i * V + xd + (long)L * (yd + (long)L * zd)] = ns[i];
                 }
             }
+}
+
+void orc_collide_stream(const orc_box* p, const double* nin, double* nout, const double* dp, uint32_t t)
+{
+    collide_stream<double>(p, theta_of<double>(p), nin, nout, dp, t);
 }
 
 /* single-node collision for tests (no streaming) */
@@ -269,38 +355,39 @@ void orc_collide_one(const orc_box* p, const double* n, const double* dp, uint32
     build_tables();
     double f[3] = {0.0, 0.0, 0.0};
     if (dp) memcpy(f, dp, sizeof f);
-    collide_node(p, n, f, r, t, nout);
+    collide_node<double>(p, theta_of<double>(p), n, f, r, t, nout);
 }
 
 /* ------------------------------------------------------------ chain / MD --- */
 /* force on bead b from bead j: FENE if bonded (unwrapped separation), then the
  * purely repulsive LJ with minimum image; Sec. II.A.  Beads j are visited in
  * ascending order and the sum is taken in that order. */
-static void conservative_force(const orc_box* p, const double* x, int b, double F[3])
+template <class T>
+static void conservative_force(const orc_box* p, const T* x, int b, T F[3])
 {
     const double L = p->L;
     const double rc2 = pow(2.0, 1.0 / 3.0) * p->sigma_wca * p->sigma_wca;
     F[0] = F[1] = F[2] = 0.0;
     for (int j = 0; j < p->N; j++) {
         if (j == b) continue;
-        double d[3];
+        T d[3];
         if (j == b - 1 || j == b + 1) {
             for (int a = 0; a < 3; a++) d[a] = x[3 * b + a] - x[3 * j + a];
-            double r2 = d[0] * d[0] + d[1] * d[1] + d[2] * d[2];
+            T r2 = d[0] * d[0] + d[1] * d[1] + d[2] * d[2];
             /* -dV/dr along d for V = -(k R0^2/2) ln(1 - r^2/R0^2) */
-            double g = -p->k_fene / (1.0 - r2 / (p->r0_fene * p->r0_fene));
+            T g = -p->k_fene / (1.0 - r2 / (p->r0_fene * p->r0_fene));
             for (int a = 0; a < 3; a++) F[a] += g * d[a];
         }
         for (int a = 0; a < 3; a++) {
-            double s = x[3 * b + a] - x[3 * j + a];
-            d[a] = s - L * nearbyint(s / L);
+            T s = x[3 * b + a] - x[3 * j + a];
+            d[a] = s - L * nearbyint(val(s) / L);
         }
-        double r2 = d[0] * d[0] + d[1] * d[1] + d[2] * d[2];
-        if (r2 < rc2) {
+        T r2 = d[0] * d[0] + d[1] * d[1] + d[2] * d[2];
+        if (val(r2) < rc2) {
             /* -dV/dr along d for V = 4 eps [(s/r)^12 - (s/r)^6 + 1/4] */
-            double s2 = p->sigma_wca * p->sigma_wca / r2;
-            double s6 = s2 * s2 * s2;
-            double g = 24.0 * p->eps_wca * s6 * (2.0 * s6 - 1.0) / r2;
+            T s2 = p->sigma_wca * p->sigma_wca / r2;
+            T s6 = s2 * s2 * s2;
+            T g = 24.0 * p->eps_wca * s6 * (2.0 * s6 - 1.0) / r2;
             for (int a = 0; a < 3; a++) F[a] += g * d[a];
         }
     }
@@ -308,24 +395,25 @@ static void conservative_force(const orc_box* p, const double* x, int b, double 
 
 void orc_initial_forces(const orc_box* p, const double* x, double* f)
 {
-    for (int b = 0; b < p->N; b++) conservative_force(p, x, b, f + 3 * b);
+    for (int b = 0; b < p->N; b++) conservative_force<double>(p, x, b, f + 3 * b);
 }
 
 /* reading: nodes at integer coordinates; linear interpolation along each axis
  * between the two nearest planes of nodes, wrapped periodically. */
-static void stencil(int L, const double x[3], long node[8], double wt[8])
+template <class T>
+static void stencil(int L, const T x[3], long node[8], T wt[8])
 {
     int i0[3];
-    double fr[3];
+    T fr[3];
     for (int a = 0; a < 3; a++) {
-        double xt = x[a] - L * floor(x[a] / L);
-        double fl = floor(xt);
+        T xt = x[a] - L * floor(val(x[a]) / L);
+        double fl = floor(val(xt));
         fr[a] = xt - fl;
         i0[a] = wrap((int)fl, L);
     }
     for (int c = 0; c < 8; c++) {
         int d[3] = {c & 1, (c >> 1) & 1, (c >> 2) & 1};
-        double w = 1.0;
+        T w = 1.0;
         int idx[3];
         for (int a = 0; a < 3; a++) {
             w *= d[a] ? fr[a] : 1.0 - fr[a];
@@ -340,38 +428,39 @@ static void stencil(int L, const double x[3], long node[8], double wt[8])
  * the pre-collision state of step t; the impulse taken from the beads by
  * friction and noise is handed to the nodes of each bead's stencil.
  * dp (3*V, lattice units) is overwritten. */
-void orc_couple(const orc_box* p, const double* n, double* x, double* v, double* f,
-                double* fc, uint32_t t, double* dp)
+template <class T>
+static void couple(const orc_box* p, const Theta<T>& th, const T* n, T* x, T* v, T* f, T* fc, uint32_t t,
+                   T* dp)
 {
     build_tables();
     const int L = p->L, N = p->N;
     const long V = (long)L * L * L;
     const double dt = p->md_dt, m = p->mass;
     /* frozen node velocities in MD units: u = (j / rho) / tau_lb */
-    double* u = (double*)malloc(sizeof(double) * 3 * V);
+    std::vector<T> u(3 * V);
     for (long r = 0; r < V; r++) {
-        double rho = 0.0, j[3] = {0.0, 0.0, 0.0};
+        T rho = 0.0, j[3] = {0.0, 0.0, 0.0};
         for (int i = 0; i < 19; i++) {
-            double ni = n[i * V + r];
+            T ni = n[i * V + r];
             rho += ni;
-            for (int a = 0; a < 3; a++) j[a] += ni * C[i][a];
+            for (int a = 0; a < 3; a++) j[a] += ni * (double)C[i][a];
         }
         for (int a = 0; a < 3; a++) u[a * V + r] = j[a] / rho / p->tau_lb;
     }
-    memset(dp, 0, sizeof(double) * 3 * V);
-    const double noise_amp = sqrt(2.0 * p->kT * p->zeta / dt);
-    double* Fc = (double*)malloc(sizeof(double) * 3 * (N > 0 ? N : 1));
+    for (long q = 0; q < 3 * V; q++) dp[q] = 0.0;
+    const T noise_amp = sqrt(2.0 * p->kT * th.zeta / dt);
+    std::vector<T> Fc(3 * (N > 0 ? N : 1));
     for (int s = 0; s < p->md_substeps; s++) {
         for (int b = 0; b < N; b++)
             for (int a = 0; a < 3; a++) {
                 v[3 * b + a] += f[3 * b + a] / m * (0.5 * dt);
                 x[3 * b + a] += v[3 * b + a] * dt;
             }
-        for (int b = 0; b < N; b++) conservative_force(p, x, b, Fc + 3 * b);
+        for (int b = 0; b < N; b++) conservative_force<T>(p, x, b, &Fc[3 * b]);
         for (int b = 0; b < N; b++) {
             long node[8];
-            double wt[8], ub[3] = {0.0, 0.0, 0.0};
-            stencil(L, x + 3 * b, node, wt);
+            T wt[8], ub[3] = {0.0, 0.0, 0.0};
+            stencil<T>(L, x + 3 * b, node, wt);
             for (int c = 0; c < 8; c++)
                 for (int a = 0; a < 3; a++) ub[a] += wt[c] * u[a * V + node[c]];
             uint32_t ctr[4] = {(uint32_t)b, t, ((uint32_t)PURPOSE_BEAD << 16) | (uint32_t)s, 0};
@@ -379,8 +468,8 @@ void orc_couple(const orc_box* p, const double* n, double* x, double* v, double*
             uint32_t words[4];
             orc_philox4x32_10(ctr, key, words);
             for (int a = 0; a < 3; a++) {
-                double ffr = -p->zeta * (v[3 * b + a] - ub[a]);
-                double frn = noise_amp * orc_unit_noise(words[a]);
+                T ffr = -th.zeta * (v[3 * b + a] - ub[a]);
+                T frn = noise_amp * orc_unit_noise(words[a]);
                 fc[3 * b + a] = ffr + frn;
                 f[3 * b + a] = Fc[3 * b + a] + fc[3 * b + a];
                 v[3 * b + a] += f[3 * b + a] / m * (0.5 * dt);
@@ -391,29 +480,59 @@ void orc_couple(const orc_box* p, const double* n, double* x, double* v, double*
     }
     /* MD impulse -> lattice units: p_lat = p_MD * tau_lb / (m_unit * a) */
     for (long q = 0; q < 3 * V; q++) dp[q] *= p->tau_lb;
-    free(Fc);
-    free(u);
+}
+
+void orc_couple(const orc_box* p, const double* n, double* x, double* v, double* f, double* fc, uint32_t t,
+                double* dp)
+{
+    couple<double>(p, theta_of<double>(p), n, x, v, f, fc, t, dp);
 }
 
 /* n_steps full steps from step index t0: couple (if there are beads), then
  * collide+stream.  vel_hist (nullable) receives the bead velocities at the end
  * of each step, [n_steps][N][3]. */
-void orc_run(const orc_box* p, double* n, double* x, double* v, double* f, double* fc,
-             uint32_t t0, int32_t n_steps, double* vel_hist)
+template <class T>
+static void run(const orc_box* p, const Theta<T>& th, T* n, T* x, T* v, T* f, T* fc, uint32_t t0,
+                int32_t n_steps, T* vel_hist)
 {
     build_tables();
     const long V = (long)p->L * p->L * p->L;
-    double* tmp = (double*)malloc(sizeof(double) * 19 * V);
-    double* dp = p->N > 0 ? (double*)malloc(sizeof(double) * 3 * V) : NULL;
+    std::vector<T> tmp(19 * V);
+    std::vector<T> dp(p->N > 0 ? 3 * V : 0);
     for (int32_t s = 0; s < n_steps; s++) {
         uint32_t t = t0 + (uint32_t)s;
-        if (p->N > 0) orc_couple(p, n, x, v, f, fc, t, dp);
-        orc_collide_stream(p, n, tmp, dp, t);
-        memcpy(n, tmp, sizeof(double) * 19 * V);
-        if (vel_hist) memcpy(vel_hist + (size_t)s * 3 * p->N, v, sizeof(double) * 3 * p->N);
+        if (p->N > 0) couple<T>(p, th, n, x, v, f, fc, t, dp.data());
+        collide_stream<T>(p, th, n, tmp.data(), p->N > 0 ? dp.data() : nullptr, t);
+        for (long q = 0; q < 19 * V; q++) n[q] = tmp[q];
+        if (vel_hist)
+            for (int q = 0; q < 3 * p->N; q++) vel_hist[(size_t)s * 3 * p->N + q] = v[q];
     }
-    free(dp);
-    free(tmp);
+}
+
+void orc_run(const orc_box* p, double* n, double* x, double* v, double* f, double* fc, uint32_t t0,
+             int32_t n_steps, double* vel_hist)
+{
+    run<double>(p, theta_of<double>(p), n, x, v, f, fc, t0, n_steps, vel_hist);
+}
+
+/* Forward-mode tangent of a window of n_steps steps from the given state (the
+ * state itself does not depend on the rates): advances the state in place
+ * exactly as orc_run does, fills vel_hist [n_steps][N][3] and its derivatives
+ * dvel [n_steps][N][3][3] with respect to (omega_shear, omega_bulk, zeta). */
+void orc_window_tangent(const orc_box* p, double* n, double* x, double* v, double* f, double* fc, uint32_t t0,
+                        int32_t n_steps, double* vel_hist, double* dvel)
+{
+    const long V = (long)p->L * p->L * p->L;
+    const int N = p->N;
+    std::vector<D3> nd(n, n + 19 * V), xd(x, x + 3 * N), vd(v, v + 3 * N), fd(f, f + 3 * N),
+        fcd(fc, fc + 3 * N), hd((size_t)n_steps * 3 * N);
+    run<D3>(p, theta_of<D3>(p), nd.data(), xd.data(), vd.data(), fd.data(), fcd.data(), t0, n_steps, hd.data());
+    for (long q = 0; q < 19 * V; q++) n[q] = nd[q].v;
+    for (int q = 0; q < 3 * N; q++) { x[q] = xd[q].v; v[q] = vd[q].v; f[q] = fd[q].v; fc[q] = fcd[q].v; }
+    for (size_t q = 0; q < (size_t)n_steps * 3 * N; q++) {
+        vel_hist[q] = hd[q].v;
+        for (int k = 0; k < 3; k++) dvel[3 * q + k] = hd[q].d[k];
+    }
 }
 
 /* Observables, FP64, fixed summation order.  Layout of out[]:

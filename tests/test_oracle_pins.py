@@ -432,3 +432,40 @@ def test_bead_equipartition(orc):
     h = st.run(6000, record_velocities=True)
     v2 = np.mean(h[:, 0, :] ** 2) * p["mass"]
     assert v2 == pytest.approx(kT, rel=0.04)
+
+
+# ---------------------------------------------------------- window tangent --
+def test_window_tangent_values_equal_run(orc):
+    """The dual-number instantiation performs the same value arithmetic."""
+    L, N = 6, 4
+    bx, p = mkbox(orc, L=L, N=N, kT=1e-2, omega_s=1.2, omega_b=0.9)
+    n0 = _rand_state(orc, L, 0.02, 7)
+    x0 = lbinputs.saw_chain(N, L, 7)
+    a = orc.State(bx, n0, x0)
+    b = a.copy()
+    h = a.run(6, record_velocities=True)
+    hv, dh = b.window_tangent(6)
+    assert np.array_equal(h, hv) and np.array_equal(a.n, b.n) and np.array_equal(a.x, b.x)
+
+
+def test_window_tangent_matches_finite_differences(orc):
+    """d v(t) / d(omega_shear, omega_bulk, zeta) by forward mode equals central
+    differences of the oracle's own window."""
+    L, N, T = 6, 4, 8
+    base = dict(L=L, N=N, kT=1e-2, omega_s=1.2, omega_b=0.9, zeta=20.0)
+    n0 = _rand_state(orc, L, 0.02, 8)
+    x0 = lbinputs.saw_chain(N, L, 8)
+    bx, p = mkbox(orc, **base)
+    _, dh = orc.State(bx, n0, x0).window_tangent(T)
+    for k, name in enumerate(("omega_s", "omega_b", "zeta")):
+        hstep = 1e-6 * base[name]
+        res = []
+        for sgn in (+1, -1):
+            kw = dict(base)
+            kw[name] = base[name] + sgn * hstep
+            b2, _ = mkbox(orc, **kw)
+            res.append(orc.State(b2, n0, x0).run(T, record_velocities=True))
+        fd = (res[0] - res[1]) / (2 * hstep)
+        scale = np.max(np.abs(fd))
+        assert scale > 0
+        np.testing.assert_allclose(dh[..., k], fd, rtol=0, atol=1e-5 * scale)
