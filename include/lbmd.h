@@ -161,6 +161,30 @@ lb_status lb_velocity_history(lb_handle* h, int64_t step, double* host_out, size
  * graph and replays it; 0 launches kernels directly. */
 lb_status lb_set_launch(lb_handle* h, int32_t batched, int32_t graph_steps);
 
+/* ---- adjoint window (gradient of a loss of the bead velocities) ----------
+ * The loss is any function J of the bead velocities recorded at the end of
+ * each LB step of a window of T steps.  lb_window_backward returns, per box,
+ * dJ/d(omega_shear, omega_bulk, zeta), the rates that set the fluid's shear
+ * and bulk viscosity and the bead friction (Sec. II.B: relaxation of the
+ * stress modes, coupling friction).  It reverses collide+stream and the
+ * chain's coupling step by step by hand-written adjoint kernels, replaying
+ * the noise from Philox, and rebuilds forward states from checkpoints taken
+ * every k steps.  Chains of at most 256 beads.  The workspace d_ws is device
+ * memory owned by the caller, lb_window_bytes(h, T, k) bytes, 256-aligned,
+ * kept unchanged between the forward and backward calls. */
+size_t lb_window_bytes(const lb_handle* h, int32_t T, int32_t k);
+/* Run T steps from the current state, checkpointing every k steps; bead
+ * velocities after each step go to vhist_host [T][sum N][3] (may be NULL). */
+lb_status lb_window_forward(lb_handle* h, void* d_ws, size_t bytes, int32_t T, int32_t k, double* vhist_host);
+/* dj_host [T][sum N][3] = dJ/dv; grad_host [n_boxes][3].  Leaves the state at
+ * the end of the window.  LB_ESTATE without a recorded forward window. */
+lb_status lb_window_backward(lb_handle* h, void* d_ws, size_t bytes, const double* dj_host, double* grad_host);
+/* Restore the state at the start of the recorded window. */
+lb_status lb_window_rewind(lb_handle* h, void* d_ws, size_t bytes);
+/* Change a box's shear and bulk rates and bead friction (same ranges as in
+ * lb_box_desc). */
+lb_status lb_set_rates(lb_handle* h, int32_t box, double omega_shear, double omega_bulk, double zeta);
+
 /* Benchmark aid: enqueue n launches of the fused collide+stream kernel of
  * every box from the current state into the other buffer, with no impulses
  * and without advancing the state (the other buffer is overwritten by the

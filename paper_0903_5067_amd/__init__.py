@@ -81,13 +81,20 @@ def lib() -> ctypes.CDLL:
         L.lb_collide_only.argtypes = [vp, i32]
         L.lb_stream.argtypes = [vp]
         L.lb_stream.restype = vp
+        L.lb_window_bytes.argtypes = [vp, i32, i32]
+        L.lb_window_bytes.restype = sz
+        L.lb_window_forward.argtypes = [vp, vp, sz, i32, i32, ctypes.POINTER(ctypes.c_double)]
+        L.lb_window_backward.argtypes = [vp, vp, sz, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double)]
+        L.lb_window_rewind.argtypes = [vp, vp, sz]
+        L.lb_set_rates.argtypes = [vp, i32, ctypes.c_double, ctypes.c_double, ctypes.c_double]
         L.lb_free.argtypes = [vp]
         L.lb_free.restype = None
         L.lb_last_error.argtypes = [vp]
         L.lb_last_error.restype = ctypes.c_char_p
         for name in ("lb_query_sizes", "lb_init", "lb_couple", "lb_step", "lb_observables",
                      "lb_export_state", "lb_import_state", "lb_pending_impulse",
-                     "lb_velocity_history", "lb_set_launch", "lb_collide_only"):
+                     "lb_velocity_history", "lb_set_launch", "lb_collide_only", "lb_window_forward",
+                     "lb_window_backward", "lb_window_rewind", "lb_set_rates"):
             getattr(L, name).restype = ctypes.c_int
         _lib = L
     return _lib
@@ -234,6 +241,35 @@ class LBSystem:
         _check(lib().lb_velocity_history(self.h, int(step), buf.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
                                          buf.nbytes), self.h)
         return buf[: self.n_beads]
+
+    # -- adjoint window ---------------------------------------------------
+    def set_rates(self, box: int, omega_shear: float, omega_bulk: float, zeta: float):
+        _check(lib().lb_set_rates(self.h, int(box), float(omega_shear), float(omega_bulk), float(zeta)), self.h)
+        b = self.boxes[box]
+        b["omega_s"], b["omega_b"], b["zeta"] = float(omega_shear), float(omega_bulk), float(zeta)
+
+    def window_forward(self, T: int, k: int) -> np.ndarray:
+        """T steps with checkpoints every k; bead velocities after each step [T, sum N, 3]."""
+        import torch
+        need = lib().lb_window_bytes(self.h, int(T), int(k))
+        if getattr(self, "_ws", None) is None or self._ws.numel() < need:
+            self._ws = torch.empty(need, dtype=torch.uint8, device=self.device)
+        vh = np.zeros((T, max(self.n_beads, 1), 3))
+        _check(lib().lb_window_forward(self.h, ctypes.c_void_p(self._ws.data_ptr()), self._ws.numel(), int(T), int(k),
+                                       vh.ctypes.data_as(ctypes.POINTER(ctypes.c_double))), self.h)
+        return vh[:, : self.n_beads]
+
+    def window_backward(self, dj_dv: np.ndarray) -> np.ndarray:
+        """dJ/dv [T, sum N, 3] -> dJ/d(omega_shear, omega_bulk, zeta) per box [n_boxes, 3]."""
+        dj = np.ascontiguousarray(dj_dv, dtype=np.float64)
+        grad = np.zeros((len(self.boxes), 3))
+        _check(lib().lb_window_backward(self.h, ctypes.c_void_p(self._ws.data_ptr()), self._ws.numel(),
+                                        dj.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
+                                        grad.ctypes.data_as(ctypes.POINTER(ctypes.c_double))), self.h)
+        return grad
+
+    def window_rewind(self):
+        _check(lib().lb_window_rewind(self.h, ctypes.c_void_p(self._ws.data_ptr()), self._ws.numel()), self.h)
 
     def close(self):
         if getattr(self, "h", None):

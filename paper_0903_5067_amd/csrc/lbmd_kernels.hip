@@ -107,6 +107,8 @@ struct ChainArgs {
     int touch_cap;             // slots per bead: 8 x (substeps + 1), one stencil change per substep at most
     uint32_t* nl_rebuilds;     // per box: neighbour-list builds so far (diagnostic)
     double* vhist; int hist_len; uint64_t total_beads;
+    double* tape;              // non-null while replaying a window segment: per substep and bead,
+                               // TAPE_REC doubles (see k_couple)
 };
 
 // node velocities (MD units) of the 8 stencil nodes from the frozen populations;
@@ -405,6 +407,17 @@ __global__ __launch_bounds__(MAXT) void k_couple(const BoxDev* __restrict__ boxe
             }
             const U4 w = philox10(U4{(uint32_t)b, t, (1u << 16) | (uint32_t)s, 0u}, bx.seed, bx.box_id);
             const uint32_t ws[3] = {w.x, w.y, w.z};
+            double* tp = (ca.tape && lane == 0) ? ca.tape + ((uint64_t)s * ca.total_beads + g) * TAPE_REC : nullptr;
+            if (tp) {   // substep record for the adjoint: x1, v1, fc, base cell, fractions, node velocities
+#pragma unroll
+                for (int c = 0; c < 3; ++c) {
+                    tp[c] = x[c]; tp[3 + c] = v[c]; tp[9 + c] = (double)i0[c]; tp[12 + c] = fr[c];
+                }
+#pragma unroll
+                for (int k = 0; k < 8; ++k)
+#pragma unroll
+                    for (int c = 0; c < 3; ++c) tp[15 + 3 * k + c] = (double)cu[k][c];
+            }
 #pragma unroll
             for (int c = 0; c < 3; ++c) {
                 const double ffr = -bx.zeta * (v[c] - ub[c]);
@@ -413,6 +426,7 @@ __global__ __launch_bounds__(MAXT) void k_couple(const BoxDev* __restrict__ boxe
                 f[c] = F[c] + fcl[c];
                 v[c] += f[c] * hdt_m;
             }
+            if (tp) { tp[6] = fcl[0]; tp[7] = fcl[1]; tp[8] = fcl[2]; }
 #pragma unroll
             for (int k = 0; k < 8; ++k) {
                 acc[k][0] -= wt[k] * fcl[0] * dt;
@@ -841,7 +855,7 @@ __global__ __launch_bounds__(256) void k_chain_obs(const BoxDev* __restrict__ bo
 static ChainArgs chain_args(const LaunchCtx& c)
 {
     return ChainArgs{c.x, c.v, c.f, c.fc, c.nl_cnt, c.nl_idx, c.nl_x0, c.nl_cap, c.imp, c.touched,
-                     c.touched_cnt, c.touch_cap, c.nl_rebuilds, c.vhist, c.hist_len, c.total_beads};
+                     c.touched_cnt, c.touch_cap, c.nl_rebuilds, c.vhist, c.hist_len, c.total_beads, c.tape};
 }
 
 template <typename R>
@@ -919,6 +933,400 @@ hipError_t launch_chain_obs(const LaunchCtx& c, double* out)
     hipLaunchKernelGGL(k_chain_obs, dim3(c.n_boxes), dim3(256), 0, c.stream, c.boxes, chain_args(c), out);
     return hipGetLastError();
 }
+
+
+// =================================================================== adjoint
+// Reverse sweep of one LB step for the gradient of a loss of the bead
+// velocities with respect to (omega_shear, omega_bulk, zeta).  The forward
+// state of the step (pre-collision populations in the stored pull layout, the
+// node impulses, the substep tape of the chain) comes from replaying the
+// window segment; noise words are regenerated from Philox.  Adjoints are FP64.
+//   lam_n[i * nodes + node]   adjoint of the pre-collision population n_i
+//   lam_dp[c * nodes + node]  adjoint of the lattice impulse handed to a node
+
+// VJP of one node's collision: given lam_o = dJ/d(post-collision d*), return
+// lam_d = dJ/d(pre-collision d), lam_f = dJ/d(impulse), and the contributions
+// to dJ/d(omega_s), dJ/d(omega_b).
+__device__ __forceinline__ void collide_vjp(const double d[19], const double f[3], const CollideConst<double>& cc,
+                                            uint32_t node, uint32_t step, uint32_t k0, uint32_t k1,
+                                            const double lam_o[19], double lam_d[19], double lam_f[3],
+                                            double& g_ws, double& g_wb)
+{
+    double m[19];
+    to_modes<double>(d, m);
+    const double rho = cc.rho0 + m[0], irho = 1.0 / rho;
+    const double u[3] = {(m[1] + 0.5 * f[0]) * irho, (m[2] + 0.5 * f[1]) * irho, (m[3] + 0.5 * f[2]) * irho};
+    const double e[10] = {0, 0, 0, 0, rho * (u[0] * u[0] + u[1] * u[1] + u[2] * u[2]),
+                          rho * (2 * u[0] * u[0] - u[1] * u[1] - u[2] * u[2]), rho * (u[1] * u[1] - u[2] * u[2]),
+                          rho * u[0] * u[1], rho * u[1] * u[2], rho * u[0] * u[2]};
+    const double uf[3] = {u[0] * f[0], u[1] * f[1], u[2] * f[2]};
+    const double sv[10] = {0, 0, 0, 0, 2 * (uf[0] + uf[1] + uf[2]), 2 * (2 * uf[0] - uf[1] - uf[2]), 2 * (uf[1] - uf[2]),
+                           u[0] * f[1] + u[1] * f[0], u[1] * f[2] + u[2] * f[1], u[0] * f[2] + u[2] * f[0]};
+    double r[19];
+#pragma unroll
+    for (int k = 0; k < 19; ++k) r[k] = 0.0;
+    const double a = cc.therm > 0 ? sqrt(cc.mu * rho) : 0.0;
+    if (cc.therm > 0) {
+        const U4 w0 = philox10(U4{node, step, 0u, 0u}, k0, k1), w1 = philox10(U4{node, step, 0u, 1u}, k0, k1);
+        r[4] = unit_noise<double>(w0.x); r[5] = unit_noise<double>(w0.y); r[6] = unit_noise<double>(w0.z);
+        r[7] = unit_noise<double>(w0.w); r[8] = unit_noise<double>(w1.x); r[9] = unit_noise<double>(w1.y);
+        if (cc.therm > 1) {
+            const U4 w2 = philox10(U4{node, step, 0u, 2u}, k0, k1), w3 = philox10(U4{node, step, 0u, 3u}, k0, k1);
+            r[10] = unit_noise<double>(w1.z); r[11] = unit_noise<double>(w1.w);
+            r[12] = unit_noise<double>(w2.x); r[13] = unit_noise<double>(w2.y); r[14] = unit_noise<double>(w2.z);
+            r[15] = unit_noise<double>(w2.w); r[16] = unit_noise<double>(w3.x); r[17] = unit_noise<double>(w3.y);
+            r[18] = unit_noise<double>(w3.z);
+        }
+    }
+    // d* = w_i sum_k e_ki M_k  ->  lam_M = E (w o lam_o)
+    double wl[19], lM[19];
+#pragma unroll
+    for (int i = 0; i < 19; ++i) wl[i] = wv(i) * lam_o[i];
+    to_modes<double>(wl, lM);
+    double lm[19];
+#pragma unroll
+    for (int k = 0; k < 19; ++k) lm[k] = 0.0;
+    double lu[3] = {0, 0, 0}, lrho = 0.0, la = 0.0, lgs = 0.0, lgb = 0.0;
+    lam_f[0] = lam_f[1] = lam_f[2] = 0.0;
+    lm[0] += lM[0];
+#pragma unroll
+    for (int c = 0; c < 3; ++c) { lm[1 + c] += 3.0 * lM[1 + c]; lam_f[c] += 3.0 * lM[1 + c]; }
+    double le[10], ls[10];
+#pragma unroll
+    for (int k = 4; k <= 9; ++k) {
+        const double gam = k == 4 ? cc.gb : cc.gs, h = k == 4 ? cc.hb : cc.hs;
+        const double lP = lM[k] * inv_b<double>(k);
+        lm[k] += gam * lP;
+        le[k] = (1.0 - gam) * lP;
+        ls[k] = h * lP;
+        double lg = (m[k] - e[k]) * lP + 0.5 * sv[k] * lP;
+        if (cc.therm > 0 && cc.q[k] > 0.0) lg += a * r[k] * (-gam * inv_b<double>(k) / cc.q[k]) * lM[k];
+        la += cc.q[k] * r[k] * lM[k];
+        if (k == 4) lgb += lg; else lgs += lg;
+    }
+#pragma unroll
+    for (int k = 10; k < 19; ++k) {
+        lm[k] += cc.gg * inv_b<double>(k) * lM[k];
+        la += cc.q[k] * r[k] * lM[k];
+    }
+    // equilibrium stress modes e_k(rho, u)
+    lrho += (le[4] * e[4] + le[5] * e[5] + le[6] * e[6] + le[7] * e[7] + le[8] * e[8] + le[9] * e[9]) * irho;
+    lu[0] += rho * (2 * u[0] * le[4] + 4 * u[0] * le[5] + u[1] * le[7] + u[2] * le[9]);
+    lu[1] += rho * (2 * u[1] * le[4] - 2 * u[1] * le[5] + 2 * u[1] * le[6] + u[0] * le[7] + u[2] * le[8]);
+    lu[2] += rho * (2 * u[2] * le[4] - 2 * u[2] * le[5] - 2 * u[2] * le[6] + u[1] * le[8] + u[0] * le[9]);
+    // source terms s_k(u, f)
+    lu[0] += 2 * f[0] * ls[4] + 4 * f[0] * ls[5] + f[1] * ls[7] + f[2] * ls[9];
+    lu[1] += 2 * f[1] * ls[4] - 2 * f[1] * ls[5] + 2 * f[1] * ls[6] + f[0] * ls[7] + f[2] * ls[8];
+    lu[2] += 2 * f[2] * ls[4] - 2 * f[2] * ls[5] - 2 * f[2] * ls[6] + f[1] * ls[8] + f[0] * ls[9];
+    lam_f[0] += 2 * u[0] * ls[4] + 4 * u[0] * ls[5] + u[1] * ls[7] + u[2] * ls[9];
+    lam_f[1] += 2 * u[1] * ls[4] - 2 * u[1] * ls[5] + 2 * u[1] * ls[6] + u[0] * ls[7] + u[2] * ls[8];
+    lam_f[2] += 2 * u[2] * ls[4] - 2 * u[2] * ls[5] - 2 * u[2] * ls[6] + u[1] * ls[8] + u[0] * ls[9];
+    // a = sqrt(mu rho)
+    if (a > 0.0) lrho += la * a * 0.5 * irho;
+    // u = (j + f/2) / rho
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+        lm[1 + c] += lu[c] * irho;
+        lam_f[c] += 0.5 * lu[c] * irho;
+    }
+    lrho -= (u[0] * lu[0] + u[1] * lu[1] + u[2] * lu[2]) * irho;
+    lm[0] += lrho;
+    // m = E d  ->  lam_d = E^T lam_m
+    from_scaled_modes<double>(lm, lam_d);
+#pragma unroll
+    for (int i = 0; i < 19; ++i) lam_d[i] /= wv(i);
+    // gamma = 1 - omega
+    g_ws = -lgs;
+    g_wb = -lgb;
+}
+
+// One thread per node: lam_d*(r) is gathered from lam_n_next at the nodes the
+// populations stream to (r + c_i); the forward state is the replayed
+// pre-collision state.  Writes lam_n_cur and lam_dp; adds the tile's rate
+// gradient to gpart[tile][2].
+template <typename R>
+__global__ __launch_bounds__(256) void k_adj_collide(const BoxDev* __restrict__ boxes,
+                                                     const CollideConst<double>* __restrict__ ccd,
+                                                     const uint32_t* __restrict__ tile_box,
+                                                     const R* __restrict__ P, const unsigned long long* __restrict__ imp,
+                                                     const double* __restrict__ lam_next, double* __restrict__ lam_cur,
+                                                     double* __restrict__ lam_dp, double* __restrict__ gpart,
+                                                     uint64_t nodes, uint32_t step)
+{
+    __shared__ double red[2][256];
+    const uint32_t tile = blockIdx.x;
+    const int bi = (int)tile_box[tile];
+    const BoxDev& bx = boxes[bi];
+    const int L = bx.L;
+    const uint32_t V = (uint32_t)L * L * L;
+    const uint32_t r = (tile - bx.tile_begin) * 256u + threadIdx.x;
+    double gws = 0.0, gwb = 0.0;
+    if (r < V) {
+        const Upwind up = upwind_of(r, L, bx.inv_L);
+        R dr[19];
+        gather_pre<R, false>(P + bx.pop_off, bx.ps, up, dr);
+        double d[19], f[3] = {0, 0, 0};
+#pragma unroll
+        for (int i = 0; i < 19; ++i) d[i] = (double)dr[i];
+        const uint64_t gn = bx.node_off + r;
+        if (bx.N > 0)
+#pragma unroll
+            for (int c = 0; c < 3; ++c) f[c] = (double)(long long)imp[3 * gn + c] * IMP_INV_SCALE;
+        // the population leaving r along c_i arrives at r + c_i
+        uint32_t x, y;
+        const uint32_t q = div_L(r, L, bx.inv_L, &x);
+        const uint32_t z = div_L(q, L, bx.inv_L, &y);
+        const uint32_t Xd[3] = {x == 0 ? L - 1 : x - 1, x, x + 1 == (uint32_t)L ? 0 : x + 1};
+        const uint32_t Yd[3] = {y == 0 ? L - 1 : y - 1, y, y + 1 == (uint32_t)L ? 0 : y + 1};
+        const uint32_t Zd[3] = {z == 0 ? L - 1 : z - 1, z, z + 1 == (uint32_t)L ? 0 : z + 1};
+        double lo[19];
+#pragma unroll
+        for (int i = 0; i < 19; ++i) {
+            const uint32_t dn = Xd[cxv(i) + 1] + (uint32_t)L * (Yd[cyv(i) + 1] + (uint32_t)L * Zd[czv(i) + 1]);
+            lo[i] = lam_next[i * nodes + bx.node_off + dn];
+        }
+        double ld[19], lf[3];
+        collide_vjp(d, f, ccd[bi], r, step, bx.seed, bx.box_id, lo, ld, lf, gws, gwb);
+#pragma unroll
+        for (int i = 0; i < 19; ++i) lam_cur[i * nodes + gn] = ld[i];
+#pragma unroll
+        for (int c = 0; c < 3; ++c) lam_dp[c * nodes + gn] = lf[c];
+    }
+    red[0][threadIdx.x] = gws;
+    red[1][threadIdx.x] = gwb;
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+        if ((int)threadIdx.x < w) {
+            red[0][threadIdx.x] += red[0][threadIdx.x + w];
+            red[1][threadIdx.x] += red[1][threadIdx.x + w];
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        gpart[2 * (uint64_t)tile] += red[0][0];
+        gpart[2 * (uint64_t)tile + 1] += red[1][0];
+    }
+}
+
+// add dJ/dv(end of step) and reverse the chain's substeps of one LB step; one
+// workgroup per chain (at most 256 beads), thread per bead.
+struct AdjChainArgs {
+    const double* x0; const double* v0; const double* f0;   // bead state at the step start (replayed)
+    const double* tape;                                     // [substep][total beads][TAPE_REC]
+    const double* dj;                                       // dJ/dv at the step end [total beads][3]
+    double* lx; double* lv; double* lf;                     // bead adjoints, in: step end, out: step start
+    double* lam_n;                                          // pre-collision population adjoint (accumulated)
+    const double* lam_dp;
+    double* gz;                                             // per box dJ/dzeta
+    uint64_t nodes, total_beads;
+};
+
+__device__ __forceinline__ void pair_kernel(const double d[3], double g, double gp, const double v[3], double out[3])
+{
+    // (g I + 2 g' d d^T) v
+    const double dv = 2.0 * gp * (d[0] * v[0] + d[1] * v[1] + d[2] * v[2]);
+    out[0] += g * v[0] + dv * d[0];
+    out[1] += g * v[1] + dv * d[1];
+    out[2] += g * v[2] + dv * d[2];
+}
+
+template <typename R>
+__global__ __launch_bounds__(256) void k_adj_couple(const BoxDev* __restrict__ boxes,
+                                                    const int32_t* __restrict__ couple_list, const R* __restrict__ P,
+                                                    AdjChainArgs aa, uint32_t step)
+{
+    __shared__ double xs[3 * 256], lF[3 * 256], red[256];
+    const int bi = couple_list[blockIdx.x];
+    const BoxDev& bx = boxes[bi];
+    const int N = bx.N, b = threadIdx.x, S = bx.substeps, L = bx.L;
+    const bool act = b < N;
+    const uint64_t g = bx.bead_off + (uint64_t)(act ? b : 0);
+    const double dt = bx.dt, h = 0.5 * dt / bx.mass, tau = bx.tau_lb, Ld = (double)L, iL = bx.inv_L;
+    const double eps24 = 24.0 * bx.eps, s6c = bx.sigsq * bx.sigsq * bx.sigsq, s12c = s6c * s6c;
+    double lx[3] = {0, 0, 0}, lv[3] = {0, 0, 0}, lf[3] = {0, 0, 0};
+    if (act)
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            lx[c] = aa.lx[3 * g + c]; lv[c] = aa.lv[3 * g + c] + aa.dj[3 * g + c]; lf[c] = aa.lf[3 * g + c];
+        }
+    double gz = 0.0;
+    int cb[3] = {-1, -1, -1};
+    double lcu[8][3];          // accumulated adjoint of the stencil's node velocities
+    double rho_k[8];
+    uint32_t cnode[8];
+    double cuk[8][3];
+    bool have = false;
+    const R* pb = P + bx.pop_off;
+    auto flush = [&]() {       // node velocity adjoint -> population adjoint at the stencil nodes
+#pragma unroll
+        for (int k = 0; k < 8; ++k) {
+            const double ir = 1.0 / (rho_k[k] * tau);
+            const double ul[3] = {cuk[k][0] * tau, cuk[k][1] * tau, cuk[k][2] * tau};
+            for (int i = 0; i < 19; ++i) {
+                const double cc = (double)cxv(i) * lcu[k][0] + (double)cyv(i) * lcu[k][1] + (double)czv(i) * lcu[k][2];
+                const double lsum = lcu[k][0] * ul[0] + lcu[k][1] * ul[1] + lcu[k][2] * ul[2];
+                atomicAdd(&aa.lam_n[i * aa.nodes + bx.node_off + cnode[k]], (cc - lsum) * ir);
+            }
+        }
+    };
+    for (int s = S - 1; s >= 0; --s) {
+        const double* tp = aa.tape + ((uint64_t)s * aa.total_beads + g) * TAPE_REC;
+        double x1[3] = {0, 0, 0}, v1[3] = {0, 0, 0}, fc[3] = {0, 0, 0}, fr[3] = {0, 0, 0};
+        int i0[3] = {0, 0, 0};
+        if (act)
+#pragma unroll
+            for (int c = 0; c < 3; ++c) {
+                x1[c] = tp[c]; v1[c] = tp[3 + c]; fc[c] = tp[6 + c]; i0[c] = (int)tp[9 + c]; fr[c] = tp[12 + c];
+            }
+        if (act) { xs[3 * b] = x1[0]; xs[3 * b + 1] = x1[1]; xs[3 * b + 2] = x1[2]; }
+        // v' = v1 + f' h and f' = F_c + fc
+        double lft[3], lv1[3], lfc[3];
+#pragma unroll
+        for (int c = 0; c < 3; ++c) { lft[c] = lf[c] + h * lv[c]; lv1[c] = lv[c]; lfc[c] = lft[c]; }
+        if (act) { lF[3 * b] = lft[0]; lF[3 * b + 1] = lft[1]; lF[3 * b + 2] = lft[2]; }
+        __syncthreads();
+        double lx1[3] = {lx[0], lx[1], lx[2]};
+        if (act) {
+            // stencil of this substep
+            if (i0[0] != cb[0] || i0[1] != cb[1] || i0[2] != cb[2]) {
+                if (have) flush();
+#pragma unroll
+                for (int k = 0; k < 8; ++k) {
+                    const int ix = i0[0] + (k & 1), iy = i0[1] + ((k >> 1) & 1), iz = i0[2] + ((k >> 2) & 1);
+                    const uint32_t nx = ix >= L ? ix - L : ix, ny = iy >= L ? iy - L : iy, nz = iz >= L ? iz - L : iz;
+                    cnode[k] = nx + (uint32_t)L * (ny + (uint32_t)L * nz);
+                    const Upwind up(nx, ny, nz, (uint32_t)L);
+                    R dn[19];
+                    gather_pre<R, false>(pb, bx.ps, up, dn);
+                    double rho = 0.0;
+                    for (int i = 0; i < 19; ++i) rho += (double)dn[i];
+                    rho_k[k] = rho + bx.rho0;
+#pragma unroll
+                    for (int c = 0; c < 3; ++c) { cuk[k][c] = tp[15 + 3 * k + c]; lcu[k][c] = 0.0; }
+                }
+                cb[0] = i0[0]; cb[1] = i0[1]; cb[2] = i0[2];
+                have = true;
+            }
+            double wt[8], ub[3] = {0, 0, 0};
+#pragma unroll
+            for (int k = 0; k < 8; ++k) {
+                wt[k] = ((k & 1) ? fr[0] : 1.0 - fr[0]) * (((k >> 1) & 1) ? fr[1] : 1.0 - fr[1]) *
+                        (((k >> 2) & 1) ? fr[2] : 1.0 - fr[2]);
+                ub[0] += wt[k] * cuk[k][0]; ub[1] += wt[k] * cuk[k][1]; ub[2] += wt[k] * cuk[k][2];
+            }
+            // impulse spread: acc_k -= w_k fc dt, handed over as tau * acc
+            double lw[8];
+#pragma unroll
+            for (int k = 0; k < 8; ++k) {
+                const uint64_t gn = bx.node_off + cnode[k];
+                const double la0 = tau * aa.lam_dp[gn], la1 = tau * aa.lam_dp[aa.nodes + gn],
+                             la2 = tau * aa.lam_dp[2 * aa.nodes + gn];
+                lfc[0] -= dt * wt[k] * la0; lfc[1] -= dt * wt[k] * la1; lfc[2] -= dt * wt[k] * la2;
+                lw[k] = -dt * (fc[0] * la0 + fc[1] * la1 + fc[2] * la2);
+            }
+            // fc = -zeta (v1 - u_b) + A(zeta) r
+            const U4 w = philox10(U4{(uint32_t)b, step, (1u << 16) | (uint32_t)s, 0u}, bx.seed, bx.box_id);
+            const double rn[3] = {unit_noise<double>(w.x), unit_noise<double>(w.y), unit_noise<double>(w.z)};
+            double lub[3];
+#pragma unroll
+            for (int c = 0; c < 3; ++c) {
+                if (bx.zeta > 0.0) gz += 0.5 * bx.bead_noise / bx.zeta * rn[c] * lfc[c];
+                gz -= (v1[c] - ub[c]) * lfc[c];
+                lv1[c] -= bx.zeta * lfc[c];
+                lub[c] = bx.zeta * lfc[c];
+            }
+            // u_b = sum_k w_k cu_k
+#pragma unroll
+            for (int k = 0; k < 8; ++k) {
+                lw[k] += cuk[k][0] * lub[0] + cuk[k][1] * lub[1] + cuk[k][2] * lub[2];
+                lcu[k][0] += wt[k] * lub[0]; lcu[k][1] += wt[k] * lub[1]; lcu[k][2] += wt[k] * lub[2];
+            }
+            // trilinear weights w_k(fractions of x1)
+#pragma unroll
+            for (int k = 0; k < 8; ++k) {
+                const double g0 = (k & 1) ? fr[0] : 1.0 - fr[0], g1 = ((k >> 1) & 1) ? fr[1] : 1.0 - fr[1],
+                             g2 = ((k >> 2) & 1) ? fr[2] : 1.0 - fr[2];
+                lx1[0] += lw[k] * ((k & 1) ? 1.0 : -1.0) * g1 * g2;
+                lx1[1] += lw[k] * (((k >> 1) & 1) ? 1.0 : -1.0) * g0 * g2;
+                lx1[2] += lw[k] * (((k >> 2) & 1) ? 1.0 : -1.0) * g0 * g1;
+            }
+            // conservative forces at x1: lam_x1_b += sum_j K_bj (lam_F_b - lam_F_j)
+            for (int j = 0; j < N; ++j) {
+                if (j == b) continue;
+                const double dl[3] = {lft[0] - lF[3 * j], lft[1] - lF[3 * j + 1], lft[2] - lF[3 * j + 2]};
+                if (j == b - 1 || j == b + 1) {
+                    const double d[3] = {x1[0] - xs[3 * j], x1[1] - xs[3 * j + 1], x1[2] - xs[3 * j + 2]};
+                    const double r2 = d[0] * d[0] + d[1] * d[1] + d[2] * d[2];
+                    const double den = 1.0 - r2 * bx.inv_r0sq;
+                    const double gfe = -bx.k_fene / den;
+                    const double gpe = -bx.k_fene * bx.inv_r0sq / (den * den);
+                    pair_kernel(d, gfe, gpe, dl, lx1);
+                }
+                double d[3] = {x1[0] - xs[3 * j], x1[1] - xs[3 * j + 1], x1[2] - xs[3 * j + 2]};
+                d[0] -= Ld * rint(d[0] * iL); d[1] -= Ld * rint(d[1] * iL); d[2] -= Ld * rint(d[2] * iL);
+                const double q = d[0] * d[0] + d[1] * d[1] + d[2] * d[2];
+                if (q < bx.rc2) {
+                    const double iq = 1.0 / q, iq4 = iq * iq * iq * iq, iq7 = iq4 * iq * iq * iq;
+                    const double gw = eps24 * (2.0 * s12c * iq7 - s6c * iq4);
+                    const double gpw = eps24 * (-14.0 * s12c * iq7 * iq + 4.0 * s6c * iq4 * iq);
+                    pair_kernel(d, gw, gpw, dl, lx1);
+                }
+            }
+        }
+        // x1 = x + v1 dt,  v1 = v + f h
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            lv1[c] += dt * lx1[c];
+            lx[c] = lx1[c];
+            lv[c] = lv1[c];
+            lf[c] = h * lv1[c];
+        }
+        __syncthreads();
+    }
+    if (act) {
+        if (have) flush();
+#pragma unroll
+        for (int c = 0; c < 3; ++c) { aa.lx[3 * g + c] = lx[c]; aa.lv[3 * g + c] = lv[c]; aa.lf[3 * g + c] = lf[c]; }
+    }
+    red[threadIdx.x] = act ? gz : 0.0;
+    __syncthreads();
+    for (int wdt = 128; wdt > 0; wdt >>= 1) {
+        if ((int)threadIdx.x < wdt) red[threadIdx.x] += red[threadIdx.x + wdt];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) aa.gz[bi] += red[0];
+}
+
+template <typename R>
+hipError_t launch_adj_collide(const LaunchCtx& c, const void* ccd, const void* P, const unsigned long long* imp,
+                              const double* lam_next, double* lam_cur, double* lam_dp, double* gpart,
+                              uint64_t nodes, uint32_t total_tiles, uint32_t step)
+{
+    hipLaunchKernelGGL(k_adj_collide<R>, dim3(total_tiles), dim3(256), 0, c.stream, c.boxes,
+                       (const CollideConst<double>*)ccd, c.tile_box, (const R*)P, imp, lam_next, lam_cur, lam_dp,
+                       gpart, nodes, step);
+    return hipGetLastError();
+}
+
+template <typename R>
+hipError_t launch_adj_couple(const LaunchCtx& c, const int32_t* list, int n_list, const void* P,
+                             const AdjArgsHost& a, uint32_t step)
+{
+    if (n_list == 0) return hipSuccess;
+    AdjChainArgs aa{a.x0, a.v0, a.f0, a.tape, a.dj, a.lx, a.lv, a.lf, a.lam_n, a.lam_dp, a.gz, a.nodes,
+                    c.total_beads};
+    hipLaunchKernelGGL(k_adj_couple<R>, dim3(n_list), dim3(256), 0, c.stream, c.boxes, list, (const R*)P, aa, step);
+    return hipGetLastError();
+}
+
+template hipError_t launch_adj_collide<float>(const LaunchCtx&, const void*, const void*, const unsigned long long*,
+                                              const double*, double*, double*, double*, uint64_t, uint32_t, uint32_t);
+template hipError_t launch_adj_collide<double>(const LaunchCtx&, const void*, const void*, const unsigned long long*,
+                                               const double*, double*, double*, double*, uint64_t, uint32_t, uint32_t);
+template hipError_t launch_adj_couple<float>(const LaunchCtx&, const int32_t*, int, const void*, const AdjArgsHost&,
+                                             uint32_t);
+template hipError_t launch_adj_couple<double>(const LaunchCtx&, const int32_t*, int, const void*, const AdjArgsHost&,
+                                              uint32_t);
 
 template hipError_t launch_collide<float>(const LaunchCtx&, const void*, void*, int, uint32_t, uint32_t, uint32_t);
 template hipError_t launch_collide<double>(const LaunchCtx&, const void*, void*, int, uint32_t, uint32_t, uint32_t);

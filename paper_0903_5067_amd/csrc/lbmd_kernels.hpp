@@ -25,6 +25,7 @@ struct LaunchCtx {
     double *x, *v, *f, *fc;        // beads [total][3]
     int32_t* nl_cnt; uint16_t* nl_idx; double* nl_x0; int nl_cap;
     double* vhist; int hist_len; uint64_t total_beads;
+    double* tape;                  // substep tape while replaying an adjoint window segment (else null)
     // chains above 256 beads: one launch per substep over blocks of 64 beads
     const int2* big_blocks;        // (box, first bead of the block)
     double* xb;                    // [2][total beads][3] positions of the current / next substep
@@ -53,8 +54,25 @@ template <typename R>
 hipError_t launch_stats(const LaunchCtx& c, const void* A, uint32_t total_tiles, double* part, double* out);
 hipError_t launch_chain_obs(const LaunchCtx& c, double* out);
 
+// device pointers of one reverse step of the adjoint window
+struct AdjArgsHost {
+    const double *x0, *v0, *f0, *tape, *dj;
+    double *lx, *lv, *lf, *lam_n;
+    const double* lam_dp;
+    double* gz;
+    uint64_t nodes;
+};
+template <typename R>
+hipError_t launch_adj_collide(const LaunchCtx& c, const void* ccd, const void* P, const unsigned long long* imp,
+                              const double* lam_next, double* lam_cur, double* lam_dp, double* gpart,
+                              uint64_t nodes, uint32_t total_tiles, uint32_t step);
+template <typename R>
+hipError_t launch_adj_couple(const LaunchCtx& c, const int32_t* list, int n_list, const void* P,
+                             const AdjArgsHost& a, uint32_t step);
+
 constexpr int NSTAT_REC = 24;
 constexpr int NCHAIN_REC = 11;
 constexpr int NL_SLOTS = 48;
+constexpr int TAPE_REC = 40;     // doubles per bead and substep in the adjoint tape
 
 }  // namespace lbd

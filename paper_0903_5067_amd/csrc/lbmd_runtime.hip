@@ -217,6 +217,11 @@ struct lb_handle {
     hipGraphExec_t gexec[2] = {nullptr, nullptr};
     hipGraph_t graph[2] = {nullptr, nullptr};
     std::string err;
+    // adjoint window
+    int win_T = 0, win_k = 0;
+    uint64_t win_step0 = 0;
+    bool win_ready = false;        // a forward window is recorded in the workspace
+    void* ccd = nullptr;           // device CollideConst<double>[n_boxes] for the reverse sweep
 
     void* pop(int which) { return state + (which == 0 ? lo.st_popA : lo.st_popB); }
 };
@@ -752,6 +757,297 @@ lb_status lb_set_launch(lb_handle* h, int32_t batched, int32_t graph_steps)
     return LB_OK;
 }
 
+
+}  // extern "C"
+
+// ------------------------------------------------------------ adjoint window
+namespace {
+
+struct WinLayout {
+    size_t ck_pop, ck_beads, tape_pop, tape_imp, tape_sub, tape_beads, vh, dj, lam_a, lam_b, lam_dp, lbeads, gpart,
+        gz, bytes;
+    int nc;
+};
+
+WinLayout win_layout(const lb_handle* h, int T, int k)
+{
+    const Layout& lo = h->lo;
+    WinLayout w{};
+    const uint64_t nb = std::max<uint64_t>(lo.total_beads, 1), nodes = lo.total_nodes;
+    const size_t popb = lo.pop_elems * lo.esz;
+    int smax = 1;
+    for (const auto& d : h->desc) smax = std::max(smax, d.md_substeps);
+    w.nc = (T + k - 1) / k;
+    size_t o = 0;
+    w.ck_pop = o; o = align256(o + (size_t)(w.nc + 1) * popb);
+    w.ck_beads = o; o = align256(o + (size_t)(w.nc + 1) * 12 * nb * sizeof(double));
+    w.tape_pop = o; o = align256(o + (size_t)k * popb);
+    w.tape_imp = o; o = align256(o + (size_t)k * 3 * nodes * sizeof(unsigned long long));
+    w.tape_sub = o; o = align256(o + (size_t)k * smax * nb * TAPE_REC * sizeof(double));
+    w.tape_beads = o; o = align256(o + (size_t)k * 9 * nb * sizeof(double));
+    w.vh = o; o = align256(o + (size_t)T * 3 * nb * sizeof(double));
+    w.dj = o; o = align256(o + (size_t)T * 3 * nb * sizeof(double));
+    w.lam_a = o; o = align256(o + 19 * nodes * sizeof(double));
+    w.lam_b = o; o = align256(o + 19 * nodes * sizeof(double));
+    w.lam_dp = o; o = align256(o + 3 * nodes * sizeof(double));
+    w.lbeads = o; o = align256(o + 9 * nb * sizeof(double));
+    w.gpart = o; o = align256(o + 2 * lo.total_tiles * sizeof(double));
+    w.gz = o; o = align256(o + h->n_boxes * sizeof(double));
+    w.bytes = o;
+    return w;
+}
+
+// copy the current state (pops of the current buffer, beads) into / out of slot j
+lb_status ck_save(lb_handle* h, char* ws, const WinLayout& w, int j)
+{
+    const Layout& lo = h->lo;
+    const size_t popb = lo.pop_elems * lo.esz, bb = 3 * std::max<uint64_t>(lo.total_beads, 1) * sizeof(double);
+    HIPCHK(h, hipMemcpyAsync(ws + w.ck_pop + j * popb, h->pop(h->cur), popb, hipMemcpyDeviceToDevice, h->stream));
+    char* dst = ws + w.ck_beads + (size_t)j * 4 * bb;
+    const size_t arrs[4] = {lo.st_x, lo.st_v, lo.st_f, lo.st_fc};
+    for (int a = 0; a < 4; ++a)
+        HIPCHK(h, hipMemcpyAsync(dst + a * bb, h->state + arrs[a], bb, hipMemcpyDeviceToDevice, h->stream));
+    return LB_OK;
+}
+
+lb_status ck_restore(lb_handle* h, char* ws, const WinLayout& w, int j, uint64_t step)
+{
+    const Layout& lo = h->lo;
+    const size_t popb = lo.pop_elems * lo.esz, bb = 3 * std::max<uint64_t>(lo.total_beads, 1) * sizeof(double);
+    h->cur = 0;
+    HIPCHK(h, hipMemcpyAsync(h->pop(0), ws + w.ck_pop + j * popb, popb, hipMemcpyDeviceToDevice, h->stream));
+    const char* src = ws + w.ck_beads + (size_t)j * 4 * bb;
+    const size_t arrs[4] = {lo.st_x, lo.st_v, lo.st_f, lo.st_fc};
+    for (int a = 0; a < 4; ++a)
+        HIPCHK(h, hipMemcpyAsync(h->state + arrs[a], src + a * bb, bb, hipMemcpyDeviceToDevice, h->stream));
+    HIPCHK(h, hipStreamSynchronize(h->stream));
+    Ctrl ctrl;
+    HIPCHK(h, hipMemcpy(&ctrl, h->scratch + lo.sc_ctrl, sizeof ctrl, hipMemcpyDeviceToHost));
+    ctrl.step = (uint32_t)step;
+    HIPCHK(h, hipMemcpy(h->scratch + lo.sc_ctrl, &ctrl, sizeof ctrl, hipMemcpyHostToDevice));
+    if (lo.total_beads) HIPCHK(h, hipMemset(h->scratch + lo.sc_claim, 0, lo.total_nodes * sizeof(uint32_t)));
+    h->step = step;
+    return LB_OK;
+}
+
+// one step with the launches serialised on the main stream; optionally records
+// the impulse field before the fix-up consumes it and the chain's substep tape
+lb_status window_step(lb_handle* h, unsigned long long* imp_copy, double* tape)
+{
+    const void* A = h->pop(h->cur);
+    void* B = h->pop(1 - h->cur);
+    const bool f64 = h->prec == LB_FP64;
+    LaunchCtx c = h->ctx;
+    c.tape = tape;
+    const int nc = (int)h->couple_host.size();
+    if (nc)
+        HIPCHK(h, f64 ? launch_couple<double>(c, A, h->couple_list, nc, h->lo.couple_block, h->lo.couple_T, 0)
+                      : launch_couple<float>(c, A, h->couple_list, nc, h->lo.couple_block, h->lo.couple_T, 0));
+    if (imp_copy && h->lo.total_beads)
+        HIPCHK(h, hipMemcpyAsync(imp_copy, c.imp, 3 * h->lo.total_nodes * sizeof(unsigned long long),
+                                 hipMemcpyDeviceToDevice, h->stream));
+    HIPCHK(h, f64 ? launch_collide<double>(c, A, B, -1, 0, (uint32_t)h->lo.total_tiles, 0)
+                  : launch_collide<float>(c, A, B, -1, 0, (uint32_t)h->lo.total_tiles, 0));
+    if (h->lo.total_beads)
+        HIPCHK(h, f64 ? launch_fixup<double>(c, A, B, 0, h->lo.total_beads, 0)
+                      : launch_fixup<float>(c, A, B, 0, h->lo.total_beads, 0));
+    HIPCHK(h, launch_advance(c, 1));
+    h->cur ^= 1;
+    h->step += 1;
+    return LB_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+size_t lb_window_bytes(const lb_handle* h, int32_t T, int32_t k)
+{
+    if (!h || T <= 0 || k <= 0) return 0;
+    return win_layout(h, T, std::min(k, T)).bytes;
+}
+
+lb_status lb_set_rates(lb_handle* h, int32_t box, double omega_shear, double omega_bulk, double zeta)
+{
+    if (!h) return fail(nullptr, LB_EINVAL, "null handle");
+    if (box < 0 || box >= h->n_boxes) return fail(h, LB_EINVAL, "box index out of range");
+    if (!(omega_shear > 0 && omega_shear < 2) || !(omega_bulk > 0 && omega_bulk < 2) || !(zeta >= 0))
+        return fail(h, LB_EINVAL, "rates out of range");
+    if (h->pending) return fail(h, LB_ESTATE, "impulses pending from lb_couple");
+    lb_box_desc& d = h->desc[box];
+    d.omega_shear = omega_shear;
+    d.omega_bulk = omega_bulk;
+    d.zeta = zeta;
+    HIPCHK(h, hipStreamSynchronize(h->stream));
+    BoxDev b;
+    HIPCHK(h, hipMemcpy(&b, h->scratch + h->lo.sc_boxes + box * sizeof(BoxDev), sizeof b, hipMemcpyDeviceToHost));
+    b.gam_b = 1 - omega_bulk;
+    b.gam_s = 1 - omega_shear;
+    b.zeta = zeta;
+    b.bead_noise = std::sqrt(2.0 * d.kT * zeta / d.md_dt);
+    HIPCHK(h, hipMemcpy(h->scratch + h->lo.sc_boxes + box * sizeof(BoxDev), &b, sizeof b, hipMemcpyHostToDevice));
+    if (h->prec == LB_FP64) {
+        CollideConst<double> cc = collide_const<double>(d);
+        HIPCHK(h, hipMemcpy(h->scratch + h->lo.sc_ccs + box * sizeof(cc), &cc, sizeof cc, hipMemcpyHostToDevice));
+    } else {
+        CollideConst<float> cc = collide_const<float>(d);
+        HIPCHK(h, hipMemcpy(h->scratch + h->lo.sc_ccs + box * sizeof(cc), &cc, sizeof cc, hipMemcpyHostToDevice));
+    }
+    return LB_OK;
+}
+
+lb_status lb_window_forward(lb_handle* h, void* d_ws, size_t bytes, int32_t T, int32_t k, double* vhist_host)
+{
+    if (!h || !d_ws) return fail(h, LB_EINVAL, "null argument");
+    if (T <= 0 || k <= 0) return fail(h, LB_EINVAL, "T and k must be positive");
+    if (h->pending) return fail(h, LB_ESTATE, "impulses pending from lb_couple");
+    if (!h->lo.big_blocks.empty()) return fail(h, LB_EINVAL, "the adjoint window supports chains of at most 256 beads");
+    k = std::min(k, T);
+    const WinLayout w = win_layout(h, T, k);
+    if (bytes < w.bytes) return fail(h, LB_ENOMEM, "window workspace too small");
+    char* ws = (char*)d_ws;
+    const uint64_t nb3 = 3 * std::max<uint64_t>(h->lo.total_beads, 1);
+    h->win_T = T;
+    h->win_k = k;
+    h->win_step0 = h->step;
+    for (int t = 0; t < T; ++t) {
+        if (t % k == 0) {
+            lb_status s = ck_save(h, ws, w, t / k);
+            if (s != LB_OK) return s;
+        }
+        lb_status s = window_step(h, nullptr, nullptr);
+        if (s != LB_OK) return s;
+        HIPCHK(h, hipMemcpyAsync(ws + w.vh + t * nb3 * sizeof(double), h->state + h->lo.st_v, nb3 * sizeof(double),
+                                 hipMemcpyDeviceToDevice, h->stream));
+    }
+    if (vhist_host)
+        HIPCHK(h, hipMemcpyAsync(vhist_host, ws + w.vh, (size_t)T * nb3 * sizeof(double), hipMemcpyDeviceToHost,
+                                 h->stream));
+    HIPCHK(h, hipStreamSynchronize(h->stream));
+    h->win_ready = true;
+    return LB_OK;
+}
+
+lb_status lb_window_rewind(lb_handle* h, void* d_ws, size_t bytes)
+{
+    if (!h || !d_ws) return fail(h, LB_EINVAL, "null argument");
+    if (!h->win_ready) return fail(h, LB_ESTATE, "no forward window recorded");
+    const WinLayout w = win_layout(h, h->win_T, h->win_k);
+    if (bytes < w.bytes) return fail(h, LB_ENOMEM, "window workspace too small");
+    return ck_restore(h, (char*)d_ws, w, 0, h->win_step0);
+}
+
+lb_status lb_window_backward(lb_handle* h, void* d_ws, size_t bytes, const double* dj_host, double* grad_host)
+{
+    if (!h || !d_ws || !dj_host || !grad_host) return fail(h, LB_EINVAL, "null argument");
+    if (!h->win_ready) return fail(h, LB_ESTATE, "no forward window recorded");
+    const int T = h->win_T, k = h->win_k;
+    const WinLayout w = win_layout(h, T, k);
+    if (bytes < w.bytes) return fail(h, LB_ENOMEM, "window workspace too small");
+    char* ws = (char*)d_ws;
+    const Layout& lo = h->lo;
+    const uint64_t nbx = std::max<uint64_t>(lo.total_beads, 1), nb3 = 3 * nbx, nodes = lo.total_nodes;
+    const size_t popb = lo.pop_elems * lo.esz;
+    int smax = 1;
+    for (const auto& d : h->desc) smax = std::max(smax, d.md_substeps);
+    const bool f64 = h->prec == LB_FP64;
+    // the reverse sweep works in FP64 whatever the storage precision
+    if (!h->ccd) HIPCHK(h, hipMalloc(&h->ccd, h->n_boxes * sizeof(CollideConst<double>)));
+    {
+        std::vector<CollideConst<double>> cc(h->n_boxes);
+        for (int i = 0; i < h->n_boxes; ++i) cc[i] = collide_const<double>(h->desc[i]);
+        HIPCHK(h, hipMemcpy(h->ccd, cc.data(), cc.size() * sizeof(cc[0]), hipMemcpyHostToDevice));
+    }
+    HIPCHK(h, hipStreamSynchronize(h->stream));
+    // keep the end-of-window state, restored at the end
+    lb_status st = ck_save(h, ws, w, w.nc);
+    if (st != LB_OK) return st;
+    const uint64_t step_end = h->step;
+    const int cur_end = h->cur;
+    HIPCHK(h, hipMemcpyAsync(ws + w.dj, dj_host, (size_t)T * nb3 * sizeof(double), hipMemcpyHostToDevice, h->stream));
+    HIPCHK(h, hipMemsetAsync(ws + w.lam_a, 0, 19 * nodes * sizeof(double), h->stream));
+    HIPCHK(h, hipMemsetAsync(ws + w.lam_b, 0, 19 * nodes * sizeof(double), h->stream));
+    HIPCHK(h, hipMemsetAsync(ws + w.lbeads, 0, 9 * nbx * sizeof(double), h->stream));
+    HIPCHK(h, hipMemsetAsync(ws + w.gpart, 0, 2 * lo.total_tiles * sizeof(double), h->stream));
+    HIPCHK(h, hipMemsetAsync(ws + w.gz, 0, h->n_boxes * sizeof(double), h->stream));
+    double* lam_next = (double*)(ws + w.lam_a);
+    double* lam_cur = (double*)(ws + w.lam_b);
+    double* lb = (double*)(ws + w.lbeads);
+    for (int seg = w.nc - 1; seg >= 0; --seg) {
+        const int t0 = seg * k, t1 = std::min(T, t0 + k);
+        st = ck_restore(h, ws, w, seg, h->win_step0 + t0);
+        if (st != LB_OK) return st;
+        // replay the segment, recording what the reverse sweep needs
+        for (int t = t0; t < t1; ++t) {
+            const int j = t - t0;
+            HIPCHK(h, hipMemcpyAsync(ws + w.tape_pop + j * popb, h->pop(h->cur), popb, hipMemcpyDeviceToDevice,
+                                     h->stream));
+            const size_t arrs[3] = {lo.st_x, lo.st_v, lo.st_f};
+            for (int a = 0; a < 3; ++a)
+                HIPCHK(h, hipMemcpyAsync(ws + w.tape_beads + ((size_t)j * 9 + 3 * a) * nbx * sizeof(double),
+                                         h->state + arrs[a], nb3 * sizeof(double), hipMemcpyDeviceToDevice,
+                                         h->stream));
+            st = window_step(h, (unsigned long long*)(ws + w.tape_imp + (size_t)j * 3 * nodes * 8),
+                             (double*)(ws + w.tape_sub + (size_t)j * smax * nbx * TAPE_REC * sizeof(double)));
+            if (st != LB_OK) return st;
+        }
+        // reverse the segment's steps
+        for (int t = t1 - 1; t >= t0; --t) {
+            const int j = t - t0;
+            const uint32_t stepv = (uint32_t)(h->win_step0 + t);
+            const char* P = ws + w.tape_pop + j * popb;
+            const unsigned long long* imp = (const unsigned long long*)(ws + w.tape_imp + (size_t)j * 3 * nodes * 8);
+            HIPCHK(h, f64 ? launch_adj_collide<double>(h->ctx, h->ccd, P, imp, lam_next, lam_cur,
+                                                       (double*)(ws + w.lam_dp), (double*)(ws + w.gpart), nodes,
+                                                       (uint32_t)lo.total_tiles, stepv)
+                          : launch_adj_collide<float>(h->ctx, h->ccd, P, imp, lam_next, lam_cur,
+                                                      (double*)(ws + w.lam_dp), (double*)(ws + w.gpart), nodes,
+                                                      (uint32_t)lo.total_tiles, stepv));
+            AdjArgsHost a;
+            const double* tb = (const double*)(ws + w.tape_beads + (size_t)j * 9 * nbx * sizeof(double));
+            a.x0 = tb; a.v0 = tb + nb3; a.f0 = tb + 2 * nb3;
+            a.tape = (const double*)(ws + w.tape_sub + (size_t)j * smax * nbx * TAPE_REC * sizeof(double));
+            a.dj = (const double*)(ws + w.dj) + (size_t)t * nb3;
+            a.lx = lb; a.lv = lb + nb3; a.lf = lb + 2 * nb3;
+            a.lam_n = lam_cur;
+            a.lam_dp = (const double*)(ws + w.lam_dp);
+            a.gz = (double*)(ws + w.gz);
+            a.nodes = nodes;
+            const int nc = (int)h->couple_host.size();
+            HIPCHK(h, f64 ? launch_adj_couple<double>(h->ctx, h->couple_list, nc, P, a, stepv)
+                          : launch_adj_couple<float>(h->ctx, h->couple_list, nc, P, a, stepv));
+            std::swap(lam_next, lam_cur);
+        }
+    }
+    std::vector<double> gpart(2 * lo.total_tiles), gz(h->n_boxes);
+    HIPCHK(h, hipMemcpyAsync(gpart.data(), ws + w.gpart, gpart.size() * sizeof(double), hipMemcpyDeviceToHost,
+                             h->stream));
+    HIPCHK(h, hipMemcpyAsync(gz.data(), ws + w.gz, gz.size() * sizeof(double), hipMemcpyDeviceToHost, h->stream));
+    HIPCHK(h, hipStreamSynchronize(h->stream));
+    for (int i = 0; i < h->n_boxes; ++i) {
+        double gs = 0.0, gb = 0.0;
+        for (uint32_t t = 0; t < lo.n_tiles[i]; ++t) {
+            gs += gpart[2 * (lo.tile_begin[i] + t)];
+            gb += gpart[2 * (lo.tile_begin[i] + t) + 1];
+        }
+        grad_host[3 * i] = gs;
+        grad_host[3 * i + 1] = gb;
+        grad_host[3 * i + 2] = gz[i];
+    }
+    // back to the end of the window
+    st = ck_restore(h, ws, w, w.nc, step_end);
+    if (st != LB_OK) return st;
+    if (cur_end != 0) {   // the restored state sits in buffer 0; keep the handle's parity convention
+        HIPCHK(h, hipMemcpyAsync(h->pop(1), h->pop(0), popb, hipMemcpyDeviceToDevice, h->stream));
+        h->cur = 1;
+    }
+    HIPCHK(h, hipStreamSynchronize(h->stream));
+    return LB_OK;
+}
+
+}  // extern "C"
+
+extern "C" {
 lb_status lb_collide_only(lb_handle* h, int32_t n)
 {
     if (!h) return fail(nullptr, LB_EINVAL, "null handle");
@@ -775,6 +1071,7 @@ void lb_free(lb_handle* h)
     if (h->stream) (void)hipStreamSynchronize(h->stream);
     if (h->stream2) (void)hipStreamSynchronize(h->stream2);
     drop_graphs(h);
+    if (h->ccd) (void)hipFree(h->ccd);
     if (h->ev_fork) (void)hipEventDestroy(h->ev_fork);
     if (h->ev_join) (void)hipEventDestroy(h->ev_join);
     if (h->stream2) (void)hipStreamDestroy(h->stream2);

@@ -1,0 +1,153 @@
+"""GPU adjoint window against the oracle's exact forward-mode tangent and
+against central finite differences of the GPU forward window.
+
+The gradient is dJ/d(omega_shear, omega_bulk, zeta) of a loss J of the bead
+velocities after every LB step of a window.  The oracle's tangent gives
+dv/dtheta exactly (dual numbers through the FP64 step), so for any J the
+oracle gradient is sum (dJ/dv) (dv/dtheta)."""
+from __future__ import annotations
+
+import numpy as np
+import pytest
+
+from lbtest import chain, gpu_system, initial_pops, oracle_state, params, say
+
+pytestmark = pytest.mark.gpu
+
+FP64, FP32 = 0, 1
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    torch = pytest.importorskip("torch")
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+
+
+def _case(**kw):
+    base = dict(L=8, N=8, kT=1e-2, omega_s=1.1, omega_b=0.9, zeta=20.0, seed=4, box_id=2)
+    base.update(kw)
+    return params(**base)
+
+
+def _vacf_np(vh, tmax):
+    T = vh.shape[0]
+    N = vh.shape[1]
+    return np.array([np.sum(vh[: T - k] * vh[k:]) / (N * (T - k)) for k in range(tmax + 1)])
+
+
+def _vacf_loss_grad(vh, target):
+    """J and dJ/dv for J = sum_tau (C - C*)^2 / C*(0)^2."""
+    T, N = vh.shape[0], vh.shape[1]
+    tmax = len(target) - 1
+    C = _vacf_np(vh, tmax)
+    r = C - target
+    J = np.sum(r ** 2) / target[0] ** 2
+    g = np.zeros_like(vh)
+    for k in range(tmax + 1):
+        coef = 2 * r[k] / target[0] ** 2 / (N * (T - k))
+        g[: T - k] += coef * vh[k:]
+        g[k:] += coef * vh[: T - k]
+    return J, g
+
+
+@pytest.mark.parametrize("prec,tol", [(FP64, 1e-7), (FP32, 2e-3)])
+def test_adjoint_linear_functional_matches_oracle_tangent(orc, prec, tol):
+    """J = sum c . v(t) with random weights: dJ/dtheta from the GPU adjoint
+    equals the oracle's exact tangent contracted with c."""
+    say("adjoint linear", prec)
+    p = _case()
+    T, k = 16, 5
+    x0 = chain(p)
+    n0 = initial_pops(orc, p, amp=0.01, seed=11)
+    s = gpu_system([p], prec, xs=[x0], pops=[n0])
+    vh = s.window_forward(T, k)
+    cw = np.random.default_rng(5).normal(size=vh.shape)
+    grad = s.window_backward(cw)[0]
+    o = oracle_state(orc, p, n0, x0)
+    ho, dh = o.window_tangent(T)
+    assert np.max(np.abs(vh - ho)) < (1e-10 if prec == FP64 else 1e-5)
+    ref = np.einsum("tna,tnak->k", cw, dh)
+    np.testing.assert_allclose(grad, ref, rtol=tol, atol=tol * np.max(np.abs(ref)))
+
+
+def test_adjoint_vacf_loss_matches_oracle_and_fd(orc):
+    """VACF mismatch loss: GPU adjoint vs oracle tangent vs central finite
+    differences (relative step 1e-4) of the GPU's own forward window."""
+    say("adjoint vacf")
+    p = _case(L=10, N=12)
+    T, k, tmax = 30, 10, 8
+    x0 = chain(p)
+    # target from perturbed rates (1.1 x shear, 0.9 x bulk, 1.2 x friction), same seed and start
+    pt = dict(p)
+    pt.update(omega_s=1.1 * p["omega_s"], omega_b=0.9 * p["omega_b"], zeta=1.2 * p["zeta"])
+    st = gpu_system([pt], FP64, xs=[x0])
+    target = _vacf_np(st.window_forward(T, k), tmax)
+    s = gpu_system([p], FP64, xs=[x0])
+    vh = s.window_forward(T, k)
+    J, dj = _vacf_loss_grad(vh, target)
+    grad = s.window_backward(dj)[0]
+    # oracle
+    o = oracle_state(orc, p, initial_pops(orc, p), x0)
+    ho, dh = o.window_tangent(T)
+    _, djo = _vacf_loss_grad(ho, target)
+    ref = np.einsum("tna,tnak->k", djo, dh)
+    np.testing.assert_allclose(grad, ref, rtol=1e-6, atol=1e-6 * np.max(np.abs(ref)))
+    # finite differences on the GPU forward window
+    th = np.array([p["omega_s"], p["omega_b"], p["zeta"]])
+    fd = np.zeros(3)
+    for q in range(3):
+        Js = []
+        for sgn in (+1, -1):
+            t2 = th.copy()
+            t2[q] *= 1 + sgn * 1e-4
+            s.window_rewind()
+            s.set_rates(0, *t2)
+            Js.append(_vacf_loss_grad(s.window_forward(T, k), target)[0])
+        fd[q] = (Js[0] - Js[1]) / (2e-4 * th[q])
+    s.set_rates(0, *th)
+    np.testing.assert_allclose(grad, fd, rtol=1e-4, atol=1e-4 * np.max(np.abs(fd)))
+
+
+def test_adjoint_checkpoint_spacing_and_end_state(orc):
+    """The gradient does not depend on the checkpoint spacing, and the backward
+    sweep leaves the state at the end of the window."""
+    say("adjoint checkpoints")
+    p = _case()
+    T = 12
+    x0 = chain(p)
+    res = []
+    for k in (12, 5, 1):
+        s = gpu_system([p], FP64, xs=[x0])
+        vh = s.window_forward(T, k)
+        end = s.export_state()
+        cw = np.cos(np.arange(vh.size)).reshape(vh.shape)
+        res.append(s.window_backward(cw)[0])
+        after = s.export_state()
+        assert after["step"] == end["step"] == T
+        for ka in ("n", "x", "v", "f", "fc"):
+            assert np.array_equal(after["boxes"][0][ka], end["boxes"][0][ka]), ka
+    np.testing.assert_allclose(res[1], res[0], rtol=1e-12)
+    np.testing.assert_allclose(res[2], res[0], rtol=1e-12)
+
+
+def test_autograd_function(orc):
+    """torch.autograd.Function wrapper: loss.backward() fills theta.grad with
+    the adjoint's gradient."""
+    import torch
+
+    from paper_0903_5067_amd.adjoint import LBWindow, vacf_loss
+    say("autograd")
+    p = _case()
+    x0 = chain(p)
+    s = gpu_system([p], FP64, xs=[x0])
+    target = torch.tensor([1e-2, 5e-3, 2e-3, 1e-3], dtype=torch.float64)
+    theta = torch.tensor([[p["omega_s"], p["omega_b"], p["zeta"]]], dtype=torch.float64, requires_grad=True)
+    vh = LBWindow.apply(theta, s, 10, 5)
+    loss = vacf_loss(vh, target)
+    loss.backward()
+    s2 = gpu_system([p], FP64, xs=[x0])
+    vh2 = torch.from_numpy(s2.window_forward(10, 5)).requires_grad_(True)
+    vacf_loss(vh2, target).backward()
+    ref = s2.window_backward(vh2.grad.numpy())[0]
+    np.testing.assert_allclose(theta.grad.numpy()[0], ref, rtol=1e-12)
