@@ -27,6 +27,9 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0        # MI355X HBM3E
 BYTES_PER_NODE = {0: 304, 1: 152}   # 19 reads + 19 writes of 8 or 4 bytes
+KERNEL_SOURCES = ["paper_0903_5067_amd/csrc/lbmd_kernels.hip", "paper_0903_5067_amd/csrc/lbmd_kernels.hpp",
+                  "paper_0903_5067_amd/csrc/lbmd_device.hpp"]
+PMC_SUMMARY = "profiles/k_collide_prec256_pmc.md"
 
 
 def log(*a):
@@ -48,6 +51,51 @@ def make_system(preset, precision=None, n_boxes=None):
     s = lbm.LBSystem(boxes, precision=prec, bead_x0=x0)
     nodes = sum(int(b["L"]) ** 3 for b in boxes)
     return s, boxes, nodes, prec
+
+
+def kernel_source_hash() -> str:
+    import hashlib
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(precision_name: str):
+    """HBM bytes per collide launch from the committed PMC summary (FETCH_SIZE
+    and WRITE_SIZE, each scaled by a plain copy's counter reading), or None
+    when there is none for this storage or the kernel sources have changed
+    since the counters were taken."""
+    path = os.path.join(ROOT, PMC_SUMMARY)
+    if not os.path.exists(path):
+        return None
+    vals = {}
+    with open(path) as fh:
+        for line in fh:
+            if line.startswith("traffic:"):
+                for kv in line[len("traffic:"):].split():
+                    k, _, v = kv.partition("=")
+                    vals[k] = v
+    if vals.get("source_hash") != kernel_source_hash() or vals.get("precision") != precision_name:
+        return None
+    try:
+        return int(float(vals["bytes_per_launch"]))
+    except (KeyError, ValueError):
+        return None
+
+
+def copy_calibration():
+    """A plain elementwise copy of known size (1 GiB read, 1 GiB written per
+    launch, 10 launches) for scaling the HBM byte counters."""
+    import torch
+    a = torch.ones(1 << 28, dtype=torch.float32, device="cuda")
+    b = torch.empty_like(a)
+    for _ in range(10):
+        torch.neg(a, out=b)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_calibration": {"launches": 10, "read_bytes": a.numel() * 4,
+                                           "write_bytes": b.numel() * 4, "kernel": "torch.neg (elementwise)"}}))
 
 
 def time_steps(s, steps, warmup):
@@ -82,9 +130,38 @@ def time_collide(s, n):
     return e0.elapsed_time(e1) / 1e3 / n
 
 
+def adjoint_secondary():
+    """The 32^3 box with its N=32 chain: a 200-step window with checkpoints
+    every 20 steps, forward (recording) and backward (hand-written adjoint)
+    timed on the host clock around synchronous library calls, against plain
+    steps of the same box."""
+    import torch
+    import lbinputs
+    P = lbinputs.PRESETS["adjoint32"]
+    T, k = int(P["steps"]), int(P["checkpoint_every"])
+    s, boxes, nodes, prec = make_system("adjoint32")
+    tp, _ = time_steps(s, 2000, 50)
+    vh = s.window_forward(T, k)          # warm-up, allocates the workspace
+    s.window_backward(np.zeros_like(vh))
+    s.window_rewind()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    vh = s.window_forward(T, k)
+    t1 = time.perf_counter()
+    g = s.window_backward(np.cos(np.arange(vh.size)).reshape(vh.shape))
+    t2 = time.perf_counter()
+    s.close()
+    return {"window_steps": T, "checkpoint_every": k, "nodes": nodes, "beads": int(P["N"]),
+            "plain_mlups": round(nodes * 2000 / tp / 1e6, 1),
+            "forward_ms": round(1e3 * (t1 - t0), 2), "backward_ms": round(1e3 * (t2 - t1), 2),
+            "forward_backward_mlups": round(nodes * T / (t2 - t0) / 1e6, 2),
+            "grad_finite": bool(np.all(np.isfinite(g)))}
+
+
 def cpu_baseline(preset, budget_s=20.0):
     """The oracle (FP64 C, OpenMP) on the host cores: whole LB steps of the
-    same box and chain, as many as fit a ~20 s budget (at least one)."""
+    same box and chain, as many as fit a ~20 s budget (at least one).
+    Returns the report and the oracle state after those steps."""
     import lbinputs
     import oracle
     p = lbinputs.box_params(preset)
@@ -95,6 +172,7 @@ def cpu_baseline(preset, budget_s=20.0):
         n[i] = w[i] * p["rho0"]
     x0 = lbinputs.saw_chain(p["N"], L, p["seed"])
     st = oracle.State(oracle.make_box(**p), n, x0)
+    del n
     t0 = time.perf_counter()
     st.run(1)
     t1 = time.perf_counter() - t0
@@ -106,9 +184,61 @@ def cpu_baseline(preset, budget_s=20.0):
         t1 = time.perf_counter() - t0
         steps = more
     mlups = L ** 3 * steps / t1 / 1e6
-    return {"value": round(mlups, 3), "unit": "MLUPS", "cores": oracle.num_threads(), "kind": "oracle",
-            "sample": f"{steps} full LB step(s) of the {L}^3 box with its N={p['N']} chain, FP64 oracle, "
-                      f"{t1:.1f} s"}
+    rep = {"value": round(mlups, 3), "unit": "MLUPS", "cores": oracle.num_threads(), "kind": "oracle",
+           "sample": f"{steps} full LB step(s) of the {L}^3 box with its N={p['N']} chain (after 1 untimed), "
+                     f"FP64 oracle, {t1:.1f} s"}
+    return rep, st
+
+
+def _obs_errors(a, b, w=None):
+    """Per-observable differences of observation dict a from reference b."""
+    def rel(x, y):
+        return float(abs(x - y) / max(abs(y), 1e-300))
+    out = {"mass_rel": rel(a["mass"], b["mass"]),
+           "p_total_abs": float(np.max(np.abs(a["p_total"] - b["p_total"]))),
+           "p_fluid_abs": float(np.max(np.abs(a["p_fluid"] - b["p_fluid"]))),
+           "com_abs": float(np.max(np.abs(a["com"] - b["com"]))),
+           "rg2_rel": rel(a["rg2"], b["rg2"]), "re2_rel": rel(a["re2"], b["re2"]),
+           "mode_sq_rel_max": float(max(rel(a["mode_sq"][k], b["mode_sq"][k]) for k in range(4, 19)))}
+    return {k: float(f"{v:.3e}") for k, v in out.items()}
+
+
+def precision_study(preset, ost, s_orc, long_steps):
+    """FP32 deviation storage against FP64 storage on the GPU and against the
+    oracle: per-observable differences after the oracle's s_orc steps (all
+    three from the same initial state and noise), and FP32 against FP64 on the
+    GPU after long_steps."""
+    import torch
+    import oracle
+    import paper_0903_5067_amd as lbm
+    oo = ost.observables()
+    ref = {"mass": oo[0], "p_fluid": oo[4:7], "p_total": oo[10:13], "com": oo[13:16], "rg2": oo[16],
+           "re2": oo[17], "mode_sq": oo[19:38]}
+    c, w, e, b = oracle.tables()
+    res = {"short_steps": s_orc, "long_steps": long_steps}
+    obs_short = {}
+    for prec, name in ((lbm.FP32_DEV, "fp32_dev"), (lbm.FP64, "fp64")):
+        s, boxes, nodes, _ = make_system(preset, precision=prec)
+        s.set_launch(batched=True, graph_steps=20)
+        s.step(s_orc)
+        ob = s.observables()[0]
+        obs_short[name] = ob
+        n = s.export_state()["boxes"][0]["n"]
+        err = 0.0
+        for i in range(19):
+            err = max(err, float(np.max(np.abs(n[i] - ost.n[i]))) / (w[i] * boxes[0]["rho0"]))
+        del n
+        e_o = _obs_errors(ob, ref)
+        e_o["pop_rel_max"] = float(f"{err:.3e}")
+        res[f"{name}_vs_oracle"] = e_o
+        s.step(long_steps - s_orc)
+        obs_short[name + "_long"] = s.observables()[0]
+        s.close()
+        del s
+        torch.cuda.empty_cache()
+    res["fp32_dev_vs_fp64_gpu_short"] = _obs_errors(obs_short["fp32_dev"], obs_short["fp64"])
+    res["fp32_dev_vs_fp64_gpu_long"] = _obs_errors(obs_short["fp32_dev_long"], obs_short["fp64_long"])
+    return res
 
 
 def main():
@@ -120,6 +250,13 @@ def main():
     ap.add_argument("--no-secondary", action="store_true")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--graph-steps", type=int, default=20)
+    ap.add_argument("--no-autotune", action="store_true")
+    ap.add_argument("--variant", type=int, default=-1,
+                    help="force this collide launch shape instead of autotuning")
+    ap.add_argument("--collide-launches", type=int, default=0,
+                    help="launches of the collide kernel timed for the roofline (0: ~0.5 s worth)")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="only run the plain copy used to scale the HBM byte counters")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py runs on one GPU only: the path is built and measured for a single MI355X; "
@@ -129,17 +266,28 @@ def main():
     import torch
     import lbinputs
     torch.cuda.init()
+    if args.copy_calibration:
+        copy_calibration()
+        return
     log("workload", args.workload)
     s, boxes, nodes, prec = make_system(args.workload)
     if args.graph_steps:
         s.set_launch(batched=True, graph_steps=args.graph_steps)
+    tune = None
+    if args.variant >= 0:
+        s.set_collide_variant(args.variant)
+        tune = {"chosen": args.variant, "forced": True}
+    elif not args.no_autotune:
+        chosen, times = s.autotune(reps=20)
+        tune = {"chosen": chosen, "us_per_variant": [round(t, 2) for t in times]}
+        log("autotune", json.dumps(tune))
     obs0 = s.observables()[0]
     t_ev, t_wall = time_steps(s, args.steps, args.warmup)
     obs1 = s.observables()[0]
     ms = 1e3 * t_ev / args.steps
     mlups = nodes * args.steps / t_ev / 1e6
     log(f"{args.steps} steps: {t_ev:.4f} s (events), {t_wall:.4f} s (wall), {mlups:.1f} MLUPS")
-    n_coll = max(20, min(500, int(2.0 / max(ms / 1e3, 1e-6) / 4)))
+    n_coll = args.collide_launches or max(20, min(500, int(2.0 / max(ms / 1e3, 1e-6) / 4)))
     t_k = time_collide(s, n_coll)
     achieved = BYTES_PER_NODE[prec] * nodes / t_k / 1e9
     log(f"collide kernel: {t_k * 1e6:.1f} us avg over {n_coll} launches, {achieved:.0f} GB/s")
@@ -164,9 +312,12 @@ def main():
         "pct_hbm_peak_step": round(100.0 * BYTES_PER_NODE[prec] * nodes * args.steps / t_ev / 1e9 / HBM_PEAK_GBS, 2),
         "roofline": {"bound": "hbm", "kernel": "k_collide (fused collide+stream)",
                      "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+                     "frac": round(achieved / HBM_PEAK_GBS, 4),
+                     "traffic": (measured_traffic("fp32_dev" if prec == 1 else "fp64")
+                                 if args.workload == "prec256" else None),
                      "bytes_per_launch": BYTES_PER_NODE[prec] * nodes,
                      "avg_launch_us": round(t_k * 1e6, 2)},
+        "autotune": tune,
         "invariants": {"mass_rel_drift": abs(obs1["mass"] - obs0["mass"]) / obs0["mass"],
                        "p_total_drift": float(np.max(np.abs(obs1["p_total"] - obs0["p_total"]))),
                        "health": obs1["health"]},
@@ -195,11 +346,18 @@ def main():
                              "plain_per_box_mlups": round(nb * 100 / tp / 1e6, 1),
                              "batched_over_plain": round((nb * 500 / tb) / (nb * 100 / tp), 3)}
         sb.close()
+        sec["adjoint32"] = adjoint_secondary()
         result["secondary"] = sec
         log("secondary", json.dumps(sec))
     if not args.no_cpu:
         log("cpu baseline (oracle) ...")
-        result["cpu_baseline"] = cpu_baseline(args.workload)
+        rep, ost = cpu_baseline(args.workload)
+        result["cpu_baseline"] = rep
+        if args.workload == "prec256" and not args.no_secondary:
+            log("precision study ...")
+            result["precision"] = precision_study(args.workload, ost, ost.t, 2000)
+            log("precision", json.dumps(result["precision"]))
+        del ost
     print(json.dumps(result), flush=True)
 
 

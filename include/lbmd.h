@@ -192,6 +192,20 @@ lb_status lb_set_rates(lb_handle* h, int32_t box, double omega_shear, double ome
  * the handle's stream. */
 lb_status lb_collide_only(lb_handle* h, int32_t n);
 
+/* ---- launch-shape autotuning of the collide+stream kernel ---------------
+ * LB_N_COLLIDE_VARIANTS launch shapes compute identical values (same per-node
+ * arithmetic, bit for bit); they differ in the cap on resident waves per SIMD
+ * (4..8) and in the grid: one workgroup per 256-node tile (variants 0..4) or
+ * a grid of n_CU x waves workgroups that strides over the tiles (5..9).
+ * lb_autotune times every variant on the handle's own state (reps launches
+ * each after two untimed ones, HIP events on the handle's stream, no state
+ * change), selects the fastest, drops recorded graphs, and writes the average
+ * microseconds per launch to times_us[LB_N_COLLIDE_VARIANTS] (may be NULL) and
+ * the choice to *chosen (may be NULL).  lb_set_collide_variant forces one. */
+#define LB_N_COLLIDE_VARIANTS 10
+lb_status lb_autotune(lb_handle* h, int32_t reps, float* times_us, int32_t* chosen);
+lb_status lb_set_collide_variant(lb_handle* h, int32_t variant);
+
 /* The stream the handle enqueues on (hipStream_t as void*). */
 void* lb_stream(const lb_handle* h);
 

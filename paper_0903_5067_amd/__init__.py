@@ -17,6 +17,7 @@ LIB_PATH = os.path.join(_HERE, "liblbmd.so")
 
 LB_OK, LB_EINVAL, LB_ENOMEM, LB_EDEVICE, LB_ENUMERIC, LB_ESTATE = 0, -1, -2, -3, -4, -5
 FP64, FP32_DEV = 0, 1
+N_COLLIDE_VARIANTS = 10
 HEALTH = {"density": 0x1, "mach": 0x2, "fene": 0x4, "table": 0x8, "fixed": 0x10}
 
 
@@ -79,6 +80,8 @@ def lib() -> ctypes.CDLL:
         L.lb_velocity_history.argtypes = [vp, i64, ctypes.POINTER(ctypes.c_double), sz]
         L.lb_set_launch.argtypes = [vp, i32, i32]
         L.lb_collide_only.argtypes = [vp, i32]
+        L.lb_autotune.argtypes = [vp, i32, ctypes.POINTER(ctypes.c_float), ctypes.POINTER(i32)]
+        L.lb_set_collide_variant.argtypes = [vp, i32]
         L.lb_stream.argtypes = [vp]
         L.lb_stream.restype = vp
         L.lb_window_bytes.argtypes = [vp, i32, i32]
@@ -94,7 +97,8 @@ def lib() -> ctypes.CDLL:
         for name in ("lb_query_sizes", "lb_init", "lb_couple", "lb_step", "lb_observables",
                      "lb_export_state", "lb_import_state", "lb_pending_impulse",
                      "lb_velocity_history", "lb_set_launch", "lb_collide_only", "lb_window_forward",
-                     "lb_window_backward", "lb_window_rewind", "lb_set_rates"):
+                     "lb_window_backward", "lb_window_rewind", "lb_set_rates", "lb_autotune",
+                     "lb_set_collide_variant"):
             getattr(L, name).restype = ctypes.c_int
         _lib = L
     return _lib
@@ -171,6 +175,18 @@ class LBSystem:
     def collide_only(self, n: int = 1):
         """n launches of the fused collide+stream kernel, state not advanced."""
         _check(lib().lb_collide_only(self.h, int(n)), self.h)
+
+    def autotune(self, reps: int = 20):
+        """Time every launch shape of the collide+stream kernel on this state
+        and keep the fastest; returns (chosen variant, microseconds per launch
+        of each variant)."""
+        t = (ctypes.c_float * N_COLLIDE_VARIANTS)()
+        ch = ctypes.c_int32()
+        _check(lib().lb_autotune(self.h, int(reps), t, ctypes.byref(ch)), self.h)
+        return ch.value, [float(v) for v in t]
+
+    def set_collide_variant(self, variant: int):
+        _check(lib().lb_set_collide_variant(self.h, int(variant)), self.h)
 
     def synchronize(self):
         self.stream.synchronize()

@@ -65,25 +65,20 @@ __device__ __forceinline__ Upwind upwind_of(uint32_t r, int L, double inv_L)
 }
 
 // -------------------------------------------------------------- collide
-// At most 7 of the 8 wave slots per SIMD: the slot left free lets the short
-// chain kernels running beside this one start at once instead of queueing
-// behind the collide grid.
+// One tile of 256 nodes: gather the pre-collision populations (pull), collide
+// with no impulse, write post-collision values aligned and non-temporal.
 template <typename R>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 7))) void k_collide(const BoxDev* __restrict__ boxes,
-                                                 const CollideConst<R>* __restrict__ ccs,
-                                                 const uint32_t* __restrict__ tile_box,
-                                                 int fixed_box, uint32_t tile0,
-                                                 const R* __restrict__ A, R* __restrict__ B,
-                                                 Ctrl* __restrict__ ctrl, uint32_t s_off)
+__device__ __forceinline__ void collide_tile(const BoxDev* __restrict__ boxes, const CollideConst<R>* __restrict__ ccs,
+                                             const uint32_t* __restrict__ tile_box, int fixed_box, uint32_t tile,
+                                             const R* __restrict__ A, R* __restrict__ B, Ctrl* __restrict__ ctrl,
+                                             uint32_t t)
 {
-    const uint32_t tile = tile0 + blockIdx.x;
     const int bi = fixed_box >= 0 ? fixed_box : (int)tile_box[tile];
     const BoxDev& bx = boxes[bi];
     const int L = bx.L;
     const uint32_t V = (uint32_t)L * L * L;
     const uint32_t r = (tile - bx.tile_begin) * 256u + threadIdx.x;
     if (r >= V) return;
-    const uint32_t t = ctrl->step + s_off;
     const CollideConst<R> cc = ccs[bi];
     const uint64_t ps = bx.ps;
     const Upwind up = upwind_of(r, L, bx.inv_L);
@@ -95,6 +90,24 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 7))) voi
 #pragma unroll
     for (int i = 0; i < 19; ++i) __builtin_nontemporal_store(o[i], b + i * ps);
     if (h) atomicOr(&ctrl->health, h);
+}
+
+// Launch shapes the autotuner chooses from: W caps the waves per SIMD (4..8),
+// PERSIST selects a grid of a few blocks per CU that strides over the tiles
+// instead of one block per tile.  All shapes compute the same values.
+template <typename R, int W, bool PERSIST>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, W))) void k_collide(
+    const BoxDev* __restrict__ boxes, const CollideConst<R>* __restrict__ ccs, const uint32_t* __restrict__ tile_box,
+    int fixed_box, uint32_t tile0, uint32_t n_tiles, const R* __restrict__ A, R* __restrict__ B,
+    Ctrl* __restrict__ ctrl, uint32_t s_off)
+{
+    const uint32_t t = ctrl->step + s_off;
+    if (PERSIST) {
+        for (uint32_t k = blockIdx.x; k < n_tiles; k += gridDim.x)
+            collide_tile<R>(boxes, ccs, tile_box, fixed_box, tile0 + k, A, B, ctrl, t);
+    } else {
+        collide_tile<R>(boxes, ccs, tile_box, fixed_box, tile0 + blockIdx.x, A, B, ctrl, t);
+    }
 }
 
 // --------------------------------------------------------------- couple
@@ -858,14 +871,33 @@ static ChainArgs chain_args(const LaunchCtx& c)
                      c.touched_cnt, c.touch_cap, c.nl_rebuilds, c.vhist, c.hist_len, c.total_beads, c.tape};
 }
 
+template <typename R, int W, bool PERSIST>
+static void launch_collide_v(const LaunchCtx& c, const void* A, void* B, int fixed_box, uint32_t tile0,
+                             uint32_t n_tiles, uint32_t s_off)
+{
+    const uint32_t grid = PERSIST ? std::min<uint32_t>(n_tiles, (uint32_t)(c.n_cu * W)) : n_tiles;
+    hipLaunchKernelGGL((k_collide<R, W, PERSIST>), dim3(grid), dim3(256), 0, c.stream, c.boxes,
+                       (const CollideConst<R>*)c.ccs, c.tile_box, fixed_box, tile0, n_tiles, (const R*)A, (R*)B,
+                       c.ctrl, s_off);
+}
+
 template <typename R>
 hipError_t launch_collide(const LaunchCtx& c, const void* A, void* B, int fixed_box, uint32_t tile0,
                           uint32_t n_tiles, uint32_t s_off)
 {
     if (n_tiles == 0) return hipSuccess;
-    hipLaunchKernelGGL(k_collide<R>, dim3(n_tiles), dim3(256), 0, c.stream, c.boxes,
-                       (const CollideConst<R>*)c.ccs, c.tile_box, fixed_box, tile0, (const R*)A, (R*)B,
-                       c.ctrl, s_off);
+    switch (c.collide_variant) {
+    case 0: launch_collide_v<R, 4, false>(c, A, B, fixed_box, tile0, n_tiles, s_off); break;
+    case 1: launch_collide_v<R, 5, false>(c, A, B, fixed_box, tile0, n_tiles, s_off); break;
+    case 2: launch_collide_v<R, 6, false>(c, A, B, fixed_box, tile0, n_tiles, s_off); break;
+    case 3: launch_collide_v<R, 7, false>(c, A, B, fixed_box, tile0, n_tiles, s_off); break;
+    case 4: launch_collide_v<R, 8, false>(c, A, B, fixed_box, tile0, n_tiles, s_off); break;
+    case 5: launch_collide_v<R, 4, true>(c, A, B, fixed_box, tile0, n_tiles, s_off); break;
+    case 6: launch_collide_v<R, 5, true>(c, A, B, fixed_box, tile0, n_tiles, s_off); break;
+    case 7: launch_collide_v<R, 6, true>(c, A, B, fixed_box, tile0, n_tiles, s_off); break;
+    case 8: launch_collide_v<R, 7, true>(c, A, B, fixed_box, tile0, n_tiles, s_off); break;
+    default: launch_collide_v<R, 8, true>(c, A, B, fixed_box, tile0, n_tiles, s_off); break;
+    }
     return hipGetLastError();
 }
 

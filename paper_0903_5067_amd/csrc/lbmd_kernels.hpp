@@ -3,6 +3,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <algorithm>
+
 #include "lbmd_device.hpp"
 
 namespace lbd {
@@ -10,6 +12,8 @@ namespace lbd {
 // Device pointers and sizes every launcher needs; filled by the runtime.
 struct LaunchCtx {
     hipStream_t stream;
+    int n_cu;                      // compute units of the device
+    int collide_variant;           // launch shape of the collide kernel (0..N_COLLIDE_VARIANTS-1)
     const BoxDev* boxes;
     int n_boxes;
     const void* ccs;               // CollideConst<R>[n_boxes]
@@ -70,6 +74,8 @@ template <typename R>
 hipError_t launch_adj_couple(const LaunchCtx& c, const int32_t* list, int n_list, const void* P,
                              const AdjArgsHost& a, uint32_t step);
 
+constexpr int N_COLLIDE_VARIANTS = 10;
+constexpr int DEFAULT_COLLIDE_VARIANT = 3;   // one block per tile, at most 7 waves per SIMD
 constexpr int NSTAT_REC = 24;
 constexpr int NCHAIN_REC = 11;
 constexpr int NL_SLOTS = 48;

@@ -437,6 +437,18 @@ lb_status lb_init(const lb_box_desc* boxes, int32_t n_boxes, int32_t precision, 
 
     LaunchCtx& c = h->ctx;
     c.stream = h->stream;
+    {
+        int dev = 0, ncu = 0;
+        e = hipGetDevice(&dev);
+        if (e == hipSuccess) e = hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev);
+        if (e != hipSuccess || ncu <= 0) {
+            std::string msg = std::string("device query: ") + hipGetErrorString(e);
+            lb_free(h);
+            return fail(nullptr, LB_EDEVICE, msg);
+        }
+        c.n_cu = ncu;
+        c.collide_variant = DEFAULT_COLLIDE_VARIANT;
+    }
     c.boxes = (const BoxDev*)sc(lo.sc_boxes);
     c.n_boxes = n_boxes;
     c.ccs = sc(lo.sc_ccs);
@@ -1060,6 +1072,58 @@ lb_status lb_collide_only(lb_handle* h, int32_t n)
         else
             HIPCHK(h, launch_collide<float>(h->ctx, A, B, -1, 0, (uint32_t)h->lo.total_tiles, 0));
     }
+    return LB_OK;
+}
+
+static_assert(LB_N_COLLIDE_VARIANTS == N_COLLIDE_VARIANTS, "variant count");
+
+lb_status lb_set_collide_variant(lb_handle* h, int32_t variant)
+{
+    if (!h) return fail(nullptr, LB_EINVAL, "null handle");
+    if (variant < 0 || variant >= N_COLLIDE_VARIANTS) return fail(h, LB_EINVAL, "variant out of range");
+    HIPCHK(h, hipStreamSynchronize(h->stream));
+    drop_graphs(h);
+    h->ctx.collide_variant = h->ctx2.collide_variant = variant;
+    return LB_OK;
+}
+
+lb_status lb_autotune(lb_handle* h, int32_t reps, float* times_us, int32_t* chosen)
+{
+    if (!h) return fail(nullptr, LB_EINVAL, "null handle");
+    if (reps <= 0) return fail(h, LB_EINVAL, "reps must be > 0");
+    HIPCHK(h, hipStreamSynchronize(h->stream));
+    drop_graphs(h);
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    HIPCHK(h, hipEventCreate(&e0));
+    hipError_t e = hipEventCreate(&e1);
+    bool launch_failed = false;    // lb_collide_only already set the message
+    float best = 0.f;
+    int best_v = h->ctx.collide_variant;
+    const int keep = h->ctx.collide_variant;
+    for (int v = 0; v < N_COLLIDE_VARIANTS && e == hipSuccess && !launch_failed; ++v) {
+        h->ctx.collide_variant = v;
+        if (lb_collide_only(h, 2) != LB_OK) { launch_failed = true; break; }
+        e = hipEventRecord(e0, h->stream);
+        if (e != hipSuccess) break;
+        if (lb_collide_only(h, reps) != LB_OK) { launch_failed = true; break; }
+        e = hipEventRecord(e1, h->stream);
+        if (e == hipSuccess) e = hipEventSynchronize(e1);
+        float ms = 0.f;
+        if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+        if (e != hipSuccess) break;
+        const float us = 1e3f * ms / reps;
+        if (times_us) times_us[v] = us;
+        if (v == 0 || us < best) { best = us; best_v = v; }
+    }
+    if (e0) (void)hipEventDestroy(e0);
+    if (e1) (void)hipEventDestroy(e1);
+    if (launch_failed || e != hipSuccess) {
+        h->ctx.collide_variant = keep;
+        if (!launch_failed) h->err = std::string("autotune: ") + hipGetErrorString(e);
+        return LB_EDEVICE;
+    }
+    h->ctx.collide_variant = h->ctx2.collide_variant = best_v;
+    if (chosen) *chosen = best_v;
     return LB_OK;
 }
 

@@ -78,11 +78,11 @@ def test_adjoint_vacf_loss_matches_oracle_and_fd(orc):
     p = _case(L=10, N=12)
     T, k, tmax = 30, 10, 8
     x0 = chain(p)
-    # target from perturbed rates (1.1 x shear, 0.9 x bulk, 1.2 x friction), same seed and start
+    # target from perturbed rates (1.1 x shear, 0.9 x bulk, 1.2 x friction),
+    # same seed and start, computed by the oracle
     pt = dict(p)
     pt.update(omega_s=1.1 * p["omega_s"], omega_b=0.9 * p["omega_b"], zeta=1.2 * p["zeta"])
-    st = gpu_system([pt], FP64, xs=[x0])
-    target = _vacf_np(st.window_forward(T, k), tmax)
+    target = _vacf_np(oracle_state(orc, pt, initial_pops(orc, pt), x0).run(T, record_velocities=True), tmax)
     s = gpu_system([p], FP64, xs=[x0])
     vh = s.window_forward(T, k)
     J, dj = _vacf_loss_grad(vh, target)
@@ -151,3 +151,63 @@ def test_autograd_function(orc):
     vacf_loss(vh2, target).backward()
     ref = s2.window_backward(vh2.grad.numpy())[0]
     np.testing.assert_allclose(theta.grad.numpy()[0], ref, rtol=1e-12)
+
+
+@pytest.fixture(scope="module")
+def full_window(orc):
+    """The 32^3 box with its N=32 chain, a 200-step window: the oracle's
+    velocities and exact tangent at the base rates, and a VACF target (lags
+    0..20) from the oracle at (1.1, 0.9, 1.2) x (shear, bulk, friction)."""
+    import lbinputs
+    P = lbinputs.PRESETS["adjoint32"]
+    p = lbinputs.box_params("adjoint32")
+    T, k, tmax = int(P["steps"]), int(P["checkpoint_every"]), 20
+    x0 = chain(p)
+    pt = dict(p)
+    pt.update(omega_s=1.1 * p["omega_s"], omega_b=0.9 * p["omega_b"], zeta=1.2 * p["zeta"])
+    say("full window: oracle target")
+    target = _vacf_np(oracle_state(orc, pt, initial_pops(orc, pt), x0).run(T, record_velocities=True), tmax)
+    say("full window: oracle tangent")
+    ho, dh = oracle_state(orc, p, initial_pops(orc, p), x0).window_tangent(T)
+    _, djo = _vacf_loss_grad(ho, target)
+    ref = np.einsum("tna,tnak->k", djo, dh)
+    return dict(p=p, T=T, k=k, x0=x0, target=target, ho=ho, ref=ref)
+
+
+@pytest.mark.parametrize("prec,vtol,gtol", [(FP64, 1e-9, 1e-6), (FP32, 1e-5, 2e-3)])
+def test_adjoint_full_window_matches_oracle(full_window, prec, vtol, gtol):
+    """Full-size window (32^3, N=32, T=200, checkpoints every 20): GPU bead
+    velocities and VACF-loss gradient against the oracle's exact tangent."""
+    fw = full_window
+    say("full window adjoint", prec)
+    s = gpu_system([fw["p"]], prec, xs=[fw["x0"]])
+    vh = s.window_forward(fw["T"], fw["k"])
+    assert np.max(np.abs(vh - fw["ho"])) < vtol
+    J, dj = _vacf_loss_grad(vh, fw["target"])
+    grad = s.window_backward(dj)[0]
+    ref = fw["ref"]
+    np.testing.assert_allclose(grad, ref, rtol=gtol, atol=gtol * np.max(np.abs(ref)))
+
+
+def test_adjoint_full_window_matches_fd(full_window):
+    """Full-size window, FP64: adjoint gradient against central finite
+    differences (relative step 1e-4) of the GPU forward window."""
+    fw = full_window
+    p = fw["p"]
+    say("full window fd")
+    s = gpu_system([p], FP64, xs=[fw["x0"]])
+    vh = s.window_forward(fw["T"], fw["k"])
+    _, dj = _vacf_loss_grad(vh, fw["target"])
+    grad = s.window_backward(dj)[0]
+    th = np.array([p["omega_s"], p["omega_b"], p["zeta"]])
+    fd = np.zeros(3)
+    for q in range(3):
+        Js = []
+        for sgn in (+1, -1):
+            t2 = th.copy()
+            t2[q] *= 1 + sgn * 1e-4
+            s.window_rewind()
+            s.set_rates(0, *t2)
+            Js.append(_vacf_loss_grad(s.window_forward(fw["T"], fw["k"]), fw["target"])[0])
+        fd[q] = (Js[0] - Js[1]) / (2e-4 * th[q])
+    np.testing.assert_allclose(grad, fd, rtol=1e-4, atol=1e-4 * np.max(np.abs(fd)))

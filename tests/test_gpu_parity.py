@@ -196,6 +196,46 @@ def test_graph_equals_direct_bitwise():
             assert np.array_equal(ba[k], bb[k]), k
 
 
+@pytest.mark.parametrize("prec", [FP32, FP64])
+def test_collide_variants_bitwise_and_autotune(prec):
+    """Every launch shape of the collide+stream kernel gives the same state bit
+    for bit, batched and per box; the autotuner leaves the state untouched and
+    its choice (replayed in graphs) gives the same state too."""
+    import paper_0903_5067_amd as lbm
+    say("collide variants", prec)
+    boxes = _boxes()
+    xs = [chain(b) for b in boxes]
+    ref = gpu_system(boxes, prec, xs=xs)
+    ref.step(7)
+    a = ref.export_state()
+    for v in range(lbm.N_COLLIDE_VARIANTS):
+        for batched in (True, False):
+            s = gpu_system(boxes, prec, xs=xs)
+            s.set_collide_variant(v)
+            s.set_launch(batched=batched)
+            s.step(7)
+            b = s.export_state()
+            for ba, bb in zip(a["boxes"], b["boxes"]):
+                for k in ba:
+                    assert np.array_equal(ba[k], bb[k]), (v, batched, k)
+            s.close()
+    s = gpu_system(boxes, prec, xs=xs)
+    s.step(3)
+    chosen, times = s.autotune(reps=3)
+    assert 0 <= chosen < lbm.N_COLLIDE_VARIANTS
+    assert all(t > 0 for t in times)
+    assert times[chosen] == min(times)
+    s.set_launch(batched=True, graph_steps=2)
+    s.step(4)
+    b = s.export_state()
+    assert b["step"] == 7
+    for ba, bb in zip(a["boxes"], b["boxes"]):
+        for k in ba:
+            assert np.array_equal(ba[k], bb[k]), ("autotuned", k)
+    with pytest.raises(lbm.LBError):
+        s.set_collide_variant(lbm.N_COLLIDE_VARIANTS)
+
+
 def test_runs_are_deterministic_and_resumable():
     """Two runs are bitwise equal (the impulse spreading is order-independent
     fixed point); export after 10 steps + import + 10 steps equals 20 steps."""
