@@ -125,12 +125,13 @@ struct ChainArgs {
 };
 
 // node velocities (MD units) of the 8 stencil nodes from the frozen populations;
-// ALL_AT_ONCE issues every load before any use (for the register-rich variant)
-template <typename R, typename U, bool ALL_AT_ONCE>
+// the loads of NB nodes are issued before any of them is used (NB = 8: one
+// round trip to memory, for register-rich callers)
+template <typename R, typename U, int NB>
 __device__ __forceinline__ void stencil_velocities(const R* __restrict__ a, uint64_t ps, const int i0[3], int L,
                                                    double rho0, double inv_tau, U u[8][3])
 {
-    constexpr int NB = ALL_AT_ONCE ? 8 : 1;
+    static_assert(NB == 1 || NB == 2 || NB == 4 || NB == 8, "NB divides 8");
 #pragma unroll
     for (int k0 = 0; k0 < 8; k0 += NB) {
         R d[NB][19];
@@ -407,7 +408,7 @@ __global__ __launch_bounds__(MAXT) void k_couple(const BoxDev* __restrict__ boxe
                                (uint32_t)L * ((uint32_t)(iy >= L ? iy - L : iy) + (uint32_t)L * (uint32_t)(iz >= L ? iz - L : iz));
                     acc[k][0] = acc[k][1] = acc[k][2] = 0.0;
                 }
-                stencil_velocities<R, R, true>(a, bx.ps, i0, L, bx.rho0, inv_tau, cu);
+                stencil_velocities<R, R, 8>(a, bx.ps, i0, L, bx.rho0, inv_tau, cu);
                 cb[0] = i0[0]; cb[1] = i0[1]; cb[2] = i0[2];
                 have_acc = true;
             }
@@ -466,226 +467,319 @@ __global__ __launch_bounds__(MAXT) void k_couple(const BoxDev* __restrict__ boxe
 }
 
 // ------------------------------------------------- couple, large chains
-// Chains above 256 beads are spread over workgroups of 64 beads, one launch
-// per MD substep (graph nodes), so a chain of 1024 beads uses 16 CUs instead
-// of one.  Between launches each bead's cached stencil (base cell, node
-// velocities, accumulated impulse) lives in global memory, and positions are
-// double-buffered: substep s reads xb[s&1] for the forces and writes the
-// drifted positions of substep s+1 into xb[(s+1)&1].
-struct BigArgs {
-    const int2* blocks;        // (box, first bead of the block within the box)
-    double* xb;                // [2][total beads][3]
-    int32_t* cb;               // [total beads][4]: base cell x,y,z; touched count
-    double* cu;                // [total beads][8][3] node velocities (MD units)
-    double* acc;               // [total beads][8][3] accumulated impulse (MD units)
-    uint32_t* nl_req;          // per box: global substep id that must rebuild the list
-};
+// Chains above 256 beads take three launches per LB step, on one stream:
+//   k_near_nodes  every bead's 3x3x3 nodes around its nearest node: the node
+//                 velocities (MD units), one thread per (bead, node), so all
+//                 the population loads of the stage go out in one wave;
+//   k_chain_wg    one workgroup of up to 1024 threads per chain, one thread
+//                 per bead, every MD substep in one launch.  Positions,
+//                 neighbour lists and the positions they were built at live
+//                 in LDS (144 KB); each bead's stencil velocities in
+//                 registers, refilled from the 3x3x3 table when the bead
+//                 changes cell.  Per substep each bead writes one record
+//                 (fractions, coupling force, base cell) instead of handing
+//                 impulses over, so no atomic traffic sits in the barrier-
+//                 synchronised substep loop;
+//   k_spread      one thread per (bead, stencil corner) turns the records into
+//                 node impulses: the same accumulation per stencil as the
+//                 one-workgroup path of small chains, then one fixed-point
+//                 atomic per component and stencil.
+constexpr int WG_MAXB = 1024;
+constexpr int NEAR = 27;    // nodes in the table of one bead
 
-// first half kick and drift of substep 0; resets the per-step stencil cache
-// Workgroups are handed to the 8 XCDs round-robin by block index; the chain
-// kernels launch XCD_SPREAD blocks per working block and let only every
-// XCD_SPREAD-th one work, so a chain's blocks share one XCD's L2 and the
-// positions and stencil caches exchanged between substeps stay there.
-constexpr int XCD_SPREAD = 8;
-
-__global__ __launch_bounds__(64) void k_chain_drift(const BoxDev* __restrict__ boxes, ChainArgs ca, BigArgs ba)
+// base-cell index and fraction of one coordinate (periodic, nodes at integers)
+__device__ __forceinline__ int cell_of(double xc, int L, double Ld, double iL, double& fr)
 {
-    if (blockIdx.x % XCD_SPREAD) return;
-    __builtin_amdgcn_s_setprio(3);
-    const int2 blk = ba.blocks[blockIdx.x / XCD_SPREAD];
-    const BoxDev& bx = boxes[blk.x];
-    const int b = blk.y + (int)threadIdx.x;
-    if (b >= bx.N) return;
-    const uint64_t g = bx.bead_off + b;
-    const double dt = bx.dt, hdt_m = 0.5 * dt / bx.mass;
-#pragma unroll
-    for (int c = 0; c < 3; ++c) {
-        const double v = ca.v[3 * g + c] + ca.f[3 * g + c] * hdt_m;
-        ca.v[3 * g + c] = v;
-        ba.xb[3 * g + c] = ca.x[3 * g + c] + v * dt;
-    }
-    ba.cb[4 * g] = -1; ba.cb[4 * g + 1] = -1; ba.cb[4 * g + 2] = -1; ba.cb[4 * g + 3] = 0;
+    const double xt = xc - Ld * floor(xc * iL);
+    const double fl = floor(xt);
+    fr = xt - fl;
+    int ii = (int)fl;
+    if (ii >= L) ii -= L;
+    if (ii < 0) ii += L;
+    return ii;
+}
+
+__device__ __forceinline__ uint32_t node_of(int ix, int iy, int iz, int L)
+{
+    ix = ix >= L ? ix - L : (ix < 0 ? ix + L : ix);
+    iy = iy >= L ? iy - L : (iy < 0 ? iy + L : iy);
+    iz = iz >= L ? iz - L : (iz < 0 ? iz + L : iz);
+    return (uint32_t)ix + (uint32_t)L * ((uint32_t)iy + (uint32_t)L * (uint32_t)iz);
+}
+
+// nearest node of a bead position, per axis
+__device__ __forceinline__ int nearest_of(double xc, int L, double Ld, double iL)
+{
+    const double xt = xc - Ld * floor(xc * iL);
+    int n = (int)floor(xt + 0.5);
+    return n >= L ? n - L : n;
 }
 
 template <typename R>
-__global__ __launch_bounds__(64) void k_chain_sub(const BoxDev* __restrict__ boxes, const R* __restrict__ A,
-                                                  ChainArgs ca, BigArgs ba, int s, Ctrl* __restrict__ ctrl,
-                                                  uint32_t s_off)
+__global__ __launch_bounds__(256) void k_near_nodes(const BoxDev* __restrict__ boxes,
+                                                    const int32_t* __restrict__ list, const R* __restrict__ A,
+                                                    ChainArgs ca, R* __restrict__ near_u, int4* __restrict__ near_c)
 {
-    __shared__ double xs[3 * MAXB];
-    if (blockIdx.x % XCD_SPREAD) return;
-    // the chain is a serial chain of short launches running beside the
-    // bandwidth-bound collide kernel: its waves take issue priority
-    __builtin_amdgcn_s_setprio(3);
-    const int2 blk = ba.blocks[blockIdx.x / XCD_SPREAD];
-    const int bi = blk.x;
+    const BoxDev& bx = boxes[list[blockIdx.y]];
+    const int N = bx.N, L = bx.L;
+    const int tid = (int)(blockIdx.x * blockDim.x + threadIdx.x);
+    if (tid >= N * NEAR) return;
+    const int b = tid / NEAR, q = tid - b * NEAR;
+    const uint64_t g = bx.bead_off + (uint64_t)b;
+    const double Ld = (double)L, iL = bx.inv_L;
+    const int n0 = nearest_of(ca.x[3 * g], L, Ld, iL), n1 = nearest_of(ca.x[3 * g + 1], L, Ld, iL),
+              n2 = nearest_of(ca.x[3 * g + 2], L, Ld, iL);
+    if (q == 0) near_c[g] = make_int4(n0, n1, n2, 0);
+    const int ix = n0 - 1 + q % 3, iy = n1 - 1 + (q / 3) % 3, iz = n2 - 1 + q / 9;
+    const uint32_t node = node_of(ix, iy, iz, L);
+    const uint32_t nz = node / ((uint32_t)L * (uint32_t)L), rem = node - nz * (uint32_t)L * (uint32_t)L;
+    const uint32_t ny = rem / (uint32_t)L, nx = rem - ny * (uint32_t)L;
+    const Upwind up(nx, ny, nz, (uint32_t)L);
+    R d[19];
+    gather_pre<R, false>(A + bx.pop_off, bx.ps, up, d);
+    double rho = 0.0, jx = 0.0, jy = 0.0, jz = 0.0;
+#pragma unroll
+    for (int i = 0; i < 19; ++i) {
+        const double di = (double)d[i];
+        rho += di;
+        if (cxv(i)) jx += cxv(i) * di;
+        if (cyv(i)) jy += cyv(i) * di;
+        if (czv(i)) jz += czv(i) * di;
+    }
+    rho += bx.rho0;
+    const double inv_tau = 1.0 / bx.tau_lb;
+    R* o = near_u + (g * NEAR + (uint64_t)q) * 3;
+    o[0] = (R)(jx / rho * inv_tau);
+    o[1] = (R)(jy / rho * inv_tau);
+    o[2] = (R)(jz / rho * inv_tau);
+}
+
+// one substep of one bead, as k_spread reads it
+constexpr int REC = 8;   // doubles: fraction x3, coupling force x3, base node, unused
+
+template <typename R>
+__global__ __launch_bounds__(WG_MAXB) void k_chain_wg(const BoxDev* __restrict__ boxes,
+                                                      const int32_t* __restrict__ list,
+                                                      const R* __restrict__ A, ChainArgs ca,
+                                                      const R* __restrict__ near_u,
+                                                      const int4* __restrict__ near_c,
+                                                      double* __restrict__ rec, Ctrl* __restrict__ ctrl,
+                                                      uint32_t s_off)
+{
+    __shared__ double xs[3 * WG_MAXB];           // current positions
+    __shared__ double x0s[3 * WG_MAXB];          // positions at the last list build
+    __shared__ uint16_t nls[NL_SLOTS * WG_MAXB];  // neighbour k of bead b at [k * WG_MAXB + b]
+    __builtin_amdgcn_s_setprio(3);   // latency-bound chain beside the bandwidth-bound collide
+    const int bi = list[blockIdx.x];
     const BoxDev& bx = boxes[bi];
     const int N = bx.N;
-    const int b = blk.y + (int)threadIdx.x;
+    const int b = (int)threadIdx.x;
     const bool act = b < N;
     const uint64_t g = bx.bead_off + (uint64_t)(act ? b : 0);
     const uint32_t t = ctrl->step + s_off;
-    const int S = bx.substeps;
-    if (s >= S) return;   // boxes with fewer substeps are done
-    const uint64_t tb = ca.total_beads;
-    const double* xcur = ba.xb + (uint64_t)(s & 1) * 3 * tb + 3 * bx.bead_off;
-    for (int k = threadIdx.x; k < 3 * N; k += 64) xs[k] = xcur[k];
-    __syncthreads();
-    if (!act) return;
     const int L = bx.L;
     const double Ld = (double)L, iL = bx.inv_L;
-    const double dt = bx.dt, hdt_m = 0.5 * dt / bx.mass, inv_tau = 1.0 / bx.tau_lb, eps24 = 24.0 * bx.eps;
-    double x[3] = {xs[3 * b], xs[3 * b + 1], xs[3 * b + 2]};
-    double v[3] = {ca.v[3 * g], ca.v[3 * g + 1], ca.v[3 * g + 2]};
-    uint32_t hbits = 0;
-
-    // neighbour list: rebuilt in the substep a previous substep asked for
-    const uint32_t sigma = t * (uint32_t)S + (uint32_t)s + 1u;   // global substep id, never 0
-    int nl_n = ca.nl_cnt[g];
+    const double dt = bx.dt, hdt_m = 0.5 * dt / bx.mass;
+    const double eps24 = 24.0 * bx.eps;
     const double rl = sqrt(bx.rc2) + NL_SKIN;
-    if (nl_n == -2 || ba.nl_req[bi] == sigma) {
-        int cnt = 0;
-        for (int j = 0; j < N; ++j) {
-            if (j == b) continue;
-            double d0 = x[0] - xs[3 * j], d1 = x[1] - xs[3 * j + 1], d2 = x[2] - xs[3 * j + 2];
-            d0 -= Ld * rint(d0 * iL); d1 -= Ld * rint(d1 * iL); d2 -= Ld * rint(d2 * iL);
-            if (d0 * d0 + d1 * d1 + d2 * d2 < rl * rl) {
-                if (cnt < ca.nl_cap) ca.nl_idx[g * ca.nl_cap + cnt] = (uint16_t)j;
-                ++cnt;
-            }
-        }
-        nl_n = cnt > ca.nl_cap ? -1 : cnt;
-        ca.nl_cnt[g] = nl_n;
-#pragma unroll
-        for (int c = 0; c < 3; ++c) ca.nl_x0[3 * g + c] = x[c];
-        if (b == 0) atomicAdd(&ca.nl_rebuilds[bi], 1u);
-    }
-    double W[3] = {0, 0, 0};
-    if (nl_n >= 0) {
-        const uint16_t* nl = ca.nl_idx + g * ca.nl_cap;
-        auto jof = [&](int k) { return (int)nl[k]; };
-        for (int k = 0; k < nl_n; k += 4) wca_add4(x, xs, jof, k, nl_n, 1, b, Ld, iL, bx.rc2, bx.sigsq, eps24, W);
-    } else {
-        auto jof = [](int k) { return k; };
-        for (int j = 0; j < N; j += 4) wca_add4(x, xs, jof, j, N, 1, b, Ld, iL, bx.rc2, bx.sigsq, eps24, W);
-    }
-    double F[3] = {0, 0, 0};
-    hbits |= fene_force(bx, b, N, x, xs, F);
-    F[0] += W[0]; F[1] += W[1]; F[2] += W[2];
+    const double rl2 = rl * rl;
+    const int nl_cap = ca.nl_cap < NL_SLOTS ? ca.nl_cap : NL_SLOTS;
 
-    // stencil and its cache
-    int i0[3];
-    double fr[3];
-#pragma unroll
-    for (int c = 0; c < 3; ++c) {
-        const double xt = x[c] - Ld * floor(x[c] * iL);
-        const double fl = floor(xt);
-        fr[c] = xt - fl;
-        int ii = (int)fl;
-        if (ii >= L) ii -= L;
-        if (ii < 0) ii += L;
-        i0[c] = ii;
-    }
-    int tcnt = ba.cb[4 * g + 3];
-    double cu[8][3], acc[8][3];
-    uint32_t cnode[8];
-    const bool have = ba.cb[4 * g] >= 0;
-    const bool same = have && ba.cb[4 * g] == i0[0] && ba.cb[4 * g + 1] == i0[1] && ba.cb[4 * g + 2] == i0[2];
-    if (have) {
-        const int cb0 = ba.cb[4 * g], cb1 = ba.cb[4 * g + 1], cb2 = ba.cb[4 * g + 2];
-#pragma unroll
-        for (int k = 0; k < 8; ++k) {
-            const int ix = cb0 + (k & 1), iy = cb1 + ((k >> 1) & 1), iz = cb2 + ((k >> 2) & 1);
-            cnode[k] = (uint32_t)(ix >= L ? ix - L : ix) +
-                       (uint32_t)L * ((uint32_t)(iy >= L ? iy - L : iy) + (uint32_t)L * (uint32_t)(iz >= L ? iz - L : iz));
-#pragma unroll
-            for (int c = 0; c < 3; ++c) { acc[k][c] = ba.acc[24 * g + 3 * k + c]; cu[k][c] = ba.cu[24 * g + 3 * k + c]; }
-        }
-    }
-    if (!same) {
-        if (have) hbits |= flush_stencil(ca, bx.node_off, g, cnode, acc, bx.tau_lb, tcnt);
-#pragma unroll
-        for (int k = 0; k < 8; ++k) {
-            const int ix = i0[0] + (k & 1), iy = i0[1] + ((k >> 1) & 1), iz = i0[2] + ((k >> 2) & 1);
-            cnode[k] = (uint32_t)(ix >= L ? ix - L : ix) +
-                       (uint32_t)L * ((uint32_t)(iy >= L ? iy - L : iy) + (uint32_t)L * (uint32_t)(iz >= L ? iz - L : iz));
-            acc[k][0] = acc[k][1] = acc[k][2] = 0.0;
-        }
-        stencil_velocities<R, double, false>(A + bx.pop_off, bx.ps, i0, L, bx.rho0, inv_tau, cu);
-#pragma unroll
-        for (int k = 0; k < 8; ++k)
-#pragma unroll
-            for (int c = 0; c < 3; ++c) ba.cu[24 * g + 3 * k + c] = cu[k][c];
-        ba.cb[4 * g] = i0[0]; ba.cb[4 * g + 1] = i0[1]; ba.cb[4 * g + 2] = i0[2];
-    }
-    double wt[8], ub[3] = {0, 0, 0};
-#pragma unroll
-    for (int k = 0; k < 8; ++k) {
-        wt[k] = ((k & 1) ? fr[0] : 1.0 - fr[0]) * (((k >> 1) & 1) ? fr[1] : 1.0 - fr[1]) *
-                (((k >> 2) & 1) ? fr[2] : 1.0 - fr[2]);
-        ub[0] += wt[k] * cu[k][0]; ub[1] += wt[k] * cu[k][1]; ub[2] += wt[k] * cu[k][2];
-    }
-    const U4 w = philox10(U4{(uint32_t)b, t, (1u << 16) | (uint32_t)s, 0u}, bx.seed, bx.box_id);
-    const uint32_t ws[3] = {w.x, w.y, w.z};
-    double f[3], fcl[3];
-#pragma unroll
-    for (int c = 0; c < 3; ++c) {
-        const double ffr = -bx.zeta * (v[c] - ub[c]);
-        const double frn = bx.bead_noise * unit_noise<double>(ws[c]);
-        fcl[c] = ffr + frn;
-        f[c] = F[c] + fcl[c];
-        v[c] += f[c] * hdt_m;
-    }
-#pragma unroll
-    for (int k = 0; k < 8; ++k) {
-        acc[k][0] -= wt[k] * fcl[0] * dt;
-        acc[k][1] -= wt[k] * fcl[1] * dt;
-        acc[k][2] -= wt[k] * fcl[2] * dt;
-    }
-    if (s + 1 < S) {
-        // first half kick and drift of the next substep; ask for a list
-        // rebuild there if this bead moved too far since the last build
-        double* xn = ba.xb + (uint64_t)((s + 1) & 1) * 3 * tb + 3 * g;
-        double dd = 0.0;
+    double x[3] = {0, 0, 0}, v[3] = {0, 0, 0}, f[3] = {0, 0, 0};
+    int nl_n = -2;
+    int4 nc = make_int4(0, 0, 0, 0);
+    if (act) {
 #pragma unroll
         for (int c = 0; c < 3; ++c) {
-            v[c] += f[c] * hdt_m;
-            const double xn_c = x[c] + v[c] * dt;
-            xn[c] = xn_c;
-            const double e = xn_c - ca.nl_x0[3 * g + c];
-            dd += e * e;
+            x[c] = ca.x[3 * g + c]; v[c] = ca.v[3 * g + c]; f[c] = ca.f[3 * g + c];
+            x0s[3 * b + c] = ca.nl_x0[3 * g + c];
         }
-        if (dd > 0.25 * NL_SKIN * NL_SKIN) atomicMax(&ba.nl_req[bi], sigma + 1u);
+        nc = near_c[g];
+        nl_n = ca.nl_cnt[g];
+        for (int k = 0; k < (nl_n > 0 ? nl_n : 0); ++k) nls[k * WG_MAXB + b] = ca.nl_idx[g * ca.nl_cap + k];
+    }
+    int rebuilds = 0;
+    int cb0 = -1, cb1 = -1, cb2 = -1;   // base cell of the cached stencil
+    R cu[8][3];                          // its node velocities (MD units), storage precision
+    uint32_t hbits = 0;
+    int tcnt = 0;
+
+    for (int s = 0; s < bx.substeps; ++s) {
+        if (act) {
 #pragma unroll
-        for (int k = 0; k < 8; ++k)
+            for (int c = 0; c < 3; ++c) {
+                v[c] += f[c] * hdt_m;
+                x[c] += v[c] * dt;
+            }
+        }
+        __syncthreads();   // every read of xs by the previous substep is done
+        bool rebuild = false;
+        if (act) {
+            xs[3 * b] = x[0]; xs[3 * b + 1] = x[1]; xs[3 * b + 2] = x[2];
+            const double e0 = x[0] - x0s[3 * b], e1 = x[1] - x0s[3 * b + 1], e2 = x[2] - x0s[3 * b + 2];
+            rebuild = nl_n == -2 || e0 * e0 + e1 * e1 + e2 * e2 > 0.25 * NL_SKIN * NL_SKIN;
+        }
+        // one bead past half the skin rebuilds every list; also publishes xs
+        rebuild = __syncthreads_or(rebuild);
+        if (rebuild && act) {
+            ++rebuilds;
+            int cnt = 0;
+            for (int j = 0; j < N; ++j) {
+                if (j == b) continue;
+                double d0 = x[0] - xs[3 * j], d1 = x[1] - xs[3 * j + 1], d2 = x[2] - xs[3 * j + 2];
+                d0 -= Ld * rint(d0 * iL); d1 -= Ld * rint(d1 * iL); d2 -= Ld * rint(d2 * iL);
+                if (d0 * d0 + d1 * d1 + d2 * d2 < rl2) {
+                    if (cnt < nl_cap) {
+                        nls[cnt * WG_MAXB + b] = (uint16_t)j;
+                        ca.nl_idx[g * ca.nl_cap + cnt] = (uint16_t)j;
+                    }
+                    ++cnt;
+                }
+            }
+            nl_n = cnt > nl_cap ? -1 : cnt;   // -1: overflow, the full loop is used
+            ca.nl_cnt[g] = nl_n;
 #pragma unroll
-            for (int c = 0; c < 3; ++c) ba.acc[24 * g + 3 * k + c] = acc[k][c];
-        ba.cb[4 * g + 3] = tcnt;
+            for (int c = 0; c < 3; ++c) { x0s[3 * b + c] = x[c]; ca.nl_x0[3 * g + c] = x[c]; }
+        }
+        if (act) {
+            // stencil first: the last force is dead after the drift
+            double fr[3];
+            const int i0 = cell_of(x[0], L, Ld, iL, fr[0]), i1 = cell_of(x[1], L, Ld, iL, fr[1]),
+                      i2 = cell_of(x[2], L, Ld, iL, fr[2]);
+            if (i0 != cb0 || i1 != cb1 || i2 != cb2) {
+                cb0 = i0; cb1 = i1; cb2 = i2;
 #pragma unroll
-        for (int c = 0; c < 3; ++c) { ca.v[3 * g + c] = v[c]; ca.f[3 * g + c] = f[c]; }
-    } else {
-        // last substep: hand over the impulse, store the bead state
-        hbits |= flush_stencil(ca, bx.node_off, g, cnode, acc, bx.tau_lb, tcnt);
+                for (int k = 0; k < 8; ++k) {
+                    const uint32_t node = node_of(cb0 + (k & 1), cb1 + ((k >> 1) & 1), cb2 + ((k >> 2) & 1), L);
+                    if (tcnt < ca.touch_cap) ca.touched[g * ca.touch_cap + tcnt] = node;
+                    else hbits |= H_TABLE;
+                    ++tcnt;
+                }
+                // offset of the base cell in the bead's 3x3x3 table: the
+                // stencil lies inside it when the base cell is the nearest
+                // node or the one below, on every axis
+                int d0 = cb0 - nc.x + 1, d1 = cb1 - nc.y + 1, d2 = cb2 - nc.z + 1;
+                d0 = d0 < 0 ? d0 + L : (d0 >= L ? d0 - L : d0);
+                d1 = d1 < 0 ? d1 + L : (d1 >= L ? d1 - L : d1);
+                d2 = d2 < 0 ? d2 + L : (d2 >= L ? d2 - L : d2);
+                if (d0 <= 1 && d1 <= 1 && d2 <= 1) {
+                    const R* tb = near_u + g * NEAR * 3;
+#pragma unroll
+                    for (int k = 0; k < 8; ++k) {
+                        const int q = (d0 + (k & 1)) + 3 * (d1 + ((k >> 1) & 1)) + 9 * (d2 + ((k >> 2) & 1));
+                        cu[k][0] = tb[3 * q]; cu[k][1] = tb[3 * q + 1]; cu[k][2] = tb[3 * q + 2];
+                    }
+                } else {   // moved past the table within this LB step: read the populations
+                    const int i0v[3] = {cb0, cb1, cb2};
+                    stencil_velocities<R, R, 1>(A + bx.pop_off, bx.ps, i0v, L, bx.rho0, 1.0 / bx.tau_lb, cu);
+                }
+            }
+            double F[3] = {0, 0, 0};
+            if (nl_n >= 0) {
+                auto jof = [&](int k) { return (int)nls[k * WG_MAXB + b]; };
+                for (int k = 0; k < nl_n; k += 4) wca_add4(x, xs, jof, k, nl_n, 1, b, Ld, iL, bx.rc2, bx.sigsq, eps24, F);
+            } else {
+                auto jof = [](int k) { return k; };
+                for (int j = 0; j < N; j += 4) wca_add4(x, xs, jof, j, N, 1, b, Ld, iL, bx.rc2, bx.sigsq, eps24, F);
+            }
+            double Ff[3] = {0, 0, 0};
+            hbits |= fene_force(bx, b, N, x, xs, Ff);
+            F[0] = Ff[0] + F[0]; F[1] = Ff[1] + F[1]; F[2] = Ff[2] + F[2];
+            double ub[3] = {0, 0, 0};
+#pragma unroll
+            for (int k = 0; k < 8; ++k) {
+                const double wk = ((k & 1) ? fr[0] : 1.0 - fr[0]) * (((k >> 1) & 1) ? fr[1] : 1.0 - fr[1]) *
+                                  (((k >> 2) & 1) ? fr[2] : 1.0 - fr[2]);
+                ub[0] += wk * (double)cu[k][0]; ub[1] += wk * (double)cu[k][1]; ub[2] += wk * (double)cu[k][2];
+            }
+            const U4 w = philox10(U4{(uint32_t)b, t, (1u << 16) | (uint32_t)s, 0u}, bx.seed, bx.box_id);
+            const uint32_t ws[3] = {w.x, w.y, w.z};
+            double fcl[3];
+#pragma unroll
+            for (int c = 0; c < 3; ++c) {
+                const double ffr = -bx.zeta * (v[c] - ub[c]);
+                const double frn = bx.bead_noise * unit_noise<double>(ws[c]);
+                fcl[c] = ffr + frn;
+                f[c] = F[c] + fcl[c];
+                v[c] += f[c] * hdt_m;
+            }
+            double* r = rec + ((uint64_t)s * ca.total_beads + g) * REC;
+            r[0] = fr[0]; r[1] = fr[1]; r[2] = fr[2];
+            r[3] = fcl[0]; r[4] = fcl[1]; r[5] = fcl[2];
+            r[6] = (double)node_of(cb0, cb1, cb2, L);
+            if (s + 1 == bx.substeps) {
+#pragma unroll
+                for (int c = 0; c < 3; ++c) ca.fc[3 * g + c] = fcl[c];
+            }
+        }
+    }
+    if (act) {
         ca.touched_cnt[g] = tcnt < ca.touch_cap ? tcnt : ca.touch_cap;
 #pragma unroll
         for (int c = 0; c < 3; ++c) {
-            ca.x[3 * g + c] = x[c]; ca.v[3 * g + c] = v[c]; ca.f[3 * g + c] = f[c]; ca.fc[3 * g + c] = fcl[c];
+            ca.x[3 * g + c] = x[c]; ca.v[3 * g + c] = v[c]; ca.f[3 * g + c] = f[c];
         }
         if (ca.vhist) {
             double* hv = ca.vhist + ((uint64_t)(t % (uint32_t)ca.hist_len) * ca.total_beads + g) * 3;
             hv[0] = v[0]; hv[1] = v[1]; hv[2] = v[2];
         }
-        // the drift of the next step's first substep is known already: ask for
-        // a rebuild there if it takes the bead too far from its build position
-        double dd = 0.0;
+        if (hbits) atomicOr(&ctrl->health, hbits);
+    }
+    if (b == 0 && rebuilds) atomicAdd(&ca.nl_rebuilds[bi], (uint32_t)rebuilds);
+}
+
+// node impulses from the substep records: thread (bead, corner k) accumulates
+// -w_k (F_fric + F_rand) dt over the substeps that share a stencil, in MD
+// units and in substep order, and hands each stencil's sum over when the
+// stencil changes and after the last substep (lattice units, fixed point)
+__global__ __launch_bounds__(256) void k_spread(const BoxDev* __restrict__ boxes, const int32_t* __restrict__ list,
+                                                ChainArgs ca, const double* __restrict__ rec,
+                                                Ctrl* __restrict__ ctrl)
+{
+    const BoxDev& bx = boxes[list[blockIdx.y]];
+    const int N = bx.N, L = bx.L;
+    const int tid = (int)(blockIdx.x * blockDim.x + threadIdx.x);
+    if (tid >= N * 8) return;
+    const int b = tid >> 3, k = tid & 7;
+    const uint64_t g = bx.bead_off + (uint64_t)b;
+    const double dt = bx.dt, tau = bx.tau_lb;
+    unsigned long long* imp = ca.imp + 3 * bx.node_off;
+    uint32_t hb = 0;
+    double acc[3] = {0, 0, 0};
+    uint32_t cur = 0xffffffffu;
+    for (int s = 0; s < bx.substeps; ++s) {
+        const double* r = rec + ((uint64_t)s * ca.total_beads + g) * REC;
+        const uint32_t base = (uint32_t)r[6];
+        const uint32_t bz = base / ((uint32_t)L * (uint32_t)L), rem = base - bz * (uint32_t)L * (uint32_t)L;
+        const uint32_t by = rem / (uint32_t)L, bxn = rem - by * (uint32_t)L;
+        const uint32_t node = node_of((int)bxn + (k & 1), (int)by + ((k >> 1) & 1), (int)bz + ((k >> 2) & 1), L);
+        if (node != cur) {
+            if (cur != 0xffffffffu) {
+#pragma unroll
+                for (int c = 0; c < 3; ++c) {
+                    double q = acc[c] * tau;
+                    if (!(fabs(q) < IMP_MAX)) { hb |= H_FIXED; q = 0.0; }
+                    atomicAdd(imp + 3 * (uint64_t)cur + c, (unsigned long long)(long long)llrint(q * IMP_SCALE));
+                }
+            }
+            cur = node;
+            acc[0] = acc[1] = acc[2] = 0.0;
+        }
+        const double wk = ((k & 1) ? r[0] : 1.0 - r[0]) * (((k >> 1) & 1) ? r[1] : 1.0 - r[1]) *
+                          (((k >> 2) & 1) ? r[2] : 1.0 - r[2]);
+        acc[0] -= wk * r[3] * dt;
+        acc[1] -= wk * r[4] * dt;
+        acc[2] -= wk * r[5] * dt;
+    }
+    if (cur != 0xffffffffu) {
 #pragma unroll
         for (int c = 0; c < 3; ++c) {
-            const double e = x[c] + (v[c] + f[c] * hdt_m) * dt - ca.nl_x0[3 * g + c];
-            dd += e * e;
+            double q = acc[c] * tau;
+            if (!(fabs(q) < IMP_MAX)) { hb |= H_FIXED; q = 0.0; }
+            atomicAdd(imp + 3 * (uint64_t)cur + c, (unsigned long long)(long long)llrint(q * IMP_SCALE));
         }
-        if (dd > 0.25 * NL_SKIN * NL_SKIN) atomicMax(&ba.nl_req[bi], sigma + 1u);
     }
-    if (hbits) atomicOr(&ctrl->health, hbits);
+    if (hb) atomicOr(&ctrl->health, hb);
 }
 
 // ---------------------------------------------------------------- fixup
@@ -925,16 +1019,22 @@ hipError_t launch_couple(const LaunchCtx& c, const void* A, const int32_t* list,
 }
 
 template <typename R>
-hipError_t launch_couple_big(const LaunchCtx& c, const void* A, int block0, int n_blocks, int substeps,
-                             uint32_t s_off)
+hipError_t launch_couple_big(const LaunchCtx& c, const void* A, const int32_t* list, int n_list, int max_n,
+                             uint32_t s_off, hipEvent_t after_table)
 {
-    if (n_blocks == 0) return hipSuccess;
-    BigArgs ba{c.big_blocks + block0, c.xb, c.big_cb, c.big_cu, c.big_acc, c.nl_req};
-    const dim3 grid(n_blocks * XCD_SPREAD);
-    hipLaunchKernelGGL(k_chain_drift, grid, dim3(64), 0, c.stream, c.boxes, chain_args(c), ba);
-    for (int s = 0; s < substeps; ++s)
-        hipLaunchKernelGGL(k_chain_sub<R>, grid, dim3(64), 0, c.stream, c.boxes, (const R*)A, chain_args(c), ba, s,
-                           c.ctrl, s_off);
+    if (n_list == 0) return hipSuccess;
+    if (c.nl_cap > NL_SLOTS || max_n > WG_MAXB || max_n <= 0) return hipErrorInvalidValue;
+    const ChainArgs ca = chain_args(c);
+    hipLaunchKernelGGL(k_near_nodes<R>, dim3((max_n * NEAR + 255) / 256, n_list), dim3(256), 0, c.stream, c.boxes,
+                       list, (const R*)A, ca, (R*)c.near_u, c.near_c);
+    if (after_table) {
+        const hipError_t e = hipEventRecord(after_table, c.stream);
+        if (e != hipSuccess) return e;
+    }
+    hipLaunchKernelGGL(k_chain_wg<R>, dim3(n_list), dim3(WG_MAXB), 0, c.stream, c.boxes, list, (const R*)A, ca,
+                       (const R*)c.near_u, (const int4*)c.near_c, c.sub_rec, c.ctrl, s_off);
+    hipLaunchKernelGGL(k_spread, dim3((max_n * 8 + 255) / 256, n_list), dim3(256), 0, c.stream, c.boxes, list, ca,
+                       (const double*)c.sub_rec, c.ctrl);
     return hipGetLastError();
 }
 
@@ -1366,8 +1466,10 @@ template hipError_t launch_fixup<float>(const LaunchCtx&, const void*, void*, ui
 template hipError_t launch_fixup<double>(const LaunchCtx&, const void*, void*, uint64_t, uint64_t, uint32_t);
 template hipError_t launch_couple<float>(const LaunchCtx&, const void*, const int32_t*, int, int, int, uint32_t);
 template hipError_t launch_couple<double>(const LaunchCtx&, const void*, const int32_t*, int, int, int, uint32_t);
-template hipError_t launch_couple_big<float>(const LaunchCtx&, const void*, int, int, int, uint32_t);
-template hipError_t launch_couple_big<double>(const LaunchCtx&, const void*, int, int, int, uint32_t);
+template hipError_t launch_couple_big<float>(const LaunchCtx&, const void*, const int32_t*, int, int, uint32_t,
+                                            hipEvent_t);
+template hipError_t launch_couple_big<double>(const LaunchCtx&, const void*, const int32_t*, int, int, uint32_t,
+                                             hipEvent_t);
 template hipError_t launch_stats<float>(const LaunchCtx&, const void*, uint32_t, double*, double*);
 template hipError_t launch_stats<double>(const LaunchCtx&, const void*, uint32_t, double*, double*);
 

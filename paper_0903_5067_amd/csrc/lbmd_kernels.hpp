@@ -30,13 +30,10 @@ struct LaunchCtx {
     int32_t* nl_cnt; uint16_t* nl_idx; double* nl_x0; int nl_cap;
     double* vhist; int hist_len; uint64_t total_beads;
     double* tape;                  // substep tape while replaying an adjoint window segment (else null)
-    // chains above 256 beads: one launch per substep over blocks of 64 beads
-    const int2* big_blocks;        // (box, first bead of the block)
-    double* xb;                    // [2][total beads][3] positions of the current / next substep
-    int32_t* big_cb;               // [total beads][4]
-    double* big_cu;                // [total beads][24]
-    double* big_acc;               // [total beads][24]
-    uint32_t* nl_req;              // per box
+    // chains above BIG_CHAIN beads
+    void* near_u;                  // [total beads][27][3] node velocities around each bead (storage precision)
+    int4* near_c;                  // [total beads] nearest node the table is centred on
+    double* sub_rec;               // [most substeps][total beads][8] per-substep records
 };
 
 template <typename R>
@@ -48,10 +45,14 @@ hipError_t launch_fixup(const LaunchCtx& c, const void* A, void* B, uint64_t bea
 template <typename R>
 hipError_t launch_couple(const LaunchCtx& c, const void* A, const int32_t* list, int n_list, int block, int T,
                          uint32_t s_off);
+// chains of BIG_CHAIN+1..1024 beads (at most max_n): one 1024-thread workgroup
+// per box in `list`, with its node-table and impulse-spreading launches.
+// after_table (may be null) is recorded on c.stream between the node-table
+// kernel and the chain kernel.
 template <typename R>
-hipError_t launch_couple_big(const LaunchCtx& c, const void* A, int block0, int n_blocks, int substeps,
-                             uint32_t s_off);
-constexpr int BIG_CHAIN = 256;   // chains above this many beads take the multi-workgroup path
+hipError_t launch_couple_big(const LaunchCtx& c, const void* A, const int32_t* list, int n_list, int max_n,
+                             uint32_t s_off, hipEvent_t after_table);
+constexpr int BIG_CHAIN = 256;   // chains above this many beads take the one-workgroup-per-chain kernel
 hipError_t launch_advance(const LaunchCtx& c, uint32_t n);
 hipError_t launch_init_forces(const LaunchCtx& c, const int32_t* list, int n_list, int block);
 template <typename R>

@@ -45,12 +45,11 @@ struct Layout {
     size_t st_popA = 0, st_popB = 0, st_x = 0, st_v = 0, st_f = 0, st_fc = 0, state_bytes = 0;
     size_t sc_ctrl = 0, sc_boxes = 0, sc_ccs = 0, sc_tilebox = 0, sc_couple = 0, sc_imp = 0, sc_claim = 0,
            sc_touched = 0, sc_tcnt = 0, sc_beadbox = 0, sc_nlcnt = 0, sc_nlidx = 0, sc_nlx0 = 0,
-           sc_part = 0, sc_stat = 0, sc_chain = 0, sc_vhist = 0, sc_nlreb = 0, sc_bigblk = 0, sc_xb = 0,
-           sc_bigcb = 0, sc_bigcu = 0, sc_bigacc = 0, sc_nlreq = 0, scratch_bytes = 0;
+           sc_part = 0, sc_stat = 0, sc_chain = 0, sc_vhist = 0, sc_nlreb = 0, sc_biglist = 0, sc_alllist = 0,
+           sc_nearu = 0, sc_nearc = 0, sc_subrec = 0, scratch_bytes = 0;
     int max_N = 0;         // largest chain taking the one-workgroup path
-    int big_substeps = 0;  // most substeps among chains taking the multi-workgroup path
-    std::vector<int> big_block_off, big_block_cnt;   // per box
-    std::vector<int32_t> big_blocks;                  // (box, first bead) pairs
+    std::vector<int32_t> big_list;                    // boxes whose chain takes the 1024-thread kernel
+    int big_max_n = 0, big_max_sub = 0;              // largest chain and most substeps among them
     std::vector<int32_t> small_list;                  // boxes on the one-workgroup path
     int couple_T = 1, couple_block = 64;
     int touch_cap = 8;
@@ -108,15 +107,14 @@ Layout make_layout(const lb_box_desc* b, int32_t n, int32_t prec, int32_t hist)
         Lo.node_off.push_back(nodes);
         nodes += V;
         const int N = b[i].n_beads;
-        Lo.big_block_off.push_back((int)Lo.big_blocks.size() / 2);
         if (N > BIG_CHAIN) {
-            for (int s0 = 0; s0 < N; s0 += 64) { Lo.big_blocks.push_back(i); Lo.big_blocks.push_back(s0); }
-            Lo.big_substeps = std::max(Lo.big_substeps, b[i].md_substeps);
+            Lo.big_list.push_back(i);
+            Lo.big_max_n = std::max(Lo.big_max_n, N);
+            Lo.big_max_sub = std::max(Lo.big_max_sub, b[i].md_substeps);
         } else if (N > 0) {
             Lo.small_list.push_back(i);
             Lo.max_N = std::max(Lo.max_N, N);
         }
-        Lo.big_block_cnt.push_back((int)Lo.big_blocks.size() / 2 - Lo.big_block_off.back());
     }
     Lo.pop_elems = pop;
     Lo.total_tiles = tiles;
@@ -161,12 +159,14 @@ Layout make_layout(const lb_box_desc* b, int32_t n, int32_t prec, int32_t hist)
     Lo.sc_chain = o; o = align256(o + n * NCHAIN_REC * sizeof(double));
     Lo.sc_vhist = o; o = align256(o + (size_t)hist * std::max<uint64_t>(beads, 1) * 3 * sizeof(double));
     Lo.sc_nlreb = o; o = align256(o + n * sizeof(uint32_t));
-    Lo.sc_bigblk = o; o = align256(o + std::max<size_t>(Lo.big_blocks.size(), 2) * sizeof(int32_t));
-    Lo.sc_xb = o; o = align256(o + 2 * nbx * 3 * sizeof(double));
-    Lo.sc_bigcb = o; o = align256(o + nbx * 4 * sizeof(int32_t));
-    Lo.sc_bigcu = o; o = align256(o + nbx * 24 * sizeof(double));
-    Lo.sc_bigacc = o; o = align256(o + nbx * 24 * sizeof(double));
-    Lo.sc_nlreq = o; o = align256(o + n * sizeof(uint32_t));
+    Lo.sc_biglist = o; o = align256(o + n * sizeof(int32_t));
+    Lo.sc_alllist = o; o = align256(o + n * sizeof(int32_t));
+    {   // tables of the large-chain kernels, sized only when there are such chains
+        const uint64_t nbig = Lo.big_list.empty() ? 1 : nbx;
+        Lo.sc_nearu = o; o = align256(o + nbig * 27 * 3 * Lo.esz);
+        Lo.sc_nearc = o; o = align256(o + nbig * 4 * sizeof(int32_t));
+        Lo.sc_subrec = o; o = align256(o + (uint64_t)std::max(Lo.big_max_sub, 1) * nbig * 8 * sizeof(double));
+    }
     Lo.scratch_bytes = o;
     return Lo;
 }
@@ -204,10 +204,11 @@ struct lb_handle {
     // the chain coupling runs on a second stream, concurrently with the
     // collide kernel of the same step (both only read the current state)
     hipStream_t stream2 = nullptr;
-    hipEvent_t ev_fork = nullptr, ev_join = nullptr;
+    hipEvent_t ev_fork = nullptr, ev_join = nullptr, ev_table = nullptr;
     LaunchCtx ctx{};
     LaunchCtx ctx2{};
-    int32_t* couple_list = nullptr;   // device
+    int32_t* couple_list = nullptr;   // device: boxes on the one-workgroup path (chains <= 256 beads)
+    int32_t* big_list = nullptr;      // device: boxes with chains of 257..1024 beads
     std::vector<int32_t> couple_host; // box indices with beads
     int cur = 0;                      // 0: buffer A holds the current state
     uint64_t step = 0;                // host mirror of the device step counter
@@ -252,18 +253,23 @@ lb_status enqueue_step(lb_handle* h, int from, uint32_t s_off, bool couple)
     const bool any_beads = h->lo.total_beads > 0;
     if (h->batched) {
         const bool fork = couple && any_beads;
+        const int nbig = (int)h->lo.big_list.size();
         if (fork) {
             HIPCHK(h, hipEventRecord(h->ev_fork, h->stream));
             HIPCHK(h, hipStreamWaitEvent(h->stream2, h->ev_fork, 0));
             const LaunchCtx& c2 = h->ctx2;
+            // a chain above 256 beads needs a whole CU (1024 threads, the full
+            // register file): the collide waits for its short node-table
+            // kernel, so the chain kernel queued right behind it is dispatched
+            // onto an idle GPU instead of behind the collide's workgroups
+            if (nbig)
+                HIPCHK(h, f64 ? launch_couple_big<double>(c2, A, h->big_list, nbig, h->lo.big_max_n, s_off, h->ev_table)
+                              : launch_couple_big<float>(c2, A, h->big_list, nbig, h->lo.big_max_n, s_off, h->ev_table));
             if (nc)
                 HIPCHK(h, f64 ? launch_couple<double>(c2, A, h->couple_list, nc, h->lo.couple_block, h->lo.couple_T, s_off)
                               : launch_couple<float>(c2, A, h->couple_list, nc, h->lo.couple_block, h->lo.couple_T, s_off));
-            const int nbig = (int)h->lo.big_blocks.size() / 2;
-            if (nbig)
-                HIPCHK(h, f64 ? launch_couple_big<double>(c2, A, 0, nbig, h->lo.big_substeps, s_off)
-                              : launch_couple_big<float>(c2, A, 0, nbig, h->lo.big_substeps, s_off));
             HIPCHK(h, hipEventRecord(h->ev_join, h->stream2));
+            if (nbig) HIPCHK(h, hipStreamWaitEvent(h->stream, h->ev_table, 0));
         }
         HIPCHK(h, f64 ? launch_collide<double>(c, A, B, -1, 0, (uint32_t)h->lo.total_tiles, s_off)
                       : launch_collide<float>(c, A, B, -1, 0, (uint32_t)h->lo.total_tiles, s_off));
@@ -277,12 +283,10 @@ lb_status enqueue_step(lb_handle* h, int from, uint32_t s_off, bool couple)
             HIPCHK(h, f64 ? launch_couple<double>(c, A, h->couple_list + i, 1, h->lo.couple_block, h->lo.couple_T, s_off)
                           : launch_couple<float>(c, A, h->couple_list + i, 1, h->lo.couple_block, h->lo.couple_T, s_off));
         }
-        for (int b = 0; b < h->n_boxes && couple; ++b) {
-            if (!h->lo.big_block_cnt[b]) continue;
-            HIPCHK(h, f64 ? launch_couple_big<double>(c, A, h->lo.big_block_off[b], h->lo.big_block_cnt[b],
-                                                      h->desc[b].md_substeps, s_off)
-                          : launch_couple_big<float>(c, A, h->lo.big_block_off[b], h->lo.big_block_cnt[b],
-                                                     h->desc[b].md_substeps, s_off));
+        for (int k = 0; k < (int)h->lo.big_list.size() && couple; ++k) {
+            const int nk = h->desc[h->lo.big_list[k]].n_beads;
+            HIPCHK(h, f64 ? launch_couple_big<double>(c, A, h->big_list + k, 1, nk, s_off, nullptr)
+                          : launch_couple_big<float>(c, A, h->big_list + k, 1, nk, s_off, nullptr));
         }
         for (int b = 0; b < h->n_boxes; ++b) {
             HIPCHK(h, f64 ? launch_collide<double>(c, A, B, b, h->lo.tile_begin[b], h->lo.n_tiles[b], s_off)
@@ -426,7 +430,7 @@ lb_status lb_init(const lb_box_desc* boxes, int32_t n_boxes, int32_t precision, 
     chk(up(lo.sc_tilebox, tile_box.data(), tile_box.size() * sizeof(uint32_t)));
     chk(up(lo.sc_couple, h->couple_host.data(), h->couple_host.size() * sizeof(int32_t)));
     chk(up(lo.sc_beadbox, bead_box.data(), bead_box.size() * sizeof(int32_t)));
-    chk(up(lo.sc_bigblk, lo.big_blocks.data(), lo.big_blocks.size() * sizeof(int32_t)));
+    chk(up(lo.sc_biglist, lo.big_list.data(), lo.big_list.size() * sizeof(int32_t)));
     chk(up(lo.sc_nlcnt, nlcnt.data(), nlcnt.size() * sizeof(int32_t)));
     if (nb) chk(hipMemcpy(stp(lo.st_x), bead_x0, nb * 3 * sizeof(double), hipMemcpyHostToDevice));
     if (e != hipSuccess) {
@@ -460,23 +464,22 @@ lb_status lb_init(const lb_box_desc* boxes, int32_t n_boxes, int32_t precision, 
     c.touched_cnt = (int32_t*)sc(lo.sc_tcnt);
     c.touch_cap = lo.touch_cap;
     c.nl_rebuilds = (uint32_t*)sc(lo.sc_nlreb);
-    c.big_blocks = (const int2*)sc(lo.sc_bigblk);
-    c.xb = (double*)sc(lo.sc_xb);
-    c.big_cb = (int32_t*)sc(lo.sc_bigcb);
-    c.big_cu = (double*)sc(lo.sc_bigcu);
-    c.big_acc = (double*)sc(lo.sc_bigacc);
-    c.nl_req = (uint32_t*)sc(lo.sc_nlreq);
     c.bead_box = (const int32_t*)sc(lo.sc_beadbox);
     c.x = (double*)stp(lo.st_x); c.v = (double*)stp(lo.st_v); c.f = (double*)stp(lo.st_f); c.fc = (double*)stp(lo.st_fc);
     c.nl_cnt = (int32_t*)sc(lo.sc_nlcnt); c.nl_idx = (uint16_t*)sc(lo.sc_nlidx); c.nl_x0 = (double*)sc(lo.sc_nlx0);
     c.nl_cap = NL_CAP;
+    c.near_u = sc(lo.sc_nearu);
+    c.near_c = (int4*)sc(lo.sc_nearc);
+    c.sub_rec = (double*)sc(lo.sc_subrec);
     c.vhist = hist_steps > 0 ? (double*)sc(lo.sc_vhist) : nullptr;
     c.hist_len = hist_steps > 0 ? hist_steps : 1;
     c.total_beads = nb;
     h->couple_list = (int32_t*)sc(lo.sc_couple);
+    h->big_list = (int32_t*)sc(lo.sc_biglist);
     e = hipStreamCreateWithFlags(&h->stream2, hipStreamNonBlocking);
     if (e == hipSuccess) e = hipEventCreateWithFlags(&h->ev_fork, hipEventDisableTiming);
     if (e == hipSuccess) e = hipEventCreateWithFlags(&h->ev_join, hipEventDisableTiming);
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&h->ev_table, hipEventDisableTiming);
     if (e != hipSuccess) {
         std::string msg = std::string("second stream: ") + hipGetErrorString(e);
         lb_free(h);
@@ -490,13 +493,11 @@ lb_status lb_init(const lb_box_desc* boxes, int32_t n_boxes, int32_t precision, 
         int mx = 0;
         for (int i = 0; i < n_boxes; ++i)
             if (boxes[i].n_beads > 0) { all.push_back(i); mx = std::max(mx, boxes[i].n_beads); }
-        // the per-box list of the one-workgroup path is reused as scratch for this launch
-        int32_t* dl = (int32_t*)sc(lo.sc_nlreq);
+        // every box with a chain
+        int32_t* dl = (int32_t*)sc(lo.sc_alllist);
         e = all.empty() ? hipSuccess : hipMemcpy(dl, all.data(), all.size() * sizeof(int32_t), hipMemcpyHostToDevice);
         if (e == hipSuccess)
             e = launch_init_forces(c, dl, (int)all.size(), std::max(64, (int)round_up((uint64_t)mx, 64)));
-        if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
-        if (e == hipSuccess) e = hipMemset(dl, 0, n_boxes * sizeof(uint32_t));
     }
     if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
     if (e != hipSuccess) {
@@ -516,7 +517,7 @@ lb_status lb_couple(lb_handle* h)
         const void* A = h->pop(h->cur);
         const LaunchCtx& c = h->ctx;
         const int nc = (int)h->couple_host.size();
-        const int nbig = (int)h->lo.big_blocks.size() / 2;
+        const int nbig = (int)h->lo.big_list.size();
         if (nc) {
             if (h->prec == LB_FP64)
                 HIPCHK(h, launch_couple<double>(c, A, h->couple_list, nc, h->lo.couple_block, h->lo.couple_T, 0));
@@ -525,9 +526,9 @@ lb_status lb_couple(lb_handle* h)
         }
         if (nbig) {
             if (h->prec == LB_FP64)
-                HIPCHK(h, launch_couple_big<double>(c, A, 0, nbig, h->lo.big_substeps, 0));
+                HIPCHK(h, launch_couple_big<double>(c, A, h->big_list, nbig, h->lo.big_max_n, 0, nullptr));
             else
-                HIPCHK(h, launch_couple_big<float>(c, A, 0, nbig, h->lo.big_substeps, 0));
+                HIPCHK(h, launch_couple_big<float>(c, A, h->big_list, nbig, h->lo.big_max_n, 0, nullptr));
         }
     }
     h->pending = true;
@@ -913,7 +914,7 @@ lb_status lb_window_forward(lb_handle* h, void* d_ws, size_t bytes, int32_t T, i
     if (!h || !d_ws) return fail(h, LB_EINVAL, "null argument");
     if (T <= 0 || k <= 0) return fail(h, LB_EINVAL, "T and k must be positive");
     if (h->pending) return fail(h, LB_ESTATE, "impulses pending from lb_couple");
-    if (!h->lo.big_blocks.empty()) return fail(h, LB_EINVAL, "the adjoint window supports chains of at most 256 beads");
+    if (!h->lo.big_list.empty()) return fail(h, LB_EINVAL, "the adjoint window supports chains of at most 256 beads");
     k = std::min(k, T);
     const WinLayout w = win_layout(h, T, k);
     if (bytes < w.bytes) return fail(h, LB_ENOMEM, "window workspace too small");
@@ -1138,6 +1139,7 @@ void lb_free(lb_handle* h)
     if (h->ccd) (void)hipFree(h->ccd);
     if (h->ev_fork) (void)hipEventDestroy(h->ev_fork);
     if (h->ev_join) (void)hipEventDestroy(h->ev_join);
+    if (h->ev_table) (void)hipEventDestroy(h->ev_table);
     if (h->stream2) (void)hipStreamDestroy(h->stream2);
     if (h->own_stream && h->stream) (void)hipStreamDestroy(h->stream);
     delete h;

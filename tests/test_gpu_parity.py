@@ -295,14 +295,15 @@ def test_health_flag_from_nan():
     assert o["health"] & (lbm.HEALTH["density"] | lbm.HEALTH["mach"])
 
 
-# ------------------------------------------------ chains on the multi-workgroup path
+# ------------------------------------------------ chains above 256 beads
 @pytest.mark.parametrize("prec", [FP64, FP32])
-def test_big_chain_matches_oracle(orc, prec):
-    """A 300-bead chain (above 256 beads the substeps run as one launch each over
-    workgroups of 64 beads, with a neighbour list): one coupling, then 30 full
-    steps, against the oracle."""
-    say("big chain", prec)
-    p = params(L=16, N=300, kT=1e-2)
+@pytest.mark.parametrize("L,N", [(16, 257), (20, 1024)])
+def test_big_chain_matches_oracle(orc, prec, L, N):
+    """Chains above 256 beads (one 1024-thread workgroup per chain, neighbour
+    lists in LDS, impulses handed over every substep), the smallest and the
+    largest: one coupling, then 30 full steps, against the oracle."""
+    say("big chain", prec, L, N)
+    p = params(L=L, N=N, kT=1e-2)
     x0 = chain(p)
     n0 = initial_pops(orc, p, amp=0.01, seed=3)
     s = gpu_system([p], prec, xs=[x0], pops=[n0])
