@@ -91,11 +91,20 @@ def copy_calibration():
     import torch
     a = torch.ones(1 << 28, dtype=torch.float32, device="cuda")
     b = torch.empty_like(a)
+    torch.neg(a, out=b)
+    torch.cuda.synchronize()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record()
     for _ in range(10):
         torch.neg(a, out=b)
+    e1.record()
     torch.cuda.synchronize()
-    print(json.dumps({"copy_calibration": {"launches": 10, "read_bytes": a.numel() * 4,
-                                           "write_bytes": b.numel() * 4, "kernel": "torch.neg (elementwise)"}}))
+    us = e0.elapsed_time(e1) * 1e3 / 10
+    print(json.dumps({"copy_calibration": {"launches": 11, "read_bytes": a.numel() * 4,
+                                           "write_bytes": b.numel() * 4, "kernel": "torch.neg (elementwise)",
+                                           "avg_launch_us": round(us, 1),
+                                           "gb_per_s": round(2 * a.numel() * 4 / us / 1e3, 1)}}))
 
 
 def time_steps(s, steps, warmup):
@@ -161,7 +170,8 @@ def adjoint_secondary():
 def cpu_baseline(preset, budget_s=20.0):
     """The oracle (FP64 C, OpenMP) on the host cores: whole LB steps of the
     same box and chain, as many as fit a ~20 s budget (at least one).
-    Returns the report and the oracle state after those steps."""
+    Returns the report and, for the precision study, the oracle's results as
+    plain arrays: step count, populations, observables, weights."""
     import lbinputs
     import oracle
     p = lbinputs.box_params(preset)
@@ -187,10 +197,14 @@ def cpu_baseline(preset, budget_s=20.0):
     rep = {"value": round(mlups, 3), "unit": "MLUPS", "cores": oracle.num_threads(), "kind": "oracle",
            "sample": f"{steps} full LB step(s) of the {L}^3 box with its N={p['N']} chain (after 1 untimed), "
                      f"FP64 oracle, {t1:.1f} s"}
-    return rep, st
+    oo = st.observables()
+    ref = {"t": st.t, "n": st.n, "w": np.array(w),
+           "obs": {"mass": oo[0], "p_fluid": oo[4:7], "p_total": oo[10:13], "com": oo[13:16], "rg2": oo[16],
+                   "re2": oo[17], "mode_sq": oo[19:38]}}
+    return rep, ref
 
 
-def _obs_errors(a, b, w=None):
+def _obs_errors(a, b):
     """Per-observable differences of observation dict a from reference b."""
     def rel(x, y):
         return float(abs(x - y) / max(abs(y), 1e-300))
@@ -203,18 +217,14 @@ def _obs_errors(a, b, w=None):
     return {k: float(f"{v:.3e}") for k, v in out.items()}
 
 
-def precision_study(preset, ost, s_orc, long_steps):
+def precision_study(preset, ref, long_steps):
     """FP32 deviation storage against FP64 storage on the GPU and against the
-    oracle: per-observable differences after the oracle's s_orc steps (all
-    three from the same initial state and noise), and FP32 against FP64 on the
-    GPU after long_steps."""
+    oracle's results from the CPU-baseline leg: per-observable differences
+    after the oracle's steps (all three from the same initial state and
+    noise), and FP32 against FP64 on the GPU after long_steps."""
     import torch
-    import oracle
     import paper_0903_5067_amd as lbm
-    oo = ost.observables()
-    ref = {"mass": oo[0], "p_fluid": oo[4:7], "p_total": oo[10:13], "com": oo[13:16], "rg2": oo[16],
-           "re2": oo[17], "mode_sq": oo[19:38]}
-    c, w, e, b = oracle.tables()
+    s_orc, w = ref["t"], ref["w"]
     res = {"short_steps": s_orc, "long_steps": long_steps}
     obs_short = {}
     for prec, name in ((lbm.FP32_DEV, "fp32_dev"), (lbm.FP64, "fp64")):
@@ -226,9 +236,9 @@ def precision_study(preset, ost, s_orc, long_steps):
         n = s.export_state()["boxes"][0]["n"]
         err = 0.0
         for i in range(19):
-            err = max(err, float(np.max(np.abs(n[i] - ost.n[i]))) / (w[i] * boxes[0]["rho0"]))
+            err = max(err, float(np.max(np.abs(n[i] - ref["n"][i]))) / (w[i] * boxes[0]["rho0"]))
         del n
-        e_o = _obs_errors(ob, ref)
+        e_o = _obs_errors(ob, ref["obs"])
         e_o["pop_rel_max"] = float(f"{err:.3e}")
         res[f"{name}_vs_oracle"] = e_o
         s.step(long_steps - s_orc)
@@ -351,13 +361,13 @@ def main():
         log("secondary", json.dumps(sec))
     if not args.no_cpu:
         log("cpu baseline (oracle) ...")
-        rep, ost = cpu_baseline(args.workload)
+        rep, ref = cpu_baseline(args.workload)
         result["cpu_baseline"] = rep
         if args.workload == "prec256" and not args.no_secondary:
             log("precision study ...")
-            result["precision"] = precision_study(args.workload, ost, ost.t, 2000)
+            result["precision"] = precision_study(args.workload, ref, 2000)
             log("precision", json.dumps(result["precision"]))
-        del ost
+        del ref
     print(json.dumps(result), flush=True)
 
 

@@ -284,7 +284,7 @@ __device__ __forceinline__ uint32_t flush_stencil(const ChainArgs& ca, uint64_t 
 template <typename R, int MAXT = 256>
 __global__ __launch_bounds__(MAXT) void k_couple(const BoxDev* __restrict__ boxes,
                                                  const int32_t* __restrict__ couple_list,
-                                                 const R* __restrict__ A, ChainArgs ca, int T,
+                                                 const R* __restrict__ A, ChainArgs ca,
                                                  Ctrl* __restrict__ ctrl, uint32_t s_off)
 {
     __shared__ double xs[3 * MAXB];
@@ -293,6 +293,9 @@ __global__ __launch_bounds__(MAXT) void k_couple(const BoxDev* __restrict__ boxe
     const int bi = couple_list[blockIdx.x];
     const BoxDev& bx = boxes[bi];
     const int N = bx.N;
+    // lanes per bead depend on this chain's length alone, so a box computes
+    // the same bits in any batch
+    const int T = bx.couple_T;
     const int b = threadIdx.x / T, lane = threadIdx.x % T;
     const bool act = b < N;
     const bool writer = act && lane == 0;
@@ -1008,13 +1011,13 @@ hipError_t launch_fixup(const LaunchCtx& c, const void* A, void* B, uint64_t bea
 }
 
 template <typename R>
-hipError_t launch_couple(const LaunchCtx& c, const void* A, const int32_t* list, int n_list, int block, int T,
+hipError_t launch_couple(const LaunchCtx& c, const void* A, const int32_t* list, int n_list, int block,
                          uint32_t s_off)
 {
     if (n_list == 0) return hipSuccess;
-    if (block > 256) return hipErrorInvalidValue;   // larger chains take the multi-workgroup path
+    if (block > 256) return hipErrorInvalidValue;   // larger chains take the one-workgroup-per-chain kernel
     hipLaunchKernelGGL((k_couple<R, 256>), dim3(n_list), dim3(block), 0, c.stream, c.boxes, list, (const R*)A,
-                       chain_args(c), T, c.ctrl, s_off);
+                       chain_args(c), c.ctrl, s_off);
     return hipGetLastError();
 }
 
@@ -1464,8 +1467,8 @@ template hipError_t launch_collide<float>(const LaunchCtx&, const void*, void*, 
 template hipError_t launch_collide<double>(const LaunchCtx&, const void*, void*, int, uint32_t, uint32_t, uint32_t);
 template hipError_t launch_fixup<float>(const LaunchCtx&, const void*, void*, uint64_t, uint64_t, uint32_t);
 template hipError_t launch_fixup<double>(const LaunchCtx&, const void*, void*, uint64_t, uint64_t, uint32_t);
-template hipError_t launch_couple<float>(const LaunchCtx&, const void*, const int32_t*, int, int, int, uint32_t);
-template hipError_t launch_couple<double>(const LaunchCtx&, const void*, const int32_t*, int, int, int, uint32_t);
+template hipError_t launch_couple<float>(const LaunchCtx&, const void*, const int32_t*, int, int, uint32_t);
+template hipError_t launch_couple<double>(const LaunchCtx&, const void*, const int32_t*, int, int, uint32_t);
 template hipError_t launch_couple_big<float>(const LaunchCtx&, const void*, const int32_t*, int, int, uint32_t,
                                             hipEvent_t);
 template hipError_t launch_couple_big<double>(const LaunchCtx&, const void*, const int32_t*, int, int, uint32_t,

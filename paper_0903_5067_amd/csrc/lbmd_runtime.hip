@@ -51,7 +51,8 @@ struct Layout {
     std::vector<int32_t> big_list;                    // boxes whose chain takes the 1024-thread kernel
     int big_max_n = 0, big_max_sub = 0;              // largest chain and most substeps among them
     std::vector<int32_t> small_list;                  // boxes on the one-workgroup path
-    int couple_T = 1, couple_block = 64;
+    std::vector<int> couple_T;   // per box: lanes per bead on the one-workgroup path
+    int couple_block = 64;
     int touch_cap = 8;
 };
 
@@ -121,13 +122,18 @@ Layout make_layout(const lb_box_desc* b, int32_t n, int32_t prec, int32_t hist)
     Lo.total_beads = beads;
     Lo.total_nodes = nodes;
     // lanes per bead in the coupling workgroup: split the pair loop while the
-    // chain is small, one lane per bead (up to 1024) otherwise
-    if (Lo.max_N > 0) {
+    // chain is small (a function of the box's own N, so that a box computes
+    // the same bits alone and in any batch), one lane per bead otherwise
+    int widest = 0;
+    for (int i = 0; i < n; ++i) {
+        const int N = b[i].n_beads;
         int T = 1;
-        while (T < 16 && 2 * T * Lo.max_N <= 256) T *= 2;
-        Lo.couple_T = T;
-        Lo.couple_block = (int)round_up((uint64_t)T * Lo.max_N, 64);
+        if (N > 0 && N <= BIG_CHAIN)
+            while (T < 16 && 2 * T * N <= 256) T *= 2;
+        Lo.couple_T.push_back(T);
+        if (N > 0 && N <= BIG_CHAIN) widest = std::max(widest, T * N);
     }
+    if (widest > 0) Lo.couple_block = (int)round_up((uint64_t)widest, 64);
     size_t o = 0;
     Lo.st_popA = o; o = align256(o + pop * Lo.esz);
     Lo.st_popB = o; o = align256(o + pop * Lo.esz);
@@ -266,8 +272,8 @@ lb_status enqueue_step(lb_handle* h, int from, uint32_t s_off, bool couple)
                 HIPCHK(h, f64 ? launch_couple_big<double>(c2, A, h->big_list, nbig, h->lo.big_max_n, s_off, h->ev_table)
                               : launch_couple_big<float>(c2, A, h->big_list, nbig, h->lo.big_max_n, s_off, h->ev_table));
             if (nc)
-                HIPCHK(h, f64 ? launch_couple<double>(c2, A, h->couple_list, nc, h->lo.couple_block, h->lo.couple_T, s_off)
-                              : launch_couple<float>(c2, A, h->couple_list, nc, h->lo.couple_block, h->lo.couple_T, s_off));
+                HIPCHK(h, f64 ? launch_couple<double>(c2, A, h->couple_list, nc, h->lo.couple_block, s_off)
+                              : launch_couple<float>(c2, A, h->couple_list, nc, h->lo.couple_block, s_off));
             HIPCHK(h, hipEventRecord(h->ev_join, h->stream2));
             if (nbig) HIPCHK(h, hipStreamWaitEvent(h->stream, h->ev_table, 0));
         }
@@ -280,8 +286,8 @@ lb_status enqueue_step(lb_handle* h, int from, uint32_t s_off, bool couple)
     } else {
         for (int i = 0; i < nc; ++i) {
             if (!couple) break;
-            HIPCHK(h, f64 ? launch_couple<double>(c, A, h->couple_list + i, 1, h->lo.couple_block, h->lo.couple_T, s_off)
-                          : launch_couple<float>(c, A, h->couple_list + i, 1, h->lo.couple_block, h->lo.couple_T, s_off));
+            HIPCHK(h, f64 ? launch_couple<double>(c, A, h->couple_list + i, 1, h->lo.couple_block, s_off)
+                          : launch_couple<float>(c, A, h->couple_list + i, 1, h->lo.couple_block, s_off));
         }
         for (int k = 0; k < (int)h->lo.big_list.size() && couple; ++k) {
             const int nk = h->desc[h->lo.big_list[k]].n_beads;
@@ -391,6 +397,7 @@ lb_status lb_init(const lb_box_desc* boxes, int32_t n_boxes, int32_t precision, 
         b.node_off = lo.node_off[i]; b.pop_off = lo.pop_off[i]; b.ps = lo.ps[i]; b.bead_off = lo.bead_off[i];
         b.tile_begin = lo.tile_begin[i]; b.n_tiles = lo.n_tiles[i];
         b.therm = d.thermalize; b.substeps = d.md_substeps;
+        b.couple_T = lo.couple_T[i]; b.pad_ = 0;
         b.rho0 = d.rho0; b.gam_b = 1 - d.omega_bulk; b.gam_s = 1 - d.omega_shear; b.gam_g = 1 - d.omega_ghost;
         b.mu = 3.0 * d.kT * d.tau_lb * d.tau_lb;
         b.tau_lb = d.tau_lb; b.dt = d.md_dt; b.mass = d.bead_mass; b.zeta = d.zeta; b.k_fene = d.k_fene;
@@ -520,9 +527,9 @@ lb_status lb_couple(lb_handle* h)
         const int nbig = (int)h->lo.big_list.size();
         if (nc) {
             if (h->prec == LB_FP64)
-                HIPCHK(h, launch_couple<double>(c, A, h->couple_list, nc, h->lo.couple_block, h->lo.couple_T, 0));
+                HIPCHK(h, launch_couple<double>(c, A, h->couple_list, nc, h->lo.couple_block, 0));
             else
-                HIPCHK(h, launch_couple<float>(c, A, h->couple_list, nc, h->lo.couple_block, h->lo.couple_T, 0));
+                HIPCHK(h, launch_couple<float>(c, A, h->couple_list, nc, h->lo.couple_block, 0));
         }
         if (nbig) {
             if (h->prec == LB_FP64)
@@ -854,8 +861,8 @@ lb_status window_step(lb_handle* h, unsigned long long* imp_copy, double* tape)
     c.tape = tape;
     const int nc = (int)h->couple_host.size();
     if (nc)
-        HIPCHK(h, f64 ? launch_couple<double>(c, A, h->couple_list, nc, h->lo.couple_block, h->lo.couple_T, 0)
-                      : launch_couple<float>(c, A, h->couple_list, nc, h->lo.couple_block, h->lo.couple_T, 0));
+        HIPCHK(h, f64 ? launch_couple<double>(c, A, h->couple_list, nc, h->lo.couple_block, 0)
+                      : launch_couple<float>(c, A, h->couple_list, nc, h->lo.couple_block, 0));
     if (imp_copy && h->lo.total_beads)
         HIPCHK(h, hipMemcpyAsync(imp_copy, c.imp, 3 * h->lo.total_nodes * sizeof(unsigned long long),
                                  hipMemcpyDeviceToDevice, h->stream));

@@ -1,6 +1,6 @@
-"""Full-size parity in the benchmark's launch configuration: the 256^3 box with
-its N=1024 chain, FP32 deviation storage, batched launches replayed from HIP
-graphs of 20 steps, autotuned collide launch shape.
+"""Full-size parity in the benchmark's launch configuration (batched launches
+replayed from HIP graphs of 20 steps, autotuned collide launch shape), on the
+256^3 box with its N=1024 chain, the 64^3 box with N=64 and the 256-box sweep.
 
 The oracle cannot afford whole 256^3 runs inside a test, so the checks are on
 outputs it computes one by one from the GPU's own inputs:
@@ -96,3 +96,82 @@ def test_prec256_sampled_parity(orc):
             worst = max(worst, abs(got - post[i]) / (w[i] * p["rho0"]))
     say("prec256: sampled nodes", len(sample), "impulse nodes", len(hit), "worst rel err", worst)
     assert worst < 1e-6
+
+
+def test_single64_first_200_steps(orc):
+    """The 64^3 box with its N=64 chain, FP32 deviation storage, the
+    benchmark's launch configuration (batched, graphs of 20 steps): bead
+    velocities after each of the first 200 steps, their autocorrelation
+    (lags 0..50) and Rg^2 / Re^2 after 200 steps against the oracle."""
+    import lbinputs
+    import paper_0903_5067_amd as lbm
+    p = lbinputs.box_params("single64")
+    L, N, T = int(p["L"]), int(p["N"]), 200
+    x0 = lbinputs.saw_chain(N, L, p["seed"])
+    say("single64: GPU 200 steps")
+    s = lbm.LBSystem([p], precision=lbm.FP32_DEV, bead_x0=x0, hist_steps=T)
+    s.set_launch(batched=True, graph_steps=20)
+    s.step(T)
+    hg = np.stack([s.velocity_history(t) for t in range(T)])
+    og = s.observables()[0]
+    s.close()
+    say("single64: oracle 200 steps")
+    c, w, _, _ = orc.tables()
+    n0 = w[:, None, None, None] * p["rho0"] * np.ones((19, L, L, L))
+    o = orc.State(orc.make_box(**p), n0, x0)
+    ho = o.run(T, record_velocities=True)
+    oo = o.observables()
+    vmax = np.max(np.abs(ho))
+    err = np.max(np.abs(hg - ho))
+    say("single64: max |dv|", err, "of", vmax)
+    assert err < 1e-6 * max(1.0, vmax)
+
+    def vacf(h, tmax=50):
+        return np.array([np.mean(np.sum(h[: T - k] * h[k:], axis=2)) for k in range(tmax + 1)])
+
+    # near its zero crossings C(tau) is tiny, so the bar is set against C(0):
+    # velocities agree to 1e-6 of their scale, hence C to ~1e-6 of C(0)
+    cg, co = vacf(hg), vacf(ho)
+    assert np.max(np.abs(cg - co)) < 1e-6 * co[0]
+    assert og["rg2"] == pytest.approx(oo[16], rel=1e-8)
+    assert og["re2"] == pytest.approx(oo[17], rel=1e-8)
+
+
+def test_batched256_boxes_equal_single_boxes_bitwise(orc):
+    """The 256-box sweep (L in {16..64}, N in {8..64}) in one batch, graphs of
+    20 steps, autotuned collide: after 25 steps, sampled boxes (the first,
+    the last, the largest, one of each size) equal the same box run alone,
+    bit for bit; one small box of the batch also matches the oracle."""
+    import lbinputs
+    import paper_0903_5067_amd as lbm
+    table = lbinputs.batched_table(256, 1)
+    boxes = [lbinputs.box_params("batched256", L=L, N=N, box_id=i) for i, (L, N) in enumerate(table)]
+    xs = [lbinputs.saw_chain(b["N"], b["L"], b["seed"] + 7919 * b["box_id"]) for b in boxes]
+    say("batched256: batch of", len(boxes), "boxes,", sum(b["L"] ** 3 for b in boxes), "nodes")
+    sb = lbm.LBSystem(boxes, precision=lbm.FP32_DEV, bead_x0=np.concatenate(xs))
+    sb.set_launch(batched=True, graph_steps=20)
+    sb.autotune(reps=2)
+    sb.step(25)
+    assert sb.observables()[0]["health"] == 0
+    batch = sb.export_state()["boxes"]
+    sb.close()
+    pick = {0, len(boxes) - 1, int(np.argmax([b["L"] for b in boxes]))}
+    for Lv in (16, 24, 32, 48, 64):
+        pick.add(next(i for i, b in enumerate(boxes) if b["L"] == Lv))
+    for i in sorted(pick):
+        say("batched256: single box", i, boxes[i]["L"], boxes[i]["N"])
+        si = lbm.LBSystem([boxes[i]], precision=lbm.FP32_DEV, bead_x0=xs[i])
+        si.step(25)
+        single = si.export_state()["boxes"][0]
+        si.close()
+        for k in ("n", "x", "v", "f", "fc"):
+            assert np.array_equal(batch[i][k], single[k]), (i, k)
+    i16 = next(i for i, b in enumerate(boxes) if b["L"] == 16)
+    b = boxes[i16]
+    c, w, _, _ = orc.tables()
+    n0 = w[:, None, None, None] * b["rho0"] * np.ones((19, 16, 16, 16))
+    o = orc.State(orc.make_box(**b), n0, xs[i16])
+    o.run(25)
+    err = np.max(np.abs(batch[i16]["n"] - o.n) / (w[:, None, None, None] * b["rho0"]))
+    assert err < 1e-5
+    assert np.max(np.abs(batch[i16]["x"] - o.x)) < 1e-6

@@ -146,10 +146,13 @@ def test_velocity_history_and_vacf(orc):
 
 # ------------------------------------------------------------- structure
 def _boxes():
+    # chain lengths whose coupling workgroups would split the pair loop
+    # differently if the split followed the longest chain of the batch
     b0 = params(L=8, N=4, seed=5, box_id=0)
     b1 = params(L=11, N=8, seed=5, box_id=1, kT=1e-3, omega_s=1.2)
     b2 = params(L=6, N=0, seed=6, box_id=2)
-    return [b0, b1, b2]
+    b3 = params(L=10, N=40, seed=5, box_id=3)
+    return [b0, b1, b2, b3]
 
 
 def test_batched_equals_single_bitwise(orc):
