@@ -342,8 +342,12 @@ def main():
         if args.graph_steps:
             s64.set_launch(batched=True, graph_steps=args.graph_steps)
         t64, _ = time_steps(s64, 2000, 50)
+        c64 = time_collide(s64, 200)
+        o64 = s64.observables()[0]
         sec["single64"] = {"mlups": round(n64 * 2000 / t64 / 1e6, 1), "ms_per_step": round(1e3 * t64 / 2000, 4),
-                           "collide_us": round(1e6 * time_collide(s64, 200), 2)}
+                           "collide_us": round(1e6 * c64, 2),
+                           "collide_gbs": round(BYTES_PER_NODE[p64] * n64 / c64 / 1e9, 1),
+                           "rg2_after_2050_steps": round(o64["rg2"], 4), "re2_after_2050_steps": round(o64["re2"], 4)}
         s64.close()
         sb, bb, nb, pb = make_system("batched256")
         if args.graph_steps:
@@ -353,6 +357,7 @@ def main():
         tp, _ = time_steps(sb, 100, 5)
         sec["batched256"] = {"boxes": len(bb), "nodes": nb, "beads": int(sum(b["N"] for b in bb)),
                              "batched_mlups": round(nb * 500 / tb / 1e6, 1),
+                             "batched_pct_hbm_peak": round(100.0 * BYTES_PER_NODE[pb] * nb * 500 / tb / 1e9 / HBM_PEAK_GBS, 1),
                              "plain_per_box_mlups": round(nb * 100 / tp / 1e6, 1),
                              "batched_over_plain": round((nb * 500 / tb) / (nb * 100 / tp), 3)}
         sb.close()

@@ -197,11 +197,12 @@ lb_status lb_collide_only(lb_handle* h, int32_t n);
  * arithmetic, bit for bit); they differ in the cap on resident waves per SIMD
  * (4..8) and in the grid: one workgroup per 256-node tile (variants 0..4) or
  * a grid of n_CU x waves workgroups that strides over the tiles (5..9).
- * lb_autotune times every variant on the handle's own state (reps launches
- * each after two untimed ones, HIP events on the handle's stream, no state
- * change), selects the fastest, drops recorded graphs, and writes the average
- * microseconds per launch to times_us[LB_N_COLLIDE_VARIANTS] (may be NULL) and
- * the choice to *chosen (may be NULL).  lb_set_collide_variant forces one. */
+ * lb_autotune times every variant on the handle's own state (two sweeps; in
+ * each, reps launches per variant after two untimed ones, HIP events on the
+ * handle's stream, no state change), selects the fastest, drops recorded
+ * graphs, and writes each variant's faster sweep average in microseconds per
+ * launch to times_us[LB_N_COLLIDE_VARIANTS] (may be NULL) and the choice to
+ * *chosen (may be NULL).  lb_set_collide_variant forces one. */
 #define LB_N_COLLIDE_VARIANTS 10
 lb_status lb_autotune(lb_handle* h, int32_t reps, float* times_us, int32_t* chosen);
 lb_status lb_set_collide_variant(lb_handle* h, int32_t variant);

@@ -28,15 +28,22 @@ def _gpu():
         pytest.skip("no GPU")
 
 
-def test_prec256_sampled_parity(orc):
+# bars: FP32 deviation storage as in the FP32 parity tests.  FP64 storage:
+# populations to 1e-12 of w_i rho0 (round-off only); bead positions,
+# velocities and coupling forces to 1e-11; conservative forces to 1e-9, since
+# positions near the box centre (x ~ 128) carry round-off of ~1 ulp(128)
+# ~ 3e-14 and the WCA stiffness at closest approach is ~2.3e3
+@pytest.mark.parametrize("prec,pop_tol,dp_tol,bead_tol,f_tol",
+                         [(1, 1e-6, 1e-9, 1e-6, 1e-6), (0, 1e-12, 1e-13, 1e-11, 1e-9)])
+def test_prec256_sampled_parity(orc, prec, pop_tol, dp_tol, bead_tol, f_tol):
     import lbinputs
     import paper_0903_5067_amd as lbm
     p = lbinputs.box_params("prec256")
     L, N = int(p["L"]), int(p["N"])
     V = L ** 3
     x0 = lbinputs.saw_chain(N, L, p["seed"])
-    say("prec256: init + autotune")
-    s = lbm.LBSystem([p], precision=lbm.FP32_DEV, bead_x0=x0)
+    say("prec256: init + autotune, precision", prec)
+    s = lbm.LBSystem([p], precision=prec, bead_x0=x0)
     s.set_launch(batched=True, graph_steps=20)
     chosen, _ = s.autotune(reps=3)
     obs0 = s.observables()[0]
@@ -70,9 +77,9 @@ def test_prec256_sampled_parity(orc):
     o.t = t
     dp_o = o.couple()
     assert np.count_nonzero(np.any(dp_o != 0, axis=0)) == np.count_nonzero(np.any(dp_g != 0, axis=0)) > 0
-    assert np.max(np.abs(dp_g - dp_o)) < 1e-9
+    assert np.max(np.abs(dp_g - dp_o)) < dp_tol
     for k, ref in (("x", o.x), ("v", o.v), ("f", o.f), ("fc", o.fc)):
-        assert np.max(np.abs(bg[k] - ref)) < 1e-6, k
+        assert np.max(np.abs(bg[k] - ref)) < (f_tol if k == "f" else bead_tol), k
     del o
 
     say("prec256: sampled post-collision nodes")
@@ -95,7 +102,7 @@ def test_prec256_sampled_parity(orc):
             got = nB2[i, xd + L * (yd + L * zd)]
             worst = max(worst, abs(got - post[i]) / (w[i] * p["rho0"]))
     say("prec256: sampled nodes", len(sample), "impulse nodes", len(hit), "worst rel err", worst)
-    assert worst < 1e-6
+    assert worst < pop_tol
 
 
 def test_single64_first_200_steps(orc):
