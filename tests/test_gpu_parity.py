@@ -343,3 +343,64 @@ def test_big_chain_in_batch_bitwise():
         single = si.export_state()["boxes"][0]
         for k in ("n", "x", "v", "f", "fc"):
             assert np.array_equal(batch[i][k], single[k]), (i, k)
+
+
+# ------------------------------------------------ fast beads, paper parameters
+def _left_table(x_start, x_end, L):
+    """Beads whose end-of-step base cell lies outside the 3x3x3 node table
+    centred on their start-of-step nearest node (any axis)."""
+    nrst = np.floor(np.mod(x_start, L) + 0.5)
+    base = np.floor(np.mod(x_end, L))
+    return np.any(np.mod(base - nrst + 1, L) > 1, axis=1)
+
+
+@pytest.mark.parametrize("prec", [FP64, FP32])
+def test_big_chain_beads_leaving_their_node_table(orc, prec):
+    """Hot beads (kT = 1, LB step 0.25, no fluid noise, weak friction) move
+    past the 3x3x3 node table built at the start of their LB step, so the
+    chain kernel reads those stencils from the populations: 12 steps against
+    the oracle.  In the oracle a perturbation of 1e-14 in one coordinate grows
+    over these steps to ~6e-13 in positions, ~4e-12 in velocities and ~3e-14
+    in populations (~1e-12 of w_i rho0), so the FP64 bars are 1e-10 on all
+    three (about 100 x that amplification)."""
+    say("big chain, fast beads", prec)
+    p = params(L=14, N=300, kT=1.0, therm=0, md_dt=0.01, md_substeps=25, tau_lb=0.25, zeta=1.0,
+               k_fene=7.0, r0_fene=2.0, seed=3, box_id=1)
+    L = int(p["L"])
+    x0 = chain(p)
+    n0 = initial_pops(orc, p)
+    s = gpu_system([p], prec, xs=[x0])
+    o = oracle_state(orc, p, n0, x0)
+    left = 0
+    for _ in range(12):
+        xs = o.x.copy()
+        o.run(1)
+        left += int(_left_table(xs, o.x, L).sum())
+        s.step(1)
+    assert left > 0   # the case under test occurred
+    st = s.export_state()["boxes"][0]
+    assert s.observables()[0]["health"] == 0
+    assert max_rel_pop_err(st["n"], o.n, orc) < (1e-10 if prec == FP64 else 1e-5)
+    for k, ref in (("x", o.x), ("v", o.v)):
+        assert np.max(np.abs(st[k] - ref)) < (1e-10 if prec == FP64 else 1e-4), k
+
+
+@pytest.mark.parametrize("prec", [FP64, FP32])
+def test_paper_parameter_set(orc, prec):
+    """The paper's own parameters (Sec. II.E: kT = 1.2, rho = 0.864, nu = 2.8,
+    zeta = 20.8, k_FENE = 7, R0 = 2, dt = 0.01, LB step 0.02, N = 32) in a
+    15^3 box: 200 LB steps against the oracle."""
+    import lbinputs
+    say("paper parameters", prec)
+    p = lbinputs.box_params("paper")
+    x0 = chain(p)
+    n0 = initial_pops(orc, p)
+    s = gpu_system([p], prec, xs=[x0])
+    s.step(200)
+    st = s.export_state()["boxes"][0]
+    o = oracle_state(orc, p, n0, x0)
+    o.run(200)
+    assert s.observables()[0]["health"] == 0
+    assert max_rel_pop_err(st["n"], o.n, orc) < (1e-12 if prec == FP64 else 1e-5)
+    for k, ref in (("x", o.x), ("v", o.v)):
+        assert np.max(np.abs(st[k] - ref)) < (1e-10 if prec == FP64 else 1e-5), k
