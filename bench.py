@@ -139,6 +139,33 @@ def time_collide(s, n):
     return e0.elapsed_time(e1) / 1e3 / n
 
 
+def thermalization_secondary(L=64, warm=50, samples=300):
+    """Node-level mode variances <m_k^2> / (mu rho0 b_k) of a fluid-only 64^3
+    box (kT = 1e-2, rates 1.25 / 0.8 / 1.4) with noise on every non-conserved
+    mode against noise on the stress modes only (Sec. II.B): group means over
+    bulk (k=4), shear (5..9) and ghost (10..18) modes."""
+    import lbinputs
+    import paper_0903_5067_amd as lbm
+    b = np.array([1, 1 / 3, 1 / 3, 1 / 3, 2 / 3, 4 / 3, 4 / 9, 1 / 9, 1 / 9, 1 / 9,
+                  2 / 3, 2 / 3, 2 / 3, 2 / 9, 2 / 9, 2 / 9, 2, 4 / 3, 4 / 9])
+    out = {}
+    for therm, name in ((2, "all_modes"), (1, "stress_only")):
+        p = lbinputs.box_params("single64", L=L, N=0, kT=1e-2, therm=therm, omega_s=1.25, omega_b=0.8,
+                                omega_g=1.4)
+        s = lbm.LBSystem([p], precision=lbm.FP32_DEV)
+        s.step(warm)
+        acc = np.zeros(19)
+        for _ in range(samples):
+            s.step(1)
+            acc += s.observables()[0]["mode_sq"]
+        s.close()
+        r = acc / (samples * L ** 3) / (3 * p["kT"] * p["tau_lb"] ** 2 * p["rho0"] * b)
+        out[name] = {"bulk": round(float(r[4]), 4), "shear": round(float(np.mean(r[5:10])), 4),
+                     "ghost": round(float(np.mean(r[10:])), 4)}
+    out["samples"] = samples
+    return out
+
+
 def adjoint_secondary():
     """The 32^3 box with its N=32 chain: a 200-step window with checkpoints
     every 20 steps, forward (recording) and backward (hand-written adjoint)
@@ -362,6 +389,7 @@ def main():
                              "batched_over_plain": round((nb * 500 / tb) / (nb * 100 / tp), 3)}
         sb.close()
         sec["adjoint32"] = adjoint_secondary()
+        sec["thermalization"] = thermalization_secondary()
         result["secondary"] = sec
         log("secondary", json.dumps(sec))
     if not args.no_cpu:
