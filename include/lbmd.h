@@ -155,6 +155,12 @@ lb_status lb_pending_impulse(lb_handle* h, double* host_dense, size_t bytes);
  * FP64 host.  LB_EINVAL if that step is no longer in the ring. */
 lb_status lb_velocity_history(lb_handle* h, int64_t step, double* host_out, size_t bytes);
 
+/* Bead positions at the current LB-step boundary, unwrapped (a chain's
+ * coordinates are continuous across the periodic boundary, Sec. II.A),
+ * [sum N][3] FP64 host, boxes in order.  Waits for the handle's stream.
+ * LB_ESTATE between lb_couple and lb_step (the positions are mid-step). */
+lb_status lb_bead_positions(lb_handle* h, double* host_out, size_t bytes);
+
 /* Launch structure: batched = 1 advances every box with one launch per kernel
  * (the default); batched = 0 launches per box (the plain form).
  * graph_steps > 0 records that many LB steps (rounded up to even) in a HIP

@@ -78,6 +78,7 @@ def lib() -> ctypes.CDLL:
         L.lb_import_state.argtypes = [vp, vp, sz]
         L.lb_pending_impulse.argtypes = [vp, ctypes.POINTER(ctypes.c_double), sz]
         L.lb_velocity_history.argtypes = [vp, i64, ctypes.POINTER(ctypes.c_double), sz]
+        L.lb_bead_positions.argtypes = [vp, ctypes.POINTER(ctypes.c_double), sz]
         L.lb_set_launch.argtypes = [vp, i32, i32]
         L.lb_collide_only.argtypes = [vp, i32]
         L.lb_autotune.argtypes = [vp, i32, ctypes.POINTER(ctypes.c_float), ctypes.POINTER(i32)]
@@ -96,7 +97,7 @@ def lib() -> ctypes.CDLL:
         L.lb_last_error.restype = ctypes.c_char_p
         for name in ("lb_query_sizes", "lb_init", "lb_couple", "lb_step", "lb_observables",
                      "lb_export_state", "lb_import_state", "lb_pending_impulse",
-                     "lb_velocity_history", "lb_set_launch", "lb_collide_only", "lb_window_forward",
+                     "lb_velocity_history", "lb_bead_positions", "lb_set_launch", "lb_collide_only", "lb_window_forward",
                      "lb_window_backward", "lb_window_rewind", "lb_set_rates", "lb_autotune",
                      "lb_set_collide_variant"):
             getattr(L, name).restype = ctypes.c_int
@@ -256,6 +257,13 @@ class LBSystem:
         buf = np.zeros((max(self.n_beads, 1), 3))
         _check(lib().lb_velocity_history(self.h, int(step), buf.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
                                          buf.nbytes), self.h)
+        return buf[: self.n_beads]
+
+    def bead_positions(self) -> np.ndarray:
+        """Unwrapped bead positions [sum N, 3] at the current step boundary."""
+        buf = np.zeros((max(self.n_beads, 1), 3))
+        _check(lib().lb_bead_positions(self.h, buf.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), buf.nbytes),
+               self.h)
         return buf[: self.n_beads]
 
     # -- adjoint window ---------------------------------------------------

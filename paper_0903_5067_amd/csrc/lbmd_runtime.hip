@@ -765,6 +765,17 @@ lb_status lb_velocity_history(lb_handle* h, int64_t step, double* host_out, size
     return LB_OK;
 }
 
+lb_status lb_bead_positions(lb_handle* h, double* host_out, size_t bytes)
+{
+    if (!h || !host_out) return fail(h, LB_EINVAL, "null argument");
+    const uint64_t nb = h->lo.total_beads;
+    if (bytes < nb * 3 * sizeof(double)) return fail(h, LB_ENOMEM, "host buffer too small");
+    if (h->pending) return fail(h, LB_ESTATE, "impulses pending from lb_couple");
+    HIPCHK(h, hipStreamSynchronize(h->stream));
+    if (nb) HIPCHK(h, hipMemcpy(host_out, h->state + h->lo.st_x, nb * 3 * sizeof(double), hipMemcpyDeviceToHost));
+    return LB_OK;
+}
+
 lb_status lb_set_launch(lb_handle* h, int32_t batched, int32_t graph_steps)
 {
     if (!h) return fail(nullptr, LB_EINVAL, "null handle");

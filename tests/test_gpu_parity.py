@@ -440,3 +440,34 @@ def test_thermalization_full_vs_stress_only_on_gpu():
     np.testing.assert_allclose(full[4:], 1.0, atol=0.015)
     assert np.all(stress[4:10] < 0.8)
     assert np.all(stress[10:] < 0.8)
+
+
+def test_bead_positions_and_chain_observables():
+    """lb_bead_positions returns the exported positions bit for bit, and the
+    chain observables the GPU sums in FP64 (centre of mass, R_g^2 in the
+    pair form, R_e^2) equal the host analysis of those positions."""
+    import paper_0903_5067_amd as lbm
+    from paper_0903_5067_amd import analysis as an
+    say("bead positions")
+    boxes = _boxes()
+    xs = [chain(b) for b in boxes]
+    s = gpu_system(boxes, FP32, xs=xs)
+    s.step(17)
+    pos = s.bead_positions()
+    st = s.export_state()["boxes"]
+    obs = s.observables()
+    o = 0
+    for b, bst, ob in zip(boxes, st, obs):
+        n = int(b["N"])
+        if n == 0:
+            continue
+        x = pos[o:o + n]
+        o += n
+        assert np.array_equal(x, bst["x"])
+        np.testing.assert_allclose(ob["com"], x.mean(axis=0), rtol=1e-13, atol=1e-13)
+        assert ob["rg2"] == pytest.approx(float(an.rg2(x)), rel=1e-12)
+        assert ob["re2"] == pytest.approx(float(an.re2(x)), rel=1e-12)
+    s.couple()
+    with pytest.raises(lbm.LBError):
+        s.bead_positions()
+    s.step(1)
