@@ -1,7 +1,8 @@
 // HIP kernels of the fluctuating D3Q19 LB step with a dissipatively coupled
 // bead-spring chain, for gfx950 (MI355X).
 //
-//   k_couple      one workgroup per chain (T lanes per bead): velocity-Verlet
+//   k_couple      chains of up to 256 beads, one workgroup per chain (T lanes
+//                 per bead, T a function of N only): velocity-Verlet
 //                 substeps in the fluid velocity field frozen at the
 //                 pre-collision state, trilinear interpolation, friction +
 //                 Langevin force, and the impulse handed back to the stencil
@@ -15,6 +16,11 @@
 //                 the pre-collision population of node r is n_i(r) =
 //                 p_i(r - c_i); reads are gathered, writes aligned and
 //                 non-temporal.
+//   k_near_nodes, k_chain_wg, k_spread
+//                 the same coupling stage for chains of 257..1024 beads: node
+//                 velocities around each bead, all substeps in one
+//                 1024-thread workgroup writing per-substep records, and the
+//                 records turned into node impulses
 //   k_fixup       re-collides the nodes the beads touched, with their
 //                 impulse, and overwrites their outputs
 //   k_stats*      FP64 conserved sums, mode variances, negative-population
@@ -287,8 +293,7 @@ __global__ __launch_bounds__(MAXT) void k_couple(const BoxDev* __restrict__ boxe
                                                  const R* __restrict__ A, ChainArgs ca,
                                                  Ctrl* __restrict__ ctrl, uint32_t s_off)
 {
-    __shared__ double xs[3 * MAXB];
-    __shared__ uint16_t nls[1];   // neighbour lists are used on the multi-workgroup path only
+    __shared__ double xs[3 * BIG_CHAIN];   // chains on this path have at most BIG_CHAIN beads
     __builtin_amdgcn_s_setprio(3);   // latency-bound chain beside the bandwidth-bound collide
     const int bi = couple_list[blockIdx.x];
     const BoxDev& bx = boxes[bi];
@@ -307,25 +312,12 @@ __global__ __launch_bounds__(MAXT) void k_couple(const BoxDev* __restrict__ boxe
     const double inv_tau = 1.0 / bx.tau_lb;
     const double eps24 = 24.0 * bx.eps;
     const R* a = A + bx.pop_off;
-    const bool use_nl = false;   // chains on this path have at most 256 beads
-    const double rl = sqrt(bx.rc2) + NL_SKIN;
-    const double rl2 = rl * rl;
-    const int nl_cap = ca.nl_cap;
 
     double x[3] = {0, 0, 0}, v[3] = {0, 0, 0}, f[3] = {0, 0, 0}, fcl[3] = {0, 0, 0};
-    double x0n[3] = {0, 0, 0};    // positions at the last neighbour-list build
-    int nl_n = -2;
     if (act) {
 #pragma unroll
         for (int c = 0; c < 3; ++c) { x[c] = ca.x[3 * g + c]; v[c] = ca.v[3 * g + c]; f[c] = ca.f[3 * g + c]; }
-        if (use_nl) {
-            nl_n = ca.nl_cnt[g];
-#pragma unroll
-            for (int c = 0; c < 3; ++c) x0n[c] = ca.nl_x0[3 * g + c];
-            for (int k = 0; k < (nl_n > 0 ? nl_n : 0); ++k) nls[k * MAXB + b] = ca.nl_idx[g * nl_cap + k];
-        }
     }
-    int rebuilds = 0;
     int cb[3] = {-1, -1, -1};     // base cell of the cached stencil
     // node velocities of the cached stencil (MD units), kept in the storage
     // precision: FP32 storage carries no more digits than that
@@ -345,43 +337,12 @@ __global__ __launch_bounds__(MAXT) void k_couple(const BoxDev* __restrict__ boxe
             }
             if (lane == 0) { xs[3 * b] = x[0]; xs[3 * b + 1] = x[1]; xs[3 * b + 2] = x[2]; }
         }
-        bool rebuild = false;
-        if (use_nl) {   // uniform over the block: the barrier is taken by all threads or none
-            if (act) {
-                const double dx0 = x[0] - x0n[0], dy0 = x[1] - x0n[1], dz0 = x[2] - x0n[2];
-                rebuild = nl_n == -2 || dx0 * dx0 + dy0 * dy0 + dz0 * dz0 > 0.25 * NL_SKIN * NL_SKIN;
-            }
-            rebuild = __syncthreads_or(rebuild);
-        } else {
-            __syncthreads();
-        }
-        if (use_nl && rebuild && act) {
-            ++rebuilds;
-            int cnt = 0;
-            for (int j = 0; j < N; ++j) {
-                if (j == b) continue;
-                double d0 = x[0] - xs[3 * j], d1 = x[1] - xs[3 * j + 1], d2 = x[2] - xs[3 * j + 2];
-                d0 -= Ld * rint(d0 * iL); d1 -= Ld * rint(d1 * iL); d2 -= Ld * rint(d2 * iL);
-                if (d0 * d0 + d1 * d1 + d2 * d2 < rl2) {
-                    if (cnt < nl_cap) { nls[cnt * MAXB + b] = (uint16_t)j; ca.nl_idx[g * nl_cap + cnt] = (uint16_t)j; }
-                    ++cnt;
-                }
-            }
-            nl_n = cnt > nl_cap ? -1 : cnt;   // -1: overflow, use the full loop
-            ca.nl_cnt[g] = nl_n;
-#pragma unroll
-            for (int c = 0; c < 3; ++c) { ca.nl_x0[3 * g + c] = x[c]; x0n[c] = x[c]; }
-        }
+        __syncthreads();
         if (act) {
-            // repulsive LJ, this lane's share of the partners
+            // repulsive LJ over all partners (at most 256), this lane's share
             double W[3] = {0, 0, 0};
-            if (use_nl && nl_n >= 0) {
-                auto jof = [&](int k) { return (int)nls[k * MAXB + b]; };
-                for (int k = 0; k < nl_n; k += 4) wca_add4(x, xs, jof, k, nl_n, 1, b, Ld, iL, bx.rc2, bx.sigsq, eps24, W);
-            } else {
-                auto jof = [](int k) { return k; };
-                for (int j = lane; j < N; j += 4 * T) wca_add4(x, xs, jof, j, N, T, b, Ld, iL, bx.rc2, bx.sigsq, eps24, W);
-            }
+            auto jof = [](int k) { return k; };
+            for (int j = lane; j < N; j += 4 * T) wca_add4(x, xs, jof, j, N, T, b, Ld, iL, bx.rc2, bx.sigsq, eps24, W);
             for (int o = 1; o < T; o <<= 1) {
 #pragma unroll
                 for (int c = 0; c < 3; ++c) W[c] += __shfl_xor(W[c], o, T);
@@ -466,7 +427,6 @@ __global__ __launch_bounds__(MAXT) void k_couple(const BoxDev* __restrict__ boxe
         }
     }
     if (act && hbits) atomicOr(&ctrl->health, hbits);
-    if (b == 0 && lane == 0 && rebuilds) atomicAdd(&ca.nl_rebuilds[bi], (uint32_t)rebuilds);
 }
 
 // ------------------------------------------------- couple, large chains
