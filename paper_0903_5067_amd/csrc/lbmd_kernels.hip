@@ -1225,6 +1225,12 @@ __device__ __forceinline__ void pair_kernel(const double d[3], double g, double 
     out[2] += g * v[2] + dv * d[2];
 }
 
+// Reverse sweep of one LB step's substeps for chains of at most 256 beads.
+// Thread layout as in the forward kernel: T lanes per bead (T a function of
+// N only), bead b = tid / T.  All lanes of a bead carry identical copies of
+// the bead's adjoint; the pair loop of the force Hessian is split over the
+// lanes (partners j = lane mod T) and combined by a butterfly, which gives
+// every lane the same bits; lane 0 writes and performs the atomics.
 template <typename R>
 __global__ __launch_bounds__(256) void k_adj_couple(const BoxDev* __restrict__ boxes,
                                                     const int32_t* __restrict__ couple_list, const R* __restrict__ P,
@@ -1233,8 +1239,11 @@ __global__ __launch_bounds__(256) void k_adj_couple(const BoxDev* __restrict__ b
     __shared__ double xs[3 * 256], lF[3 * 256], red[256];
     const int bi = couple_list[blockIdx.x];
     const BoxDev& bx = boxes[bi];
-    const int N = bx.N, b = threadIdx.x, S = bx.substeps, L = bx.L;
+    const int N = bx.N, S = bx.substeps, L = bx.L;
+    const int T = bx.couple_T;
+    const int b = (int)threadIdx.x / T, lane = (int)threadIdx.x % T;
     const bool act = b < N;
+    const bool writer = act && lane == 0;
     const uint64_t g = bx.bead_off + (uint64_t)(act ? b : 0);
     const double dt = bx.dt, h = 0.5 * dt / bx.mass, tau = bx.tau_lb, Ld = (double)L, iL = bx.inv_L;
     const double eps24 = 24.0 * bx.eps, s6c = bx.sigsq * bx.sigsq * bx.sigsq, s12c = s6c * s6c;
@@ -1273,32 +1282,46 @@ __global__ __launch_bounds__(256) void k_adj_couple(const BoxDev* __restrict__ b
             for (int c = 0; c < 3; ++c) {
                 x1[c] = tp[c]; v1[c] = tp[3 + c]; fc[c] = tp[6 + c]; i0[c] = (int)tp[9 + c]; fr[c] = tp[12 + c];
             }
-        if (act) { xs[3 * b] = x1[0]; xs[3 * b + 1] = x1[1]; xs[3 * b + 2] = x1[2]; }
         // v' = v1 + f' h and f' = F_c + fc
         double lft[3], lv1[3], lfc[3];
 #pragma unroll
         for (int c = 0; c < 3; ++c) { lft[c] = lf[c] + h * lv[c]; lv1[c] = lv[c]; lfc[c] = lft[c]; }
-        if (act) { lF[3 * b] = lft[0]; lF[3 * b + 1] = lft[1]; lF[3 * b + 2] = lft[2]; }
+        if (writer) {
+            xs[3 * b] = x1[0]; xs[3 * b + 1] = x1[1]; xs[3 * b + 2] = x1[2];
+            lF[3 * b] = lft[0]; lF[3 * b + 1] = lft[1]; lF[3 * b + 2] = lft[2];
+        }
         __syncthreads();
         double lx1[3] = {lx[0], lx[1], lx[2]};
         if (act) {
             // stencil of this substep
             if (i0[0] != cb[0] || i0[1] != cb[1] || i0[2] != cb[2]) {
-                if (have) flush();
+                if (have && lane == 0) flush();
+                // the densities of the 8 nodes: all population loads of a
+                // batch are issued before any is summed
+                constexpr int NB = sizeof(R) == 4 ? 8 : 4;
 #pragma unroll
-                for (int k = 0; k < 8; ++k) {
-                    const int ix = i0[0] + (k & 1), iy = i0[1] + ((k >> 1) & 1), iz = i0[2] + ((k >> 2) & 1);
-                    const uint32_t nx = ix >= L ? ix - L : ix, ny = iy >= L ? iy - L : iy, nz = iz >= L ? iz - L : iz;
-                    cnode[k] = nx + (uint32_t)L * (ny + (uint32_t)L * nz);
-                    const Upwind up(nx, ny, nz, (uint32_t)L);
-                    R dn[19];
-                    gather_pre<R, false>(pb, bx.ps, up, dn);
-                    double rho = 0.0;
-                    for (int i = 0; i < 19; ++i) rho += (double)dn[i];
-                    rho_k[k] = rho + bx.rho0;
+                for (int k0 = 0; k0 < 8; k0 += NB) {
+                    R dn[NB][19];
+#pragma unroll
+                    for (int kk = 0; kk < NB; ++kk) {
+                        const int k = k0 + kk;
+                        const int ix = i0[0] + (k & 1), iy = i0[1] + ((k >> 1) & 1), iz = i0[2] + ((k >> 2) & 1);
+                        const uint32_t nx = ix >= L ? ix - L : ix, ny = iy >= L ? iy - L : iy, nz = iz >= L ? iz - L : iz;
+                        cnode[k] = nx + (uint32_t)L * (ny + (uint32_t)L * nz);
+                        const Upwind up(nx, ny, nz, (uint32_t)L);
+                        gather_pre<R, false>(pb, bx.ps, up, dn[kk]);
+                    }
+#pragma unroll
+                    for (int kk = 0; kk < NB; ++kk) {
+                        double rho = 0.0;
+                        for (int i = 0; i < 19; ++i) rho += (double)dn[kk][i];
+                        rho_k[k0 + kk] = rho + bx.rho0;
+                    }
+                }
+#pragma unroll
+                for (int k = 0; k < 8; ++k)
 #pragma unroll
                     for (int c = 0; c < 3; ++c) { cuk[k][c] = tp[15 + 3 * k + c]; lcu[k][c] = 0.0; }
-                }
                 cb[0] = i0[0]; cb[1] = i0[1]; cb[2] = i0[2];
                 have = true;
             }
@@ -1345,8 +1368,10 @@ __global__ __launch_bounds__(256) void k_adj_couple(const BoxDev* __restrict__ b
                 lx1[1] += lw[k] * (((k >> 1) & 1) ? 1.0 : -1.0) * g0 * g2;
                 lx1[2] += lw[k] * (((k >> 2) & 1) ? 1.0 : -1.0) * g0 * g1;
             }
-            // conservative forces at x1: lam_x1_b += sum_j K_bj (lam_F_b - lam_F_j)
-            for (int j = 0; j < N; ++j) {
+            // conservative forces at x1: lam_x1_b += sum_j K_bj (lam_F_b - lam_F_j),
+            // this lane's share of the partners, summed over the lanes
+            double lp[3] = {0, 0, 0};
+            for (int j = lane; j < N; j += T) {
                 if (j == b) continue;
                 const double dl[3] = {lft[0] - lF[3 * j], lft[1] - lF[3 * j + 1], lft[2] - lF[3 * j + 2]};
                 if (j == b - 1 || j == b + 1) {
@@ -1355,7 +1380,7 @@ __global__ __launch_bounds__(256) void k_adj_couple(const BoxDev* __restrict__ b
                     const double den = 1.0 - r2 * bx.inv_r0sq;
                     const double gfe = -bx.k_fene / den;
                     const double gpe = -bx.k_fene * bx.inv_r0sq / (den * den);
-                    pair_kernel(d, gfe, gpe, dl, lx1);
+                    pair_kernel(d, gfe, gpe, dl, lp);
                 }
                 double d[3] = {x1[0] - xs[3 * j], x1[1] - xs[3 * j + 1], x1[2] - xs[3 * j + 2]};
                 d[0] -= Ld * rint(d[0] * iL); d[1] -= Ld * rint(d[1] * iL); d[2] -= Ld * rint(d[2] * iL);
@@ -1364,9 +1389,14 @@ __global__ __launch_bounds__(256) void k_adj_couple(const BoxDev* __restrict__ b
                     const double iq = 1.0 / q, iq4 = iq * iq * iq * iq, iq7 = iq4 * iq * iq * iq;
                     const double gw = eps24 * (2.0 * s12c * iq7 - s6c * iq4);
                     const double gpw = eps24 * (-14.0 * s12c * iq7 * iq + 4.0 * s6c * iq4 * iq);
-                    pair_kernel(d, gw, gpw, dl, lx1);
+                    pair_kernel(d, gw, gpw, dl, lp);
                 }
             }
+            for (int o = 1; o < T; o <<= 1) {
+#pragma unroll
+                for (int c = 0; c < 3; ++c) lp[c] += __shfl_xor(lp[c], o, T);
+            }
+            lx1[0] += lp[0]; lx1[1] += lp[1]; lx1[2] += lp[2];
         }
         // x1 = x + v1 dt,  v1 = v + f h
 #pragma unroll
@@ -1378,15 +1408,19 @@ __global__ __launch_bounds__(256) void k_adj_couple(const BoxDev* __restrict__ b
         }
         __syncthreads();
     }
-    if (act) {
+    if (writer) {
         if (have) flush();
 #pragma unroll
         for (int c = 0; c < 3; ++c) { aa.lx[3 * g + c] = lx[c]; aa.lv[3 * g + c] = lv[c]; aa.lf[3 * g + c] = lf[c]; }
     }
-    red[threadIdx.x] = act ? gz : 0.0;
+    // dJ/dzeta of the box: one copy per bead, summed over a zero-padded array
+    // (the block may hold fewer than 256 threads)
+    for (int i = (int)threadIdx.x; i < 256; i += (int)blockDim.x) red[i] = 0.0;
+    __syncthreads();
+    if (writer) red[threadIdx.x] = gz;
     __syncthreads();
     for (int wdt = 128; wdt > 0; wdt >>= 1) {
-        if ((int)threadIdx.x < wdt) red[threadIdx.x] += red[threadIdx.x + wdt];
+        for (int i = (int)threadIdx.x; i < wdt; i += (int)blockDim.x) red[i] += red[i + wdt];
         __syncthreads();
     }
     if (threadIdx.x == 0) aa.gz[bi] += red[0];
@@ -1404,13 +1438,15 @@ hipError_t launch_adj_collide(const LaunchCtx& c, const void* ccd, const void* P
 }
 
 template <typename R>
-hipError_t launch_adj_couple(const LaunchCtx& c, const int32_t* list, int n_list, const void* P,
+hipError_t launch_adj_couple(const LaunchCtx& c, const int32_t* list, int n_list, int block, const void* P,
                              const AdjArgsHost& a, uint32_t step)
 {
     if (n_list == 0) return hipSuccess;
+    if (block < 64 || block > 256) return hipErrorInvalidValue;
     AdjChainArgs aa{a.x0, a.v0, a.f0, a.tape, a.dj, a.lx, a.lv, a.lf, a.lam_n, a.lam_dp, a.gz, a.nodes,
                     c.total_beads};
-    hipLaunchKernelGGL(k_adj_couple<R>, dim3(n_list), dim3(256), 0, c.stream, c.boxes, list, (const R*)P, aa, step);
+    hipLaunchKernelGGL(k_adj_couple<R>, dim3(n_list), dim3(block), 0, c.stream, c.boxes, list, (const R*)P, aa,
+                       step);
     return hipGetLastError();
 }
 
@@ -1418,10 +1454,10 @@ template hipError_t launch_adj_collide<float>(const LaunchCtx&, const void*, con
                                               const double*, double*, double*, double*, uint64_t, uint32_t, uint32_t);
 template hipError_t launch_adj_collide<double>(const LaunchCtx&, const void*, const void*, const unsigned long long*,
                                                const double*, double*, double*, double*, uint64_t, uint32_t, uint32_t);
-template hipError_t launch_adj_couple<float>(const LaunchCtx&, const int32_t*, int, const void*, const AdjArgsHost&,
-                                             uint32_t);
-template hipError_t launch_adj_couple<double>(const LaunchCtx&, const int32_t*, int, const void*, const AdjArgsHost&,
-                                              uint32_t);
+template hipError_t launch_adj_couple<float>(const LaunchCtx&, const int32_t*, int, int, const void*,
+                                             const AdjArgsHost&, uint32_t);
+template hipError_t launch_adj_couple<double>(const LaunchCtx&, const int32_t*, int, int, const void*,
+                                              const AdjArgsHost&, uint32_t);
 
 template hipError_t launch_collide<float>(const LaunchCtx&, const void*, void*, int, uint32_t, uint32_t, uint32_t);
 template hipError_t launch_collide<double>(const LaunchCtx&, const void*, void*, int, uint32_t, uint32_t, uint32_t);

@@ -72,7 +72,7 @@ hipError_t launch_adj_collide(const LaunchCtx& c, const void* ccd, const void* P
                               const double* lam_next, double* lam_cur, double* lam_dp, double* gpart,
                               uint64_t nodes, uint32_t total_tiles, uint32_t step);
 template <typename R>
-hipError_t launch_adj_couple(const LaunchCtx& c, const int32_t* list, int n_list, const void* P,
+hipError_t launch_adj_couple(const LaunchCtx& c, const int32_t* list, int n_list, int block, const void* P,
                              const AdjArgsHost& a, uint32_t step);
 
 constexpr int N_COLLIDE_VARIANTS = 10;

@@ -1045,8 +1045,8 @@ lb_status lb_window_backward(lb_handle* h, void* d_ws, size_t bytes, const doubl
             a.gz = (double*)(ws + w.gz);
             a.nodes = nodes;
             const int nc = (int)h->couple_host.size();
-            HIPCHK(h, f64 ? launch_adj_couple<double>(h->ctx, h->couple_list, nc, P, a, stepv)
-                          : launch_adj_couple<float>(h->ctx, h->couple_list, nc, P, a, stepv));
+            HIPCHK(h, f64 ? launch_adj_couple<double>(h->ctx, h->couple_list, nc, lo.couple_block, P, a, stepv)
+                          : launch_adj_couple<float>(h->ctx, h->couple_list, nc, lo.couple_block, P, a, stepv));
             std::swap(lam_next, lam_cur);
         }
     }
