@@ -17,8 +17,12 @@ Parity status per function (what pins it is listed in the test files):
   collide_stream       pinned (brute force, equilibrium, conservation,
                                equipartition, shear and sound damping)
   couple               pinned (force = -grad V, exact linear interpolation,
-                               momentum invariant, bead equipartition)
-  observables          pinned (closed forms on hand-made states)
+                               momentum invariant, bead equipartition; several
+                               chains per box: -grad V with bonds along each
+                               chain only, far-apart chains move bit for bit
+                               as they do alone)
+  observables          pinned (closed forms on hand-made states, one chain
+                               and several rods)
   window_tangent       pinned (central finite differences of the oracle's own
                                window; values identical to run())
   specific noise realisations / long trajectories: parity unpinned beyond the
@@ -67,6 +71,7 @@ class Box(ctypes.Structure):
         ("k_fene", ctypes.c_double), ("r0_fene", ctypes.c_double),
         ("eps_wca", ctypes.c_double), ("sigma_wca", ctypes.c_double),
         ("seed", ctypes.c_uint32), ("box_id", ctypes.c_uint32),
+        ("chain_len", ctypes.c_int32),
     ]
 
 
@@ -107,7 +112,7 @@ def _p(a: np.ndarray | None):
 def make_box(**kw) -> Box:
     b = Box()
     for name, _ in Box._fields_:
-        setattr(b, name, kw[name])
+        setattr(b, name, kw.get(name, 0) if name == "chain_len" else kw[name])
     return b
 
 

@@ -18,6 +18,7 @@
  *     handed back to the surrounding fluid:             Sec. II.B, coupling paragraph
  *   - FENE and LJ (cut at 2^(1/6) sigma) potentials:    Sec. II.A, potentials
  *   - R_g^2 and R_e^2:                                  Sec. III.A, first equations
+ *   - several chains in one box (semidilute solution):  Sec. III.C, Efficiency
  * Where the paper is silent (mode basis, noise law, forcing scheme, stencil
  * convention, MD integrator, units) the reading used is the one listed in the
  * design notes of this repository; each such place is marked "reading:" below.
@@ -98,6 +99,8 @@ typedef struct {
     int32_t md_substeps;
     double mass, zeta, k_fene, r0_fene, eps_wca, sigma_wca;
     uint32_t seed, box_id;
+    int32_t chain_len; /* beads per chain; the N beads form N / chain_len chains of
+                          consecutive indices; 0 = a single chain of N */
 } orc_box;
 
 extern "C" {
@@ -359,19 +362,25 @@ void orc_collide_one(const orc_box* p, const double* n, const double* dp, uint32
 }
 
 /* ------------------------------------------------------------ chain / MD --- */
-/* force on bead b from bead j: FENE if bonded (unwrapped separation), then the
- * purely repulsive LJ with minimum image; Sec. II.A.  Beads j are visited in
- * ascending order and the sum is taken in that order. */
+/* beads per chain: a box holds N / chain_len chains (the semidilute solution
+ * of M chains that Sec. III.C, Efficiency, discusses), a single chain otherwise */
+static int chain_length(const orc_box* p) { return p->chain_len > 0 ? p->chain_len : p->N; }
+
+/* force on bead b from bead j: FENE if bonded, i.e. neighbours along the same
+ * chain (unwrapped separation), then the purely repulsive LJ with minimum
+ * image between every pair; Sec. II.A.  Beads j are visited in ascending order
+ * and the sum is taken in that order. */
 template <class T>
 static void conservative_force(const orc_box* p, const T* x, int b, T F[3])
 {
     const double L = p->L;
     const double rc2 = pow(2.0, 1.0 / 3.0) * p->sigma_wca * p->sigma_wca;
+    const int n = chain_length(p);
     F[0] = F[1] = F[2] = 0.0;
     for (int j = 0; j < p->N; j++) {
         if (j == b) continue;
         T d[3];
-        if (j == b - 1 || j == b + 1) {
+        if ((j == b - 1 || j == b + 1) && j / n == b / n) {
             for (int a = 0; a < 3; a++) d[a] = x[3 * b + a] - x[3 * j + a];
             T r2 = d[0] * d[0] + d[1] * d[1] + d[2] * d[2];
             /* -dV/dr along d for V = -(k R0^2/2) ln(1 - r^2/R0^2) */
@@ -538,7 +547,8 @@ void orc_window_tangent(const orc_box* p, double* n, double* x, double* v, doubl
 /* Observables, FP64, fixed summation order.  Layout of out[]:
  *  0 mass, 1-3 fluid momentum (lattice), 4-6 fluid momentum (MD),
  *  7-9 bead momentum, 10-12 conserved total (fluid + beads + dt/2 sum fc),
- *  13-15 chain centre of mass, 16 R_g^2, 17 R_e^2, 18 count of n_i < 0,
+ *  13-15 centre of mass of all beads, 16 R_g^2 and 17 R_e^2 (each the mean over
+ *  the box's chains), 18 count of n_i < 0,
  *  19-37 sum over nodes of (m_k - rho0 delta_k0)^2, k = 0..18. */
 void orc_observables(const orc_box* p, const double* n, const double* x, const double* v,
                      const double* fc, double* out)
@@ -574,21 +584,29 @@ void orc_observables(const orc_box* p, const double* n, const double* x, const d
         for (int b = 0; b < N; b++)
             for (int a = 0; a < 3; a++) out[13 + a] += x[3 * b + a];
         for (int a = 0; a < 3; a++) out[13 + a] /= N;
-        /* R_g^2 = (1 / 2N^2) sum_ij r_ij^2 (pair form, Sec. III.A) */
-        double s = 0.0;
-        for (int i = 0; i < N; i++)
-            for (int j = 0; j < N; j++)
-                for (int a = 0; a < 3; a++) {
-                    double d = x[3 * i + a] - x[3 * j + a];
-                    s += d * d;
-                }
-        out[16] = s / (2.0 * N * (double)N);
-        double e2 = 0.0;
-        for (int a = 0; a < 3; a++) {
-            double d = x[3 * (N - 1) + a] - x[a];
-            e2 += d * d;
+        /* per chain, averaged over the chains of the box:
+         * R_g^2 = (1 / 2n^2) sum_ij r_ij^2 (pair form, Sec. III.A) and
+         * R_e^2 = (r_n - r_1)^2 */
+        const int n = chain_length(p), M = N / n;
+        for (int c = 0; c < M; c++) {
+            const double* xc = x + 3 * (size_t)c * n;
+            double s = 0.0;
+            for (int i = 0; i < n; i++)
+                for (int j = 0; j < n; j++)
+                    for (int a = 0; a < 3; a++) {
+                        double d = xc[3 * i + a] - xc[3 * j + a];
+                        s += d * d;
+                    }
+            out[16] += s / (2.0 * n * (double)n);
+            double e2 = 0.0;
+            for (int a = 0; a < 3; a++) {
+                double d = xc[3 * (n - 1) + a] - xc[a];
+                e2 += d * d;
+            }
+            out[17] += e2;
         }
-        out[17] = e2;
+        out[16] /= M;
+        out[17] /= M;
     }
 }
 

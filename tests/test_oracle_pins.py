@@ -320,11 +320,14 @@ def test_stress_only_thermalization_is_poor_at_short_scales(orc):
 
 # -------------------------------------------------------------- chain / MD --
 def _fene_wca_energy(p, x):
-    """Total potential of Sec. II.A (FENE on bonds, LJ cut and shifted at 2^(1/6) sigma
-    between all pairs, minimum image)."""
+    """Total potential of Sec. II.A (FENE on the bonds along each chain, LJ cut
+    and shifted at 2^(1/6) sigma between all pairs, minimum image)."""
     N, L = len(x), p["L"]
+    n = p.get("chain_len", 0) or N
     U = 0.0
     for i in range(N - 1):
+        if (i + 1) % n == 0:      # last bead of a chain: no bond to the next chain
+            continue
         r2 = np.sum((x[i + 1] - x[i]) ** 2)
         U += -0.5 * p["k_fene"] * p["r0_fene"] ** 2 * np.log(1 - r2 / p["r0_fene"] ** 2)
     for i in range(N):
@@ -353,6 +356,66 @@ def test_forces_are_minus_gradient(orc):
             xm[bead, a] -= h
             g = (_fene_wca_energy(p, xp) - _fene_wca_energy(p, xm)) / (2 * h)
             assert F[bead, a] == pytest.approx(-g, rel=1e-6, abs=1e-6)
+
+
+def test_several_chains_forces_are_minus_gradient(orc):
+    """Three chains of three beads (Sec. III.C's semidilute solution): bonds
+    only along each chain, LJ between all beads.  The end of each chain sits
+    inside the LJ range of the next chain's start, so both a bond wrongly
+    carried across chains and a missing inter-chain LJ term change the force."""
+    bx, p = mkbox(orc, L=8, N=9, chain_len=3)
+    x = np.array([[2.0, 2.0, 2.0], [2.97, 2.0, 2.0], [3.5, 2.8, 2.1],
+                  [4.0, 3.7, 2.0], [4.9, 4.0, 2.2], [5.2, 4.9, 2.6],
+                  [6.1, 5.3, 2.9], [6.6, 6.1, 3.0], [7.5, 6.4, 3.3]])
+    r_end_start = [np.linalg.norm(x[3 * c + 2] - x[3 * c + 3]) for c in range(2)]
+    assert max(r_end_start) < 2 ** (1 / 6) and min(r_end_start) > 0.8
+    F = orc.initial_forces(bx, x)
+    h = 1e-6
+    for bead in range(9):
+        for a in range(3):
+            xp, xm = x.copy(), x.copy()
+            xp[bead, a] += h
+            xm[bead, a] -= h
+            g = (_fene_wca_energy(p, xp) - _fene_wca_energy(p, xm)) / (2 * h)
+            assert F[bead, a] == pytest.approx(-g, rel=1e-6, abs=1e-6)
+    # chain_len = N is the single chain of the default
+    b1, _ = mkbox(orc, L=8, N=9, chain_len=9)
+    b0, _ = mkbox(orc, L=8, N=9, chain_len=0)
+    assert np.array_equal(orc.initial_forces(b1, x), orc.initial_forces(b0, x))
+
+
+def test_separated_chains_move_as_single_chains(orc):
+    """Without friction and noise (zeta = 0, kT = 0) chains further apart than
+    the LJ range do not see each other or the fluid: each follows the
+    trajectory it has alone in the box, bit for bit (the LJ terms of the other
+    chains are zero and skipped)."""
+    L, n, M = 16, 5, 3
+    ang = np.deg2rad(70.0)
+    one = np.array([[0.0, 0, 0], [0.97, 0, 0], [0.97 + 0.9 * np.cos(ang), 0.9 * np.sin(ang), 0.2],
+                    [0.5, 1.5, 0.1], [-0.3, 1.2, -0.4]])
+    offs = [np.array([3.0, 4.0, 8.0]), np.array([8.0, 9.0, 8.0]), np.array([13.0, 3.0, 2.0])]
+    x = np.concatenate([one + o for o in offs])
+    kw = dict(L=L, kT=0.0, zeta=0.0, k_fene=7.0, r0_fene=2.0)
+    bx, p = mkbox(orc, N=n * M, chain_len=n, **kw)
+    n0 = np.ones((19, L, L, L)) * orc.tables()[1][:, None, None, None]
+    st = orc.State(bx, n0, x)
+    st.run(20)
+    moved = 0.0
+    for c in range(M):
+        b1, _ = mkbox(orc, N=n, **kw)
+        one_st = orc.State(b1, n0, x[c * n:(c + 1) * n])
+        one_st.run(20)
+        assert np.array_equal(st.x[c * n:(c + 1) * n], one_st.x)
+        assert np.array_equal(st.v[c * n:(c + 1) * n], one_st.v)
+        moved = max(moved, float(np.max(np.abs(one_st.x - x[c * n:(c + 1) * n]))))
+    assert moved > 1e-3
+    # and the chains stayed out of each other's LJ range
+    d = st.x[:, None] - st.x[None]
+    d -= L * np.round(d / L)
+    r = np.sqrt(np.sum(d * d, -1))
+    for c in range(M):
+        r[c * n:(c + 1) * n, c * n:(c + 1) * n] = 99.0
+    assert r.min() > 2 ** (1 / 6)
 
 
 def test_wca_vanishes_at_cutoff_and_min_image(orc):
@@ -415,6 +478,26 @@ def test_chain_observables_closed_forms(orc):
     assert o[17] == pytest.approx(np.sum((x[-1] - x[0]) ** 2), rel=1e-14)
 
 
+def test_several_chains_observables_closed_forms(orc):
+    """M straight rods of n beads with spacings a_c: R_g^2 = a_c^2 (n^2 - 1) / 12
+    and R_e^2 = a_c^2 (n - 1)^2 per rod; the box reports their means over the
+    chains, and the centre of mass of all beads."""
+    n, M = 6, 4
+    a = np.array([0.9, 1.0, 0.75, 1.2])
+    rods = []
+    for c in range(M):
+        r = np.zeros((n, 3))
+        r[:, c % 3] = a[c] * np.arange(n)
+        rods.append(r + [1.0 + c, 2.0 * c, 0.5])
+    x = np.concatenate(rods)
+    bx, p = mkbox(orc, L=12, N=n * M, chain_len=n)
+    st = orc.State(bx, np.ones((19, 12, 12, 12)) / 19, x)
+    o = st.observables()
+    assert o[16] == pytest.approx(np.mean(a ** 2) * (n * n - 1) / 12, rel=1e-13)
+    assert o[17] == pytest.approx(np.mean(a ** 2) * (n - 1) ** 2, rel=1e-13)
+    np.testing.assert_allclose(o[13:16], x.mean(0), rtol=1e-14)
+
+
 @pytest.mark.slow
 def test_bead_equipartition(orc):
     """Fluctuation-dissipation (Sec. II.B): a bead in the thermal fluid reaches
@@ -448,13 +531,14 @@ def test_window_tangent_values_equal_run(orc):
     assert np.array_equal(h, hv) and np.array_equal(a.n, b.n) and np.array_equal(a.x, b.x)
 
 
-def test_window_tangent_matches_finite_differences(orc):
+@pytest.mark.parametrize("N,chain_len", [(4, 0), (6, 3)])
+def test_window_tangent_matches_finite_differences(orc, N, chain_len):
     """d v(t) / d(omega_shear, omega_bulk, zeta) by forward mode equals central
-    differences of the oracle's own window."""
-    L, N, T = 6, 4, 8
-    base = dict(L=L, N=N, kT=1e-2, omega_s=1.2, omega_b=0.9, zeta=20.0)
+    differences of the oracle's own window (one chain, and two chains)."""
+    L, T = 6, 8
+    base = dict(L=L, N=N, chain_len=chain_len, kT=1e-2, omega_s=1.2, omega_b=0.9, zeta=20.0)
     n0 = _rand_state(orc, L, 0.02, 8)
-    x0 = lbinputs.saw_chain(N, L, 8)
+    x0 = lbinputs.initial_chains(dict(L=L, N=N, chain_len=chain_len, seed=8))
     bx, p = mkbox(orc, **base)
     _, dh = orc.State(bx, n0, x0).window_tangent(T)
     for k, name in enumerate(("omega_s", "omega_b", "zeta")):
