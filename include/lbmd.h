@@ -72,7 +72,9 @@ typedef enum { LB_THERM_OFF = 0, LB_THERM_STRESS = 1, LB_THERM_ALL = 2 } lb_ther
 /* One box.  An array of these is a batch of independent boxes. */
 typedef struct {
     int32_t L;            /* sites per edge, 2 <= L <= 1625; cubic, periodic, spacing 1 */
-    int32_t n_beads;      /* N, 0 <= N <= min(1024, L^3); 0 = pure fluid */
+    int32_t n_beads;      /* N, 0 <= N <= min(1024, L^3); 0 = pure fluid.  The
+                             beads of a box form one chain, or chain_len-bead
+                             chains (see chain_len) */
     double rho0;          /* fluid density, > 0 */
     double omega_shear;   /* shear-mode relaxation rate, in (0, 2) */
     double omega_bulk;    /* bulk-mode relaxation rate, in (0, 2) */
@@ -90,6 +92,12 @@ typedef struct {
     double sigma_wca;     /* LJ length, > 0; cut and shifted at 2^(1/6) sigma */
     uint32_t seed;        /* Philox key word 0 */
     uint32_t box_id;      /* Philox key word 1 */
+    int32_t chain_len;    /* beads per chain: beads c*chain_len .. c*chain_len +
+                             chain_len - 1 form chain c, bonded along the chain
+                             only; LJ acts between all beads of the box (a
+                             semidilute solution of N / chain_len chains,
+                             Sec. III.C).  0 = one chain of n_beads.  Must
+                             divide n_beads. */
 } lb_box_desc;
 
 /* Observables of one box, FP64 sums in a fixed order. */
@@ -100,9 +108,9 @@ typedef struct {
     double p_beads[3];    /* sum of m v over beads */
     double p_total[3];    /* p_fluid + p_beads + (md_dt/2) sum of the beads'
                              last coupling forces: conserved at LB-step boundaries */
-    double com[3];        /* chain centre of mass (unwrapped coordinates) */
-    double rg2;           /* radius of gyration squared */
-    double re2;           /* end-to-end distance squared */
+    double com[3];        /* centre of mass of the box's beads (unwrapped coordinates) */
+    double rg2;           /* radius of gyration squared, mean over the box's chains */
+    double re2;           /* end-to-end distance squared, mean over the box's chains */
     double neg_count;     /* number of populations n_i < 0 */
     double mode_sq[19];   /* sum over nodes of (m_k - rho0 delta_k0)^2 */
     uint32_t health;      /* LB_HEALTH_* bits accumulated since init (sticky) */

@@ -38,7 +38,7 @@ class BoxDesc(ctypes.Structure):
         ("zeta", ctypes.c_double), ("k_fene", ctypes.c_double),
         ("r0_fene", ctypes.c_double), ("eps_wca", ctypes.c_double),
         ("sigma_wca", ctypes.c_double), ("seed", ctypes.c_uint32),
-        ("box_id", ctypes.c_uint32),
+        ("box_id", ctypes.c_uint32), ("chain_len", ctypes.c_int32),
     ]
 
 
@@ -120,6 +120,7 @@ def make_desc(p: dict) -> BoxDesc:
     d.bead_mass, d.zeta, d.k_fene, d.r0_fene = p["mass"], p["zeta"], p["k_fene"], p["r0_fene"]
     d.eps_wca, d.sigma_wca = p["eps_wca"], p["sigma_wca"]
     d.seed, d.box_id = int(p["seed"]), int(p["box_id"])
+    d.chain_len = int(p.get("chain_len", 0))
     return d
 
 

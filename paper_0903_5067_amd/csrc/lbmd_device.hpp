@@ -25,7 +25,7 @@ struct BoxDev {
     int32_t therm;       // 0 none, 1 stress modes, 2 all non-conserved modes
     int32_t substeps;
     int32_t couple_T;    // lanes per bead on the one-workgroup coupling path (a function of N only)
-    int32_t pad_;
+    int32_t chain_len;   // beads per chain (> 0; N for a single chain)
     double rho0, gam_b, gam_s, gam_g, mu;
     double tau_lb, dt, mass, zeta, k_fene, r0sq, eps, sigsq, rc2, bead_noise;
     double inv_L, inv_r0sq;

@@ -171,15 +171,27 @@ __device__ __forceinline__ void stencil_velocities(const R* __restrict__ a, uint
 constexpr int MAXB = 1024;
 constexpr double NL_SKIN = 0.5;
 
-// FENE force on bead b from its bonded neighbours (Sec. II.A), unwrapped separations
-__device__ __forceinline__ uint32_t fene_force(const BoxDev& bx, int b, int N, const double x[3],
+// first and last bead of bead b's chain: a box's beads form chains of
+// chain_len consecutive indices (one chain, or the several chains of a
+// semidilute solution, Sec. III.C)
+struct ChainSpan { int lo, hi; };
+__device__ __forceinline__ ChainSpan chain_span(const BoxDev& bx, int b)
+{
+    const int n = bx.chain_len;
+    const int lo = b - b % n;
+    return ChainSpan{lo, lo + n - 1};
+}
+
+// FENE force on bead b from its bonded neighbours, b - 1 and b + 1 when they
+// are on its chain (Sec. II.A), unwrapped separations
+__device__ __forceinline__ uint32_t fene_force(const BoxDev& bx, int b, ChainSpan sp, const double x[3],
                                                const double* xs, double F[3])
 {
     uint32_t hb = 0;
 #pragma unroll
     for (int side = 0; side < 2; ++side) {
         const int j = side ? b + 1 : b - 1;
-        if (j < 0 || j >= N) continue;
+        if (j < sp.lo || j > sp.hi) continue;
         const double d0 = x[0] - xs[3 * j], d1 = x[1] - xs[3 * j + 1], d2 = x[2] - xs[3 * j + 2];
         const double r2 = d0 * d0 + d1 * d1 + d2 * d2;
         double den = 1.0 - r2 * bx.inv_r0sq;
@@ -251,7 +263,7 @@ __global__ __launch_bounds__(1024) void k_init_forces(const BoxDev* __restrict__
     __syncthreads();
     if (b < N) {
         double F[3] = {0, 0, 0};
-        uint32_t hb = fene_force(bx, b, N, x, xs, F);
+        uint32_t hb = fene_force(bx, b, chain_span(bx, b), x, xs, F);
         double W[3] = {0, 0, 0};
         for (int j = 0; j < N; ++j)
             if (j != b) wca_add(x, xs, j, (double)bx.L, bx.inv_L, bx.rc2, bx.sigsq, 24.0 * bx.eps, W);
@@ -305,6 +317,7 @@ __global__ __launch_bounds__(MAXT) void k_couple(const BoxDev* __restrict__ boxe
     const bool act = b < N;
     const bool writer = act && lane == 0;
     const uint64_t g = bx.bead_off + (uint64_t)(act ? b : 0);
+    const ChainSpan sp = chain_span(bx, act ? b : 0);
     const uint32_t t = ctrl->step + s_off;
     const int L = bx.L;
     const double Ld = (double)L, iL = bx.inv_L;
@@ -348,7 +361,7 @@ __global__ __launch_bounds__(MAXT) void k_couple(const BoxDev* __restrict__ boxe
                 for (int c = 0; c < 3; ++c) W[c] += __shfl_xor(W[c], o, T);
             }
             double F[3] = {0, 0, 0};
-            hbits |= fene_force(bx, b, N, x, xs, F);
+            hbits |= fene_force(bx, b, sp, x, xs, F);
             F[0] += W[0]; F[1] += W[1]; F[2] += W[2];
             // stencil of the bead: nodes at integer coordinates, periodic
             int i0[3];
@@ -539,6 +552,7 @@ __global__ __launch_bounds__(WG_MAXB) void k_chain_wg(const BoxDev* __restrict__
     const int b = (int)threadIdx.x;
     const bool act = b < N;
     const uint64_t g = bx.bead_off + (uint64_t)(act ? b : 0);
+    const ChainSpan sp = chain_span(bx, act ? b : 0);
     const uint32_t t = ctrl->step + s_off;
     const int L = bx.L;
     const double Ld = (double)L, iL = bx.inv_L;
@@ -646,7 +660,7 @@ __global__ __launch_bounds__(WG_MAXB) void k_chain_wg(const BoxDev* __restrict__
                 for (int j = 0; j < N; j += 4) wca_add4(x, xs, jof, j, N, 1, b, Ld, iL, bx.rc2, bx.sigsq, eps24, F);
             }
             double Ff[3] = {0, 0, 0};
-            hbits |= fene_force(bx, b, N, x, xs, Ff);
+            hbits |= fene_force(bx, b, sp, x, xs, Ff);
             F[0] = Ff[0] + F[0]; F[1] = Ff[1] + F[1]; F[2] = Ff[2] + F[2];
             double ub[3] = {0, 0, 0};
 #pragma unroll
@@ -862,7 +876,8 @@ __global__ __launch_bounds__(256) void k_stats_final(const BoxDev* __restrict__ 
 }
 
 // one block per box: chain sums.  Record: [0..2] sum x, [3..5] sum m v,
-// [6..8] sum fc, [9] R_e^2, then after the second pass [10] sum |x - com|^2.
+// [6..8] sum fc, [9] sum over the chains of R_e^2, then after the second pass
+// [10] sum over beads of |x - com of the bead's chain|^2.
 constexpr int NCHAIN = 11;
 
 __global__ __launch_bounds__(256) void k_chain_obs(const BoxDev* __restrict__ boxes, ChainArgs ca,
@@ -870,8 +885,10 @@ __global__ __launch_bounds__(256) void k_chain_obs(const BoxDev* __restrict__ bo
 {
     __shared__ double red[9][256];
     __shared__ double sums[9];
+    __shared__ double ccom[3 * MAXB];   // per-chain centres of mass (several chains)
     const BoxDev& bx = boxes[blockIdx.x];
     const int N = bx.N;
+    const int n = bx.chain_len, M = N > 0 ? N / n : 0;
     double acc[9];
     for (int k = 0; k < 9; ++k) acc[k] = 0.0;
     for (int b = threadIdx.x; b < N; b += 256) {
@@ -890,12 +907,22 @@ __global__ __launch_bounds__(256) void k_chain_obs(const BoxDev* __restrict__ bo
         __syncthreads();
     }
     if (threadIdx.x < 9) sums[threadIdx.x] = red[threadIdx.x][0];
+    // several chains: each chain's centre of mass, in bead order
+    if (M > 1)
+        for (int ch = threadIdx.x; ch < M; ch += 256) {
+            double cm[3] = {0, 0, 0};
+            for (int k = 0; k < n; ++k) {
+                const uint64_t g = bx.bead_off + (uint64_t)ch * n + k;
+                for (int c = 0; c < 3; ++c) cm[c] += ca.x[3 * g + c];
+            }
+            for (int c = 0; c < 3; ++c) ccom[3 * ch + c] = cm[c] / n;
+        }
     __syncthreads();
     double s = 0.0;
     for (int b = threadIdx.x; b < N; b += 256) {
         const uint64_t g = bx.bead_off + b;
         for (int c = 0; c < 3; ++c) {
-            const double d = ca.x[3 * g + c] - sums[c] / N;
+            const double d = ca.x[3 * g + c] - (M > 1 ? ccom[3 * (b / n) + c] : sums[c] / N);
             s += d * d;
         }
     }
@@ -910,8 +937,8 @@ __global__ __launch_bounds__(256) void k_chain_obs(const BoxDev* __restrict__ bo
         for (int k = 0; k < 9; ++k) o[k] = sums[k];
         o[10] = red[0][0];
         double e2 = 0.0;
-        if (N > 0) {
-            const uint64_t g0 = bx.bead_off, g1 = bx.bead_off + N - 1;
+        for (int ch = 0; ch < M; ++ch) {
+            const uint64_t g0 = bx.bead_off + (uint64_t)ch * n, g1 = g0 + n - 1;
             for (int c = 0; c < 3; ++c) {
                 const double d = ca.x[3 * g1 + c] - ca.x[3 * g0 + c];
                 e2 += d * d;
@@ -1245,6 +1272,7 @@ __global__ __launch_bounds__(256) void k_adj_couple(const BoxDev* __restrict__ b
     const bool act = b < N;
     const bool writer = act && lane == 0;
     const uint64_t g = bx.bead_off + (uint64_t)(act ? b : 0);
+    const ChainSpan sp = chain_span(bx, act ? b : 0);
     const double dt = bx.dt, h = 0.5 * dt / bx.mass, tau = bx.tau_lb, Ld = (double)L, iL = bx.inv_L;
     const double eps24 = 24.0 * bx.eps, s6c = bx.sigsq * bx.sigsq * bx.sigsq, s12c = s6c * s6c;
     double lx[3] = {0, 0, 0}, lv[3] = {0, 0, 0}, lf[3] = {0, 0, 0};
@@ -1374,7 +1402,7 @@ __global__ __launch_bounds__(256) void k_adj_couple(const BoxDev* __restrict__ b
             for (int j = lane; j < N; j += T) {
                 if (j == b) continue;
                 const double dl[3] = {lft[0] - lF[3 * j], lft[1] - lF[3 * j + 1], lft[2] - lF[3 * j + 2]};
-                if (j == b - 1 || j == b + 1) {
+                if ((j == b - 1 || j == b + 1) && j >= sp.lo && j <= sp.hi) {
                     const double d[3] = {x1[0] - xs[3 * j], x1[1] - xs[3 * j + 1], x1[2] - xs[3 * j + 2]};
                     const double r2 = d[0] * d[0] + d[1] * d[1] + d[2] * d[2];
                     const double den = 1.0 - r2 * bx.inv_r0sq;

@@ -67,6 +67,8 @@ bool validate(const lb_box_desc* b, int32_t n, int32_t prec, int32_t hist, std::
         if (d.L < 2 || d.L > 1625) return bad("L must be in [2, 1625]");
         const uint64_t V = (uint64_t)d.L * d.L * d.L;
         if (d.n_beads < 0 || d.n_beads > 1024 || (uint64_t)d.n_beads > V) return bad("N must be in [0, min(1024, L^3)]");
+        if (d.chain_len < 0 || (d.chain_len > 0 && d.n_beads > 0 && d.n_beads % d.chain_len != 0))
+            return bad("chain_len must be 0 or divide N");
         if (!(d.rho0 > 0)) return bad("rho0 must be > 0");
         for (double w : {d.omega_shear, d.omega_bulk, d.omega_ghost})
             if (!(w > 0 && w < 2)) return bad("relaxation rates must be in (0, 2)");
@@ -360,9 +362,10 @@ lb_status lb_init(const lb_box_desc* boxes, int32_t n_boxes, int32_t precision, 
     Layout lo = make_layout(boxes, n_boxes, precision, hist_steps);
     uint64_t nb = lo.total_beads;
     if (nb > 0 && !bead_x0) return fail(nullptr, LB_EINVAL, "bead_x0 is NULL but boxes have beads");
-    // initial bonds must be shorter than R0
+    // initial bonds (consecutive beads of one chain) must be shorter than R0
     for (int i = 0; i < n_boxes; ++i)
         for (int bd = 0; bd + 1 < boxes[i].n_beads; ++bd) {
+            if (boxes[i].chain_len > 0 && (bd + 1) % boxes[i].chain_len == 0) continue;
             const double* p = bead_x0 + 3 * (lo.bead_off[i] + bd);
             double r2 = 0;
             for (int c = 0; c < 3; ++c) r2 += (p[3 + c] - p[c]) * (p[3 + c] - p[c]);
@@ -397,7 +400,8 @@ lb_status lb_init(const lb_box_desc* boxes, int32_t n_boxes, int32_t precision, 
         b.node_off = lo.node_off[i]; b.pop_off = lo.pop_off[i]; b.ps = lo.ps[i]; b.bead_off = lo.bead_off[i];
         b.tile_begin = lo.tile_begin[i]; b.n_tiles = lo.n_tiles[i];
         b.therm = d.thermalize; b.substeps = d.md_substeps;
-        b.couple_T = lo.couple_T[i]; b.pad_ = 0;
+        b.couple_T = lo.couple_T[i];
+        b.chain_len = d.chain_len > 0 ? d.chain_len : std::max(d.n_beads, 1);
         b.rho0 = d.rho0; b.gam_b = 1 - d.omega_bulk; b.gam_s = 1 - d.omega_shear; b.gam_g = 1 - d.omega_ghost;
         b.mu = 3.0 * d.kT * d.tau_lb * d.tau_lb;
         b.tau_lb = d.tau_lb; b.dt = d.md_dt; b.mass = d.bead_mass; b.zeta = d.zeta; b.k_fene = d.k_fene;
@@ -614,8 +618,11 @@ lb_status lb_observables(lb_handle* h, lb_obs* out)
             o.p_total[a] = o.p_fluid[a] + o.p_beads[a] + 0.5 * d.md_dt * c[6 + a];
             o.com[a] = d.n_beads > 0 ? c[a] / d.n_beads : 0.0;
         }
+        // record: [9] sum over chains of R_e^2, [10] sum over beads of the
+        // square distance to their chain's centre of mass
+        const int chains = d.n_beads > 0 ? (d.chain_len > 0 ? d.n_beads / d.chain_len : 1) : 1;
         o.rg2 = d.n_beads > 0 ? c[10] / d.n_beads : 0.0;
-        o.re2 = c[9];
+        o.re2 = c[9] / chains;
         o.neg_count = s[4];
         for (int k = 0; k < 19; ++k) o.mode_sq[k] = s[5 + k];
         o.health = ctrl.health;

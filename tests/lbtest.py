@@ -29,7 +29,8 @@ def initial_pops(orc, p, amp=0.0, seed=0):
 
 
 def chain(p, seed=None):
-    return lbinputs.saw_chain(int(p["N"]), int(p["L"]), p["seed"] if seed is None else seed)
+    """Initial beads of box p: one chain, or N / chain_len chains."""
+    return lbinputs.initial_chains(p, seed)
 
 
 def gpu_system(boxes, precision, xs=None, pops=None, hist_steps=0):

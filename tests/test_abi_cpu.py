@@ -62,7 +62,7 @@ def test_query_sizes_layout(lbm):
 
 @pytest.mark.parametrize("bad", [dict(L=1), dict(omega_s=2.0), dict(omega_b=0.0), dict(kT=-1.0),
                                  dict(md_substeps=5), dict(therm=3), dict(N=2000), dict(rho0=0.0),
-                                 dict(L=4, N=65)])
+                                 dict(L=4, N=65), dict(N=10, chain_len=3), dict(chain_len=-1)])
 def test_invalid_parameters_rejected(lbm, bad):
     p = lbinputs.box_params("plain16", **bad)
     with pytest.raises(lbm.LBError) as ei:
@@ -74,6 +74,19 @@ def test_overstretched_initial_bond_rejected_before_device_work(lbm):
     p = lbinputs.box_params("plain16", L=8, N=3)
     arr = (lbm.BoxDesc * 1)(lbm.make_desc(p))
     x = (ctypes.c_double * 9)(1, 1, 1, 2, 1, 1, 3.6, 1, 1)    # second bond 1.6 > R0 = 1.5
+    h = ctypes.c_void_p()
+    st = lbm.lib().lb_init(arr, 1, 1, 0, x, ctypes.c_void_p(1 << 20), ctypes.c_void_p(1 << 21), None,
+                           ctypes.byref(h))
+    assert st == lbm.LB_EINVAL
+    assert b"R0" in lbm.lib().lb_last_error(None)
+
+
+def test_overstretched_bond_inside_a_chain_rejected(lbm):
+    """With two chains of three beads the gap between bead 2 and bead 3 is no
+    bond; a stretched bond inside the second chain still is."""
+    p = lbinputs.box_params("plain16", L=8, N=6, chain_len=3)
+    arr = (lbm.BoxDesc * 1)(lbm.make_desc(p))
+    x = (ctypes.c_double * 18)(1, 1, 1, 2, 1, 1, 3, 1, 1, 5, 5, 5, 6, 5, 5, 7.6, 5, 5)
     h = ctypes.c_void_p()
     st = lbm.lib().lb_init(arr, 1, 1, 0, x, ctypes.c_void_p(1 << 20), ctypes.c_void_p(1 << 21), None,
                            ctypes.byref(h))

@@ -71,6 +71,26 @@ def test_adjoint_linear_functional_matches_oracle_tangent(orc, prec, tol):
     np.testing.assert_allclose(grad, ref, rtol=tol, atol=tol * np.max(np.abs(ref)))
 
 
+@pytest.mark.parametrize("prec,tol", [(FP64, 1e-7), (FP32, 2e-3)])
+def test_adjoint_several_chains_matches_oracle_tangent(orc, prec, tol):
+    """Four chains of six beads in one box (bonds along each chain only): the
+    adjoint of the force Hessian leaves out the links between chains."""
+    say("adjoint several chains", prec)
+    p = _case(L=8, N=24, chain_len=6)
+    T, k = 12, 4
+    x0 = chain(p)
+    n0 = initial_pops(orc, p, amp=0.01, seed=12)
+    s = gpu_system([p], prec, xs=[x0], pops=[n0])
+    vh = s.window_forward(T, k)
+    cw = np.random.default_rng(6).normal(size=vh.shape)
+    grad = s.window_backward(cw)[0]
+    o = oracle_state(orc, p, n0, x0)
+    ho, dh = o.window_tangent(T)
+    assert np.max(np.abs(vh - ho)) < (1e-10 if prec == FP64 else 1e-5)
+    ref = np.einsum("tna,tnak->k", cw, dh)
+    np.testing.assert_allclose(grad, ref, rtol=tol, atol=tol * np.max(np.abs(ref)))
+
+
 def test_adjoint_vacf_loss_matches_oracle_and_fd(orc):
     """VACF mismatch loss: GPU adjoint vs oracle tangent vs central finite
     differences (relative step 1e-4) of the GPU's own forward window."""

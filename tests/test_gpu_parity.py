@@ -345,6 +345,64 @@ def test_big_chain_in_batch_bitwise():
             assert np.array_equal(batch[i][k], single[k]), (i, k)
 
 
+# ------------------------------------------------ several chains per box
+@pytest.mark.parametrize("prec", [FP64, FP32])
+@pytest.mark.parametrize("L,M,n", [(12, 6, 8), (16, 20, 16)])
+def test_several_chains_match_oracle(orc, prec, L, M, n):
+    """A semidilute box (Sec. III.C): M chains of n beads, bonded along each
+    chain only, LJ between all beads; on the one-workgroup path (48 beads) and
+    on the 1024-thread path (320 beads): one coupling and 30 full steps, then
+    the per-chain observables, against the oracle."""
+    say("several chains", prec, L, M, n)
+    p = params(L=L, N=M * n, chain_len=n, kT=1e-2)
+    x0 = chain(p)
+    n0 = initial_pops(orc, p, amp=0.01, seed=4)
+    s = gpu_system([p], prec, xs=[x0], pops=[n0])
+    s.couple()
+    dp_g = s.pending_impulse()[0]
+    bg = s.export_state()["boxes"][0]
+    o = oracle_state(orc, p, n0, x0)
+    dp_o = o.couple()
+    assert np.max(np.abs(dp_g - dp_o)) < (1e-13 if prec == FP64 else 1e-9)
+    for k, ref in (("x", o.x), ("v", o.v), ("f", o.f), ("fc", o.fc)):
+        assert np.max(np.abs(bg[k] - ref)) < (1e-11 if prec == FP64 else 1e-6), k
+    s.step(30)
+    o.collide_stream(dp_o)
+    o.run(29)
+    st = s.export_state()["boxes"][0]
+    assert max_rel_pop_err(st["n"], o.n, orc) < (1e-11 if prec == FP64 else 1e-5)
+    assert np.max(np.abs(st["x"] - o.x)) < (1e-9 if prec == FP64 else 1e-5)
+    ob, oo = s.observables()[0], o.observables()
+    rel = 1e-10 if prec == FP64 else 1e-6
+    assert ob["rg2"] == pytest.approx(oo[16], rel=rel)
+    assert ob["re2"] == pytest.approx(oo[17], rel=rel)
+    np.testing.assert_allclose(ob["com"], oo[13:16], rtol=rel)
+    # per-chain means, not the box taken as one chain
+    one = o.x.reshape(M, n, 3)
+    assert ob["re2"] == pytest.approx(np.mean(np.sum((one[:, -1] - one[:, 0]) ** 2, -1)), rel=rel)
+    assert ob["health"] == 0
+
+
+def test_several_chains_in_batch_bitwise():
+    """Boxes of several chains on both coupling paths, batched with a
+    one-chain box, equal the same boxes run alone."""
+    say("several chains batch")
+    boxes = [params(L=12, N=48, chain_len=8, seed=3, box_id=0),
+             params(L=16, N=320, chain_len=16, seed=3, box_id=1),
+             params(L=8, N=8, seed=3, box_id=2)]
+    xs = [chain(b) for b in boxes]
+    sb = gpu_system(boxes, FP32, xs=xs)
+    sb.set_launch(batched=True, graph_steps=4)
+    sb.step(9)
+    batch = sb.export_state()["boxes"]
+    for i, b in enumerate(boxes):
+        si = gpu_system([b], FP32, xs=[xs[i]])
+        si.step(9)
+        single = si.export_state()["boxes"][0]
+        for k in ("n", "x", "v", "f", "fc"):
+            assert np.array_equal(batch[i][k], single[k]), (i, k)
+
+
 # ------------------------------------------------ fast beads, paper parameters
 def _left_table(x_start, x_end, L):
     """Beads whose end-of-step base cell lies outside the 3x3x3 node table
