@@ -44,9 +44,11 @@ def make_system(preset, precision=None, n_boxes=None):
     if preset == "batched256":
         table = lbinputs.batched_table(n_boxes or P["n_boxes"], P["seed"])
         boxes = [lbinputs.box_params(preset, L=L, N=N, box_id=i) for i, (L, N) in enumerate(table)]
+    elif preset == "semidilute":
+        boxes = [lbinputs.box_params(preset, box_id=i) for i in range(n_boxes or P["n_boxes"])]
     else:
         boxes = [lbinputs.box_params(preset)]
-    xs = [lbinputs.saw_chain(b["N"], b["L"], b["seed"] + 7919 * b["box_id"]) for b in boxes]
+    xs = [lbinputs.initial_chains(b, b["seed"] + 7919 * b["box_id"]) for b in boxes]
     x0 = np.concatenate([x for x in xs if len(x)], axis=0) if any(len(x) for x in xs) else None
     s = lbm.LBSystem(boxes, precision=prec, bead_x0=x0)
     nodes = sum(int(b["L"]) ** 3 for b in boxes)
@@ -194,6 +196,38 @@ def adjoint_secondary():
             "grad_finite": bool(np.all(np.isfinite(g)))}
 
 
+def semidilute_secondary(steps=300, graph_steps=20):
+    """Semidilute solution (Sec. III.C): a batch of 20^3 boxes, each holding 32
+    chains of 32 beads (1024 beads, the 1024-thread coupling path), at the
+    paper's parameters; against the same boxes holding one 32-bead chain."""
+    import lbinputs
+    out = {}
+    for tag, chains in (("semidilute", None), ("one_chain_per_box", 1)):
+        if chains is None:
+            s, boxes, nodes, prec = make_system("semidilute")
+        else:
+            import paper_0903_5067_amd as lbm
+            P = lbinputs.PRESETS["semidilute"]
+            boxes = [lbinputs.box_params("semidilute", N=32, chain_len=0, box_id=i) for i in range(P["n_boxes"])]
+            xs = [lbinputs.initial_chains(b, b["seed"] + 7919 * b["box_id"]) for b in boxes]
+            s = lbm.LBSystem(boxes, precision=lbm.FP32_DEV, bead_x0=np.concatenate(xs))
+            nodes = sum(int(b["L"]) ** 3 for b in boxes)
+        s.set_launch(batched=True, graph_steps=graph_steps)
+        t, _ = time_steps(s, steps, 2 * graph_steps)
+        obs = s.observables()
+        beads = sum(int(b["N"]) for b in boxes)
+        sub = int(boxes[0]["md_substeps"])
+        out[tag] = {"boxes": len(boxes), "L": int(boxes[0]["L"]),
+                    "chains_per_box": int(boxes[0]["N"]) // (int(boxes[0]["chain_len"]) or int(boxes[0]["N"])),
+                    "beads_per_box": int(boxes[0]["N"]), "md_substeps": sub,
+                    "ms_per_step": round(1e3 * t / steps, 4), "mlups": round(nodes * steps / t / 1e6, 1),
+                    "bead_substeps_per_s": round(beads * sub * steps / t, 0),
+                    "mean_rg2": round(float(np.mean([o["rg2"] for o in obs])), 3),
+                    "health": int(max(o["health"] for o in obs))}
+        s.close()
+    return out
+
+
 def cpu_baseline(preset, budget_s=20.0):
     """The oracle (FP64 C, OpenMP) on the host cores: whole LB steps of the
     same box and chain, as many as fit a ~20 s budget (at least one).
@@ -294,6 +328,8 @@ def main():
                     help="launches of the collide kernel timed for the roofline (0: ~0.5 s worth)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run the plain copy used to scale the HBM byte counters")
+    ap.add_argument("--only-semidilute", action="store_true",
+                    help="only run the semidilute secondary and print it")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py runs on one GPU only: the path is built and measured for a single MI355X; "
@@ -305,6 +341,9 @@ def main():
     torch.cuda.init()
     if args.copy_calibration:
         copy_calibration()
+        return
+    if args.only_semidilute:
+        print(json.dumps(semidilute_secondary()), flush=True)
         return
     log("workload", args.workload)
     s, boxes, nodes, prec = make_system(args.workload)
@@ -390,6 +429,7 @@ def main():
         sb.close()
         sec["adjoint32"] = adjoint_secondary()
         sec["thermalization"] = thermalization_secondary()
+        sec["semidilute"] = semidilute_secondary()
         result["secondary"] = sec
         log("secondary", json.dumps(sec))
     if not args.no_cpu:

@@ -463,6 +463,28 @@ __global__ __launch_bounds__(MAXT) void k_couple(const BoxDev* __restrict__ boxe
 constexpr int WG_MAXB = 1024;
 constexpr int NEAR = 27;    // nodes in the table of one bead
 
+// Neighbour-list build over cells: nc cells per axis, each at least the list
+// radius wide (plus a margin far above rounding), so every partner within the
+// radius lies in the 3x3x3 cells around a bead's own.  A cell's bucket is its
+// coordinates mod 16 (4096 buckets): the 27 cells around any cell land in 27
+// distinct buckets when nc <= 16, or when nc mod 16 is neither 1 nor 2, which
+// list_cells ensures (it keeps nc mod 8 off 1 and 2 above 8 by taking fewer,
+// wider cells).  Beads of other cells that share a bucket fail the distance
+// test.  The test runs in FP32 on positions wrapped into the box, against a
+// radius 1e-3 above the list radius: an FP32 rounding of the coordinates
+// (under 2.5e-4 for L <= 1625) cannot drop a partner, and the few extra
+// partners are skipped by the force loop's exact cut-off test.
+constexpr int NBK = 4096;
+constexpr double NL_FP32_MARGIN = 1e-3;
+__device__ __forceinline__ int list_cells(int L, double rl)
+{
+    int nc = (int)floor((double)L / (rl + 1e-6));
+    if (nc > 8 && (nc % 8 == 1 || nc % 8 == 2)) nc -= nc % 8;
+    return nc;
+}
+__device__ __forceinline__ int wrap_cell(int q, int nc) { return q < 0 ? q + nc : (q >= nc ? q - nc : q); }
+__device__ __forceinline__ int bucket_of(int cx, int cy, int cz) { return (cx & 15) | ((cy & 15) << 4) | ((cz & 15) << 8); }
+
 // base-cell index and fraction of one coordinate (periodic, nodes at integers)
 __device__ __forceinline__ int cell_of(double xc, int L, double Ld, double iL, double& fr)
 {
@@ -545,6 +567,11 @@ __global__ __launch_bounds__(WG_MAXB) void k_chain_wg(const BoxDev* __restrict__
     __shared__ double xs[3 * WG_MAXB];           // current positions
     __shared__ double x0s[3 * WG_MAXB];          // positions at the last list build
     __shared__ uint16_t nls[NL_SLOTS * WG_MAXB];  // neighbour k of bead b at [k * WG_MAXB + b]
+    __shared__ uint32_t bk_cnt[NBK];             // list build: beads per cell bucket,
+    __shared__ uint32_t bk_wsum[WG_MAXB / 64];   //   per-wave totals of the scan,
+    __shared__ uint16_t bk_start[NBK + 1];       //   first slot of each bucket,
+    __shared__ uint16_t bk_bead[WG_MAXB];        //   beads ordered by bucket,
+    __shared__ float bk_pos[3 * WG_MAXB];        //   and their positions wrapped into the box
     __builtin_amdgcn_s_setprio(3);   // latency-bound chain beside the bandwidth-bound collide
     const int bi = list[blockIdx.x];
     const BoxDev& bx = boxes[bi];
@@ -598,25 +625,134 @@ __global__ __launch_bounds__(WG_MAXB) void k_chain_wg(const BoxDev* __restrict__
         }
         // one bead past half the skin rebuilds every list; also publishes xs
         rebuild = __syncthreads_or(rebuild);
-        if (rebuild && act) {
+        if (rebuild) {
             ++rebuilds;
             int cnt = 0;
-            for (int j = 0; j < N; ++j) {
-                if (j == b) continue;
+            // scan over every bead (boxes under three list radii across):
+            // partner j joins the list when its minimum-image distance is
+            // below the list radius
+            auto consider = [&](int j) {
                 double d0 = x[0] - xs[3 * j], d1 = x[1] - xs[3 * j + 1], d2 = x[2] - xs[3 * j + 2];
                 d0 -= Ld * rint(d0 * iL); d1 -= Ld * rint(d1 * iL); d2 -= Ld * rint(d2 * iL);
                 if (d0 * d0 + d1 * d1 + d2 * d2 < rl2) {
-                    if (cnt < nl_cap) {
-                        nls[cnt * WG_MAXB + b] = (uint16_t)j;
-                        ca.nl_idx[g * ca.nl_cap + cnt] = (uint16_t)j;
-                    }
+                    if (cnt < nl_cap) nls[cnt * WG_MAXB + b] = (uint16_t)j;
                     ++cnt;
                 }
-            }
-            nl_n = cnt > nl_cap ? -1 : cnt;   // -1: overflow, the full loop is used
-            ca.nl_cnt[g] = nl_n;
+            };
+            const int nc = list_cells(L, rl);
+            if (nc >= 3) {
+                // beads binned by cell bucket (counting sort in LDS), then each
+                // bead visits the 27 buckets around its own cell
+                int cc[3] = {0, 0, 0}, slot = 0, hb = 0;
+                float pb[3] = {0.f, 0.f, 0.f};   // own position wrapped into [0, L)
+                if (act) {
+                    const double scl = (double)nc / Ld;
 #pragma unroll
-            for (int c = 0; c < 3; ++c) { x0s[3 * b + c] = x[c]; ca.nl_x0[3 * g + c] = x[c]; }
+                    for (int c = 0; c < 3; ++c) {
+                        double xt = x[c] - Ld * floor(x[c] * iL);
+                        if (xt < 0.0) xt += Ld;
+                        if (xt >= Ld) xt -= Ld;
+                        const int q = (int)(xt * scl);
+                        cc[c] = q < 0 ? 0 : (q >= nc ? nc - 1 : q);
+                        pb[c] = (float)xt;
+                    }
+                    hb = bucket_of(cc[0], cc[1], cc[2]);
+                }
+                for (int i = b; i < NBK; i += WG_MAXB) bk_cnt[i] = 0u;
+                __syncthreads();
+                if (act) slot = (int)atomicAdd(&bk_cnt[hb], 1u);
+                __syncthreads();
+                // exclusive prefix sum of the bucket counts, four per thread: a
+                // scan per wave, then the totals of the waves before
+                static_assert(NBK == 4 * WG_MAXB, "four buckets per thread");
+                uint32_t vb[4], vs = 0;
+#pragma unroll
+                for (int u = 0; u < 4; ++u) { vb[u] = bk_cnt[4 * b + u]; vs += vb[u]; }
+                uint32_t inc = vs;
+                for (int o = 1; o < 64; o <<= 1) {
+                    const uint32_t t = __shfl_up(inc, o, 64);
+                    if ((b & 63) >= o) inc += t;
+                }
+                if ((b & 63) == 63) bk_wsum[b >> 6] = inc;
+                __syncthreads();
+                {
+                    uint32_t base = 0;
+                    for (int w = 0; w < (b >> 6); ++w) base += bk_wsum[w];
+                    uint32_t ex = base + inc - vs;
+#pragma unroll
+                    for (int u = 0; u < 4; ++u) { bk_start[4 * b + u] = (uint16_t)ex; ex += vb[u]; }
+                    if (b == WG_MAXB - 1) bk_start[NBK] = (uint16_t)ex;
+                }
+                __syncthreads();
+                if (act) {
+                    const int sl = bk_start[hb] + slot;
+                    bk_bead[sl] = (uint16_t)b;
+                    bk_pos[3 * sl] = pb[0]; bk_pos[3 * sl + 1] = pb[1]; bk_pos[3 * sl + 2] = pb[2];
+                }
+                __syncthreads();
+                if (act) {
+                    const float Lf = (float)Ld;
+                    const float rlf2 = (float)((rl + NL_FP32_MARGIN) * (rl + NL_FP32_MARGIN));
+                    for (int dz = -1; dz <= 1; ++dz) {
+                        const int rz = cc[2] + dz, qz = wrap_cell(rz, nc);
+                        // the neighbour cell's image next to this bead
+                        const float oz = pb[2] + (rz < 0 ? Lf : (rz >= nc ? -Lf : 0.f));
+                        for (int dy = -1; dy <= 1; ++dy) {
+                            const int ry = cc[1] + dy, qy = wrap_cell(ry, nc);
+                            const float oy = pb[1] + (ry < 0 ? Lf : (ry >= nc ? -Lf : 0.f));
+#pragma unroll 1
+                            for (int dx = -1; dx <= 1; ++dx) {
+                                const int rx = cc[0] + dx;
+                                const float ox = pb[0] + (rx < 0 ? Lf : (rx >= nc ? -Lf : 0.f));
+                                const int q = bucket_of(wrap_cell(rx, nc), qy, qz);
+                                const int k1 = bk_start[q + 1];
+                                // four candidates per pass: their loads overlap
+                                for (int k = bk_start[q]; k < k1; k += 4) {
+                                    int jj[4];
+                                    float r2[4];
+#pragma unroll
+                                    for (int u = 0; u < 4; ++u) {
+                                        const bool ok = k + u < k1;
+                                        const int sl = ok ? k + u : k;
+                                        jj[u] = ok ? (int)bk_bead[sl] : b;
+                                        const float d0 = bk_pos[3 * sl] - ox, d1 = bk_pos[3 * sl + 1] - oy,
+                                                    d2 = bk_pos[3 * sl + 2] - oz;
+                                        r2[u] = jj[u] == b ? rlf2 : d0 * d0 + d1 * d1 + d2 * d2;
+                                    }
+#pragma unroll
+                                    for (int u = 0; u < 4; ++u)
+                                        if (r2[u] < rlf2) {
+                                            if (cnt < nl_cap) nls[cnt * WG_MAXB + b] = (uint16_t)jj[u];
+                                            ++cnt;
+                                        }
+                                }
+                            }
+                        }
+                    }
+                    // ascending partner order, as a scan over all beads gives
+                    if (cnt <= nl_cap)
+                        for (int i = 1; i < cnt; ++i) {
+                            const uint16_t key = nls[i * WG_MAXB + b];
+                            int k = i - 1;
+                            while (k >= 0 && nls[k * WG_MAXB + b] > key) {
+                                nls[(k + 1) * WG_MAXB + b] = nls[k * WG_MAXB + b];
+                                --k;
+                            }
+                            nls[(k + 1) * WG_MAXB + b] = key;
+                        }
+                }
+            } else if (act) {   // boxes under three list radii across: every bead
+                for (int j = 0; j < N; ++j)
+                    if (j != b) consider(j);
+            }
+            if (act) {
+                const int kept = cnt < nl_cap ? cnt : nl_cap;
+                for (int k = 0; k < kept; ++k) ca.nl_idx[g * ca.nl_cap + k] = nls[k * WG_MAXB + b];
+                nl_n = cnt > nl_cap ? -1 : cnt;   // -1: overflow, the full loop is used
+                ca.nl_cnt[g] = nl_n;
+#pragma unroll
+                for (int c = 0; c < 3; ++c) { x0s[3 * b + c] = x[c]; ca.nl_x0[3 * g + c] = x[c]; }
+            }
         }
         if (act) {
             // stencil first: the last force is dead after the drift

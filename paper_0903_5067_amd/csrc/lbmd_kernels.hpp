@@ -79,7 +79,7 @@ constexpr int N_COLLIDE_VARIANTS = 10;
 constexpr int DEFAULT_COLLIDE_VARIANT = 3;   // one block per tile, at most 7 waves per SIMD
 constexpr int NSTAT_REC = 24;
 constexpr int NCHAIN_REC = 11;
-constexpr int NL_SLOTS = 48;
+constexpr int NL_SLOTS = 32;
 constexpr int TAPE_REC = 40;     // doubles per bead and substep in the adjoint tape
 
 }  // namespace lbd
