@@ -330,6 +330,8 @@ def main():
                     help="only run the plain copy used to scale the HBM byte counters")
     ap.add_argument("--only-semidilute", action="store_true",
                     help="only run the semidilute secondary and print it")
+    ap.add_argument("--only-adjoint", action="store_true",
+                    help="only run the adjoint-window secondary and print it")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py runs on one GPU only: the path is built and measured for a single MI355X; "
@@ -344,6 +346,9 @@ def main():
         return
     if args.only_semidilute:
         print(json.dumps(semidilute_secondary()), flush=True)
+        return
+    if args.only_adjoint:
+        print(json.dumps(adjoint_secondary()), flush=True)
         return
     log("workload", args.workload)
     s, boxes, nodes, prec = make_system(args.workload)
