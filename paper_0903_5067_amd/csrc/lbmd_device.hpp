@@ -17,8 +17,7 @@ struct BoxDev {
     int32_t L, N;
     uint32_t seed, box_id;
     uint64_t node_off;   // first global node index of the box (impulse-table keys)
-    uint64_t pop_off;    // element offset of the box's plane 0 in a population buffer
-    uint64_t ps;         // plane stride in elements (>= L^3, padded)
+    uint64_t pop_off;    // element offset of the box's first population tile
     uint64_t bead_off;   // first global bead index
     uint32_t tile_begin; // first collide tile of the box
     uint32_t n_tiles;
@@ -30,6 +29,22 @@ struct BoxDev {
     double tau_lb, dt, mass, zeta, k_fene, r0sq, eps, sigsq, rc2, bead_noise;
     double inv_L, inv_r0sq;
 };
+
+// Population storage of a box: its nodes fall into tiles of PTILE
+// consecutive nodes (x fastest), and a tile holds its 19 planes one after
+// another, PTILE values each.  A wavefront's 19 loads or stores then fall in
+// one 76 KB block (FP32) instead of 19 planes a box volume apart.
+constexpr uint32_t PTILE_LOG = 10;
+constexpr uint32_t PTILE = 1u << PTILE_LOG;
+__host__ __device__ __forceinline__ uint64_t pop_at(int i, uint32_t r)
+{
+    return ((uint64_t)(r >> PTILE_LOG) * 19u + (uint32_t)i) * PTILE + (r & (PTILE - 1u));
+}
+// elements of one box's populations in one buffer
+__host__ __device__ __forceinline__ uint64_t pop_elems_of(uint64_t V)
+{
+    return (V + PTILE - 1) / PTILE * 19u * PTILE;
+}
 
 // control block in device memory: step index read by every kernel so that a
 // captured graph can be replayed without re-recording arguments

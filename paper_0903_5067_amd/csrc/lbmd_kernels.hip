@@ -56,10 +56,13 @@ struct Upwind {
 };
 
 template <typename R, bool NT>
-__device__ __forceinline__ void gather_pre(const R* __restrict__ a, uint64_t ps, const Upwind& up, R d[19])
+__device__ __forceinline__ void gather_pre(const R* __restrict__ a, const Upwind& up, R d[19])
 {
 #pragma unroll
-    for (int i = 0; i < 19; ++i) d[i] = NT ? __builtin_nontemporal_load(a + i * ps + up.src(i)) : a[i * ps + up.src(i)];
+    for (int i = 0; i < 19; ++i) {
+        const uint64_t q = pop_at(i, up.src(i));
+        d[i] = NT ? __builtin_nontemporal_load(a + q) : a[q];
+    }
 }
 
 __device__ __forceinline__ Upwind upwind_of(uint32_t r, int L, double inv_L)
@@ -86,15 +89,14 @@ __device__ __forceinline__ void collide_tile(const BoxDev* __restrict__ boxes, c
     const uint32_t r = (tile - bx.tile_begin) * 256u + threadIdx.x;
     if (r >= V) return;
     const CollideConst<R> cc = ccs[bi];
-    const uint64_t ps = bx.ps;
     const Upwind up = upwind_of(r, L, bx.inv_L);
     R d[19];
-    gather_pre<R, false>(A + bx.pop_off, ps, up, d);
+    gather_pre<R, false>(A + bx.pop_off, up, d);
     R o[19];
     const uint32_t h = collide<R>(d, o, (R)0, (R)0, (R)0, cc, r, t, bx.seed, bx.box_id);
-    R* b = B + bx.pop_off + r;
+    R* b = B + bx.pop_off;
 #pragma unroll
-    for (int i = 0; i < 19; ++i) __builtin_nontemporal_store(o[i], b + i * ps);
+    for (int i = 0; i < 19; ++i) __builtin_nontemporal_store(o[i], b + pop_at(i, r));
     if (h) atomicOr(&ctrl->health, h);
 }
 
@@ -134,7 +136,7 @@ struct ChainArgs {
 // the loads of NB nodes are issued before any of them is used (NB = 8: one
 // round trip to memory, for register-rich callers)
 template <typename R, typename U, int NB>
-__device__ __forceinline__ void stencil_velocities(const R* __restrict__ a, uint64_t ps, const int i0[3], int L,
+__device__ __forceinline__ void stencil_velocities(const R* __restrict__ a, const int i0[3], int L,
                                                    double rho0, double inv_tau, U u[8][3])
 {
     static_assert(NB == 1 || NB == 2 || NB == 4 || NB == 8, "NB divides 8");
@@ -147,7 +149,7 @@ __device__ __forceinline__ void stencil_velocities(const R* __restrict__ a, uint
             const int ix = i0[0] + (kk & 1), iy = i0[1] + ((kk >> 1) & 1), iz = i0[2] + ((kk >> 2) & 1);
             const Upwind up((uint32_t)(ix >= L ? ix - L : ix), (uint32_t)(iy >= L ? iy - L : iy),
                             (uint32_t)(iz >= L ? iz - L : iz), (uint32_t)L);
-            gather_pre<R, false>(a, ps, up, d[k]);
+            gather_pre<R, false>(a, up, d[k]);
         }
 #pragma unroll
         for (int k = 0; k < NB; ++k) {
@@ -385,7 +387,7 @@ __global__ __launch_bounds__(MAXT) void k_couple(const BoxDev* __restrict__ boxe
                                (uint32_t)L * ((uint32_t)(iy >= L ? iy - L : iy) + (uint32_t)L * (uint32_t)(iz >= L ? iz - L : iz));
                     acc[k][0] = acc[k][1] = acc[k][2] = 0.0;
                 }
-                stencil_velocities<R, R, 8>(a, bx.ps, i0, L, bx.rho0, inv_tau, cu);
+                stencil_velocities<R, R, 8>(a, i0, L, bx.rho0, inv_tau, cu);
                 cb[0] = i0[0]; cb[1] = i0[1]; cb[2] = i0[2];
                 have_acc = true;
             }
@@ -534,7 +536,7 @@ __global__ __launch_bounds__(256) void k_near_nodes(const BoxDev* __restrict__ b
     const uint32_t ny = rem / (uint32_t)L, nx = rem - ny * (uint32_t)L;
     const Upwind up(nx, ny, nz, (uint32_t)L);
     R d[19];
-    gather_pre<R, false>(A + bx.pop_off, bx.ps, up, d);
+    gather_pre<R, false>(A + bx.pop_off, up, d);
     double rho = 0.0, jx = 0.0, jy = 0.0, jz = 0.0;
 #pragma unroll
     for (int i = 0; i < 19; ++i) {
@@ -784,7 +786,7 @@ __global__ __launch_bounds__(WG_MAXB) void k_chain_wg(const BoxDev* __restrict__
                     }
                 } else {   // moved past the table within this LB step: read the populations
                     const int i0v[3] = {cb0, cb1, cb2};
-                    stencil_velocities<R, R, 1>(A + bx.pop_off, bx.ps, i0v, L, bx.rho0, 1.0 / bx.tau_lb, cu);
+                    stencil_velocities<R, R, 1>(A + bx.pop_off, i0v, L, bx.rho0, 1.0 / bx.tau_lb, cu);
                 }
             }
             double F[3] = {0, 0, 0};
@@ -921,10 +923,9 @@ __global__ __launch_bounds__(256) void k_fixup(const BoxDev* __restrict__ boxes,
     if (atomicExch(&claim[node], t + 1u) == t + 1u) return;   // another slot took this node
     const int L = bx.L;
     const CollideConst<R> cc = ccs[bi];
-    const uint64_t ps = bx.ps;
     const Upwind up = upwind_of(r, L, bx.inv_L);
     R d[19];
-    gather_pre<R, false>(A + bx.pop_off, ps, up, d);
+    gather_pre<R, false>(A + bx.pop_off, up, d);
     R fimp[3];
 #pragma unroll
     for (int c = 0; c < 3; ++c) {
@@ -933,9 +934,9 @@ __global__ __launch_bounds__(256) void k_fixup(const BoxDev* __restrict__ boxes,
     }
     R o[19];
     const uint32_t h = collide<R>(d, o, fimp[0], fimp[1], fimp[2], cc, r, t, bx.seed, bx.box_id);
-    R* b = B + bx.pop_off + r;
+    R* b = B + bx.pop_off;
 #pragma unroll
-    for (int i = 0; i < 19; ++i) b[i * ps] = o[i];
+    for (int i = 0; i < 19; ++i) b[pop_at(i, r)] = o[i];
     if (h) atomicOr(&ctrl->health, h);
 }
 
@@ -968,7 +969,7 @@ __global__ __launch_bounds__(256) void k_stats(const BoxDev* __restrict__ boxes,
     if (r < V) {
         const Upwind up = upwind_of(r, bx.L, bx.inv_L);
         R dr[19];
-        gather_pre<R, false>(A + bx.pop_off, bx.ps, up, dr);
+        gather_pre<R, false>(A + bx.pop_off, up, dr);
         double d[19], m[19];
 #pragma unroll
         for (int i = 0; i < 19; ++i) {
@@ -1322,7 +1323,7 @@ __global__ __launch_bounds__(256) void k_adj_collide(const BoxDev* __restrict__ 
     if (r < V) {
         const Upwind up = upwind_of(r, L, bx.inv_L);
         R dr[19];
-        gather_pre<R, false>(P + bx.pop_off, bx.ps, up, dr);
+        gather_pre<R, false>(P + bx.pop_off, up, dr);
         double d[19], f[3] = {0, 0, 0};
 #pragma unroll
         for (int i = 0; i < 19; ++i) d[i] = (double)dr[i];
@@ -1473,7 +1474,7 @@ __global__ __launch_bounds__(256) void k_adj_couple(const BoxDev* __restrict__ b
                         const uint32_t nx = ix >= L ? ix - L : ix, ny = iy >= L ? iy - L : iy, nz = iz >= L ? iz - L : iz;
                         cnode[k] = nx + (uint32_t)L * (ny + (uint32_t)L * nz);
                         const Upwind up(nx, ny, nz, (uint32_t)L);
-                        gather_pre<R, false>(pb, bx.ps, up, dn[kk]);
+                        gather_pre<R, false>(pb, up, dn[kk]);
                     }
 #pragma unroll
                     for (int kk = 0; kk < NB; ++kk) {

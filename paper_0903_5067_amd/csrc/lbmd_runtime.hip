@@ -39,7 +39,7 @@ constexpr double MODE_B[19] = {1, 1. / 3, 1. / 3, 1. / 3, 2. / 3, 4. / 3, 4. / 9
 
 struct Layout {
     size_t esz = 8;
-    std::vector<uint64_t> pop_off, ps, bead_off, V, node_off;
+    std::vector<uint64_t> pop_off, bead_off, V, node_off;
     std::vector<uint32_t> tile_begin, n_tiles;
     uint64_t pop_elems = 0, total_tiles = 0, total_beads = 0, total_nodes = 0;
     size_t st_popA = 0, st_popB = 0, st_x = 0, st_v = 0, st_f = 0, st_fc = 0, state_bytes = 0;
@@ -88,20 +88,15 @@ Layout make_layout(const lb_box_desc* b, int32_t n, int32_t prec, int32_t hist)
 {
     Layout Lo;
     Lo.esz = prec == LB_FP64 ? 8 : 4;
-    const uint64_t align_el = 256 / Lo.esz;
-    uint64_t pad = align_el;
-    if (const char* e = std::getenv("LBMD_PLANE_PAD")) pad = round_up(std::strtoull(e, nullptr, 10), align_el);
     uint64_t pop = 0, tiles = 0, beads = 0, nodes = 0;
     int max_sub = 1;
     for (int i = 0; i < n; ++i) max_sub = std::max(max_sub, b[i].md_substeps);
     Lo.touch_cap = 8 * (max_sub + 1);
     for (int i = 0; i < n; ++i) {
         const uint64_t V = (uint64_t)b[i].L * b[i].L * b[i].L;
-        const uint64_t ps = round_up(V, align_el) + pad;
         Lo.V.push_back(V);
-        Lo.ps.push_back(ps);
         Lo.pop_off.push_back(pop);
-        pop += 19 * ps;
+        pop += pop_elems_of(V);   // whole tiles of PTILE nodes (4 or 8 KB per plane)
         Lo.tile_begin.push_back((uint32_t)tiles);
         Lo.n_tiles.push_back((uint32_t)((V + 255) / 256));
         tiles += (V + 255) / 256;
@@ -397,7 +392,7 @@ lb_status lb_init(const lb_box_desc* boxes, int32_t n_boxes, int32_t precision, 
         BoxDev& b = bd[i];
         std::memset(&b, 0, sizeof b);
         b.L = d.L; b.N = d.n_beads; b.seed = d.seed; b.box_id = d.box_id;
-        b.node_off = lo.node_off[i]; b.pop_off = lo.pop_off[i]; b.ps = lo.ps[i]; b.bead_off = lo.bead_off[i];
+        b.node_off = lo.node_off[i]; b.pop_off = lo.pop_off[i]; b.bead_off = lo.bead_off[i];
         b.tile_begin = lo.tile_begin[i]; b.n_tiles = lo.n_tiles[i];
         b.therm = d.thermalize; b.substeps = d.md_substeps;
         b.couple_T = lo.couple_T[i];
@@ -657,10 +652,10 @@ lb_status lb_export_state(lb_handle* h, void* host_buf, size_t bytes)
     for (int i = 0; i < h->n_boxes; ++i) {
         const uint64_t V = lo.V[i];
         double* n = (double*)o;
-        std::vector<char> raw(V * lo.esz);
+        std::vector<char> raw(pop_elems_of(V) * lo.esz);
         const int L = h->desc[i].L;
+        HIPCHK(h, hipMemcpy(raw.data(), P + lo.pop_off[i] * lo.esz, raw.size(), hipMemcpyDeviceToHost));
         for (int q = 0; q < 19; ++q) {
-            HIPCHK(h, hipMemcpy(raw.data(), P + (lo.pop_off[i] + q * lo.ps[i]) * lo.esz, V * lo.esz, hipMemcpyDeviceToHost));
             const double base = wv(q) * h->desc[i].rho0;
             // stored p_q(s) is the population that arrives at s + c_q
             for (int z = 0; z < L; ++z)
@@ -669,7 +664,8 @@ lb_status lb_export_state(lb_handle* h, void* host_buf, size_t bytes)
                         const uint64_t s = x + (uint64_t)L * (y + (uint64_t)L * z);
                         const int xd = (x + cxv(q) + L) % L, yd = (y + cyv(q) + L) % L, zd = (z + czv(q) + L) % L;
                         const uint64_t dd = xd + (uint64_t)L * (yd + (uint64_t)L * zd);
-                        const double dv = lo.esz == 8 ? ((const double*)raw.data())[s] : (double)((const float*)raw.data())[s];
+                        const uint64_t a = pop_at(q, (uint32_t)s);
+                        const double dv = lo.esz == 8 ? ((const double*)raw.data())[a] : (double)((const float*)raw.data())[a];
                         n[q * V + dd] = base + dv;
                     }
         }
@@ -700,7 +696,7 @@ lb_status lb_import_state(lb_handle* h, const void* host_buf, size_t bytes)
     for (int i = 0; i < h->n_boxes; ++i) {
         const uint64_t V = lo.V[i];
         const double* n = (const double*)o;
-        std::vector<char> raw(V * lo.esz);
+        std::vector<char> raw(pop_elems_of(V) * lo.esz, 0);
         const int L = h->desc[i].L;
         for (int q = 0; q < 19; ++q) {
             const double base = wv(q) * h->desc[i].rho0;
@@ -710,11 +706,12 @@ lb_status lb_import_state(lb_handle* h, const void* host_buf, size_t bytes)
                         const uint64_t s = x + (uint64_t)L * (y + (uint64_t)L * z);
                         const int xd = (x + cxv(q) + L) % L, yd = (y + cyv(q) + L) % L, zd = (z + czv(q) + L) % L;
                         const double dv = n[q * V + xd + (uint64_t)L * (yd + (uint64_t)L * zd)] - base;
-                        if (lo.esz == 8) ((double*)raw.data())[s] = dv;
-                        else ((float*)raw.data())[s] = (float)dv;
+                        const uint64_t a = pop_at(q, (uint32_t)s);
+                        if (lo.esz == 8) ((double*)raw.data())[a] = dv;
+                        else ((float*)raw.data())[a] = (float)dv;
                     }
-            HIPCHK(h, hipMemcpy(P + (lo.pop_off[i] + q * lo.ps[i]) * lo.esz, raw.data(), V * lo.esz, hipMemcpyHostToDevice));
         }
+        HIPCHK(h, hipMemcpy(P + lo.pop_off[i] * lo.esz, raw.data(), raw.size(), hipMemcpyHostToDevice));
         o += 19 * V * sizeof(double);
         const size_t nbb = (size_t)h->desc[i].n_beads * 3 * sizeof(double);
         const size_t goff = lo.bead_off[i] * 3 * sizeof(double);
