@@ -917,6 +917,7 @@ __global__ __launch_bounds__(256) void k_fixup(const BoxDev* __restrict__ boxes,
     if (k >= ca.touched_cnt[g]) return;
     const int bi = bead_box[g];
     const BoxDev& bx = boxes[bi];
+    if (bx.dense) return;   // its collide takes the impulses itself
     const uint32_t r = ca.touched[g * ca.touch_cap + k];
     const uint64_t node = bx.node_off + r;
     const uint32_t t = ctrl->step + s_off;
@@ -937,6 +938,42 @@ __global__ __launch_bounds__(256) void k_fixup(const BoxDev* __restrict__ boxes,
     R* b = B + bx.pop_off;
 #pragma unroll
     for (int i = 0; i < 19; ++i) b[pop_at(i, r)] = o[i];
+    if (h) atomicOr(&ctrl->health, h);
+}
+
+// Collide and stream every node of a dense box after its coupling stage: the
+// node's impulse comes straight from the fixed-point field, which is cleared
+// where it was set.  Same arithmetic as the fix-up, over whole tiles.
+template <typename R>
+__global__ __launch_bounds__(256) void k_collide_forced(const BoxDev* __restrict__ boxes,
+                                                        const CollideConst<R>* __restrict__ ccs,
+                                                        const uint32_t* __restrict__ tile_box, int fixed_box,
+                                                        uint32_t tile0, unsigned long long* __restrict__ imp,
+                                                        const R* __restrict__ A, R* __restrict__ B,
+                                                        Ctrl* __restrict__ ctrl, uint32_t s_off)
+{
+    const uint32_t tile = tile0 + blockIdx.x;
+    const int bi = fixed_box >= 0 ? fixed_box : (int)tile_box[tile];
+    const BoxDev& bx = boxes[bi];
+    const int L = bx.L;
+    const uint32_t V = (uint32_t)L * L * L;
+    const uint32_t r = (tile - bx.tile_begin) * 256u + threadIdx.x;
+    if (r >= V) return;
+    const uint32_t t = ctrl->step + s_off;
+    const CollideConst<R> cc = ccs[bi];
+    const Upwind up = upwind_of(r, L, bx.inv_L);
+    R d[19];
+    gather_pre<R, false>(A + bx.pop_off, up, d);
+    unsigned long long* q = imp + 3 * (bx.node_off + r);
+    const unsigned long long q0 = q[0], q1 = q[1], q2 = q[2];
+    if (q0 | q1 | q2) { q[0] = 0ull; q[1] = 0ull; q[2] = 0ull; }
+    const R fx = (R)((double)(long long)q0 * IMP_INV_SCALE), fy = (R)((double)(long long)q1 * IMP_INV_SCALE),
+            fz = (R)((double)(long long)q2 * IMP_INV_SCALE);
+    R o[19];
+    const uint32_t h = collide<R>(d, o, fx, fy, fz, cc, r, t, bx.seed, bx.box_id);
+    R* b = B + bx.pop_off;
+#pragma unroll
+    for (int i = 0; i < 19; ++i) __builtin_nontemporal_store(o[i], b + pop_at(i, r));
     if (h) atomicOr(&ctrl->health, h);
 }
 
@@ -1131,6 +1168,17 @@ hipError_t launch_fixup(const LaunchCtx& c, const void* A, void* B, uint64_t bea
     hipLaunchKernelGGL(k_fixup<R>, dim3((n + 255) / 256), dim3(256), 0, c.stream, c.boxes,
                        (const CollideConst<R>*)c.ccs, c.bead_box, bead0, n, chain_args(c), c.claim,
                        (const R*)A, (R*)B, c.ctrl, s_off);
+    return hipGetLastError();
+}
+
+template <typename R>
+hipError_t launch_collide_forced(const LaunchCtx& c, const void* A, void* B, int fixed_box, uint32_t tile0,
+                                 uint32_t n_tiles, uint32_t s_off)
+{
+    if (n_tiles == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_collide_forced<R>, dim3(n_tiles), dim3(256), 0, c.stream, c.boxes,
+                       (const CollideConst<R>*)c.ccs, c.tile_box, fixed_box, tile0, c.imp, (const R*)A, (R*)B,
+                       c.ctrl, s_off);
     return hipGetLastError();
 }
 
@@ -1628,6 +1676,10 @@ template hipError_t launch_collide<float>(const LaunchCtx&, const void*, void*, 
 template hipError_t launch_collide<double>(const LaunchCtx&, const void*, void*, int, uint32_t, uint32_t, uint32_t);
 template hipError_t launch_fixup<float>(const LaunchCtx&, const void*, void*, uint64_t, uint64_t, uint32_t);
 template hipError_t launch_fixup<double>(const LaunchCtx&, const void*, void*, uint64_t, uint64_t, uint32_t);
+template hipError_t launch_collide_forced<float>(const LaunchCtx&, const void*, void*, int, uint32_t, uint32_t,
+                                                 uint32_t);
+template hipError_t launch_collide_forced<double>(const LaunchCtx&, const void*, void*, int, uint32_t, uint32_t,
+                                                  uint32_t);
 template hipError_t launch_couple<float>(const LaunchCtx&, const void*, const int32_t*, int, int, uint32_t);
 template hipError_t launch_couple<double>(const LaunchCtx&, const void*, const int32_t*, int, int, uint32_t);
 template hipError_t launch_couple_big<float>(const LaunchCtx&, const void*, const int32_t*, int, int, uint32_t,

@@ -43,6 +43,9 @@ template <typename R>
 hipError_t launch_fixup(const LaunchCtx& c, const void* A, void* B, uint64_t bead0, uint64_t n_beads,
                         uint32_t s_off);
 template <typename R>
+hipError_t launch_collide_forced(const LaunchCtx& c, const void* A, void* B, int fixed_box, uint32_t tile0,
+                                 uint32_t n_tiles, uint32_t s_off);
+template <typename R>
 hipError_t launch_couple(const LaunchCtx& c, const void* A, const int32_t* list, int n_list, int block,
                          uint32_t s_off);
 // chains of BIG_CHAIN+1..1024 beads (at most max_n): one 1024-thread workgroup

@@ -41,6 +41,8 @@ struct Layout {
     size_t esz = 8;
     std::vector<uint64_t> pop_off, bead_off, V, node_off;
     std::vector<uint32_t> tile_begin, n_tiles;
+    std::vector<uint8_t> dense;                       // per box: collide after the coupling, no fix-up
+    uint64_t tiles_sparse = 0, beads_sparse = 0;      // collide tiles (first in tile order) and beads of the other boxes
     uint64_t pop_elems = 0, total_tiles = 0, total_beads = 0, total_nodes = 0;
     size_t st_popA = 0, st_popB = 0, st_x = 0, st_v = 0, st_f = 0, st_fc = 0, state_bytes = 0;
     size_t sc_ctrl = 0, sc_boxes = 0, sc_ccs = 0, sc_tilebox = 0, sc_couple = 0, sc_imp = 0, sc_claim = 0,
@@ -97,9 +99,13 @@ Layout make_layout(const lb_box_desc* b, int32_t n, int32_t prec, int32_t hist)
         Lo.V.push_back(V);
         Lo.pop_off.push_back(pop);
         pop += pop_elems_of(V);   // whole tiles of PTILE nodes (4 or 8 KB per plane)
-        Lo.tile_begin.push_back((uint32_t)tiles);
         Lo.n_tiles.push_back((uint32_t)((V + 255) / 256));
         tiles += (V + 255) / 256;
+        // a chain on the workgroup path whose stencils (8 nodes per bead)
+        // cover a quarter of the box or more: re-colliding its nodes in a
+        // fix-up would cost more than colliding the box after the coupling
+        Lo.dense.push_back(b[i].n_beads > BIG_CHAIN && 32 * (uint64_t)b[i].n_beads >= V ? 1 : 0);
+        if (!Lo.dense.back()) Lo.beads_sparse += (uint64_t)b[i].n_beads;
         Lo.bead_off.push_back(beads);
         beads += b[i].n_beads;
         Lo.node_off.push_back(nodes);
@@ -114,6 +120,17 @@ Layout make_layout(const lb_box_desc* b, int32_t n, int32_t prec, int32_t hist)
             Lo.max_N = std::max(Lo.max_N, N);
         }
     }
+    // collide tiles: the other boxes first, dense boxes after them, so that
+    // each group is one contiguous range
+    uint64_t t0 = 0;
+    Lo.tile_begin.assign(n, 0);
+    for (int pass = 0; pass < 2; ++pass)
+        for (int i = 0; i < n; ++i)
+            if (Lo.dense[i] == pass) {
+                Lo.tile_begin[i] = (uint32_t)t0;
+                t0 += Lo.n_tiles[i];
+                if (pass == 0) Lo.tiles_sparse = t0;
+            }
     Lo.pop_elems = pop;
     Lo.total_tiles = tiles;
     Lo.total_beads = beads;
@@ -274,12 +291,15 @@ lb_status enqueue_step(lb_handle* h, int from, uint32_t s_off, bool couple)
             HIPCHK(h, hipEventRecord(h->ev_join, h->stream2));
             if (nbig) HIPCHK(h, hipStreamWaitEvent(h->stream, h->ev_table, 0));
         }
-        HIPCHK(h, f64 ? launch_collide<double>(c, A, B, -1, 0, (uint32_t)h->lo.total_tiles, s_off)
-                      : launch_collide<float>(c, A, B, -1, 0, (uint32_t)h->lo.total_tiles, s_off));
+        const uint32_t ts = (uint32_t)h->lo.tiles_sparse, td = (uint32_t)(h->lo.total_tiles - h->lo.tiles_sparse);
+        HIPCHK(h, f64 ? launch_collide<double>(c, A, B, -1, 0, ts, s_off)
+                      : launch_collide<float>(c, A, B, -1, 0, ts, s_off));
         if (fork) HIPCHK(h, hipStreamWaitEvent(h->stream, h->ev_join, 0));
-        if (h->lo.total_beads)
+        if (h->lo.beads_sparse)
             HIPCHK(h, f64 ? launch_fixup<double>(c, A, B, 0, h->lo.total_beads, s_off)
                           : launch_fixup<float>(c, A, B, 0, h->lo.total_beads, s_off));
+        HIPCHK(h, f64 ? launch_collide_forced<double>(c, A, B, -1, ts, td, s_off)
+                      : launch_collide_forced<float>(c, A, B, -1, ts, td, s_off));
     } else {
         for (int i = 0; i < nc; ++i) {
             if (!couple) break;
@@ -292,6 +312,11 @@ lb_status enqueue_step(lb_handle* h, int from, uint32_t s_off, bool couple)
                           : launch_couple_big<float>(c, A, h->big_list + k, 1, nk, s_off, nullptr));
         }
         for (int b = 0; b < h->n_boxes; ++b) {
+            if (h->lo.dense[b]) {
+                HIPCHK(h, f64 ? launch_collide_forced<double>(c, A, B, b, h->lo.tile_begin[b], h->lo.n_tiles[b], s_off)
+                              : launch_collide_forced<float>(c, A, B, b, h->lo.tile_begin[b], h->lo.n_tiles[b], s_off));
+                continue;
+            }
             HIPCHK(h, f64 ? launch_collide<double>(c, A, B, b, h->lo.tile_begin[b], h->lo.n_tiles[b], s_off)
                           : launch_collide<float>(c, A, B, b, h->lo.tile_begin[b], h->lo.n_tiles[b], s_off));
             const uint64_t nb = (uint64_t)h->desc[b].n_beads;
@@ -397,6 +422,8 @@ lb_status lb_init(const lb_box_desc* boxes, int32_t n_boxes, int32_t precision, 
         b.therm = d.thermalize; b.substeps = d.md_substeps;
         b.couple_T = lo.couple_T[i];
         b.chain_len = d.chain_len > 0 ? d.chain_len : std::max(d.n_beads, 1);
+        b.dense = lo.dense[i];
+        b.pad_ = 0;
         b.rho0 = d.rho0; b.gam_b = 1 - d.omega_bulk; b.gam_s = 1 - d.omega_shear; b.gam_g = 1 - d.omega_ghost;
         b.mu = 3.0 * d.kT * d.tau_lb * d.tau_lb;
         b.tau_lb = d.tau_lb; b.dt = d.md_dt; b.mass = d.bead_mass; b.zeta = d.zeta; b.k_fene = d.k_fene;
