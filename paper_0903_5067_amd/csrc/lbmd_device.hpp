@@ -19,6 +19,7 @@ struct BoxDev {
     uint64_t node_off;   // first global node index of the box (impulse-table keys)
     uint64_t pop_off;    // element offset of the box's first population tile
     uint64_t bead_off;   // first global bead index
+    uint64_t field_off;  // dense boxes: first node of the box in the node-velocity field
     uint32_t tile_begin; // first collide tile of the box
     uint32_t n_tiles;
     int32_t therm;       // 0 none, 1 stress modes, 2 all non-conserved modes

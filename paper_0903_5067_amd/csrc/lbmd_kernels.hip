@@ -515,10 +515,54 @@ __device__ __forceinline__ int nearest_of(double xc, int L, double Ld, double iL
     return n >= L ? n - L : n;
 }
 
+// fluid velocity of one node in MD units (u = j / rho / tau_lb) from its
+// gathered pre-collision deviations
+template <typename R>
+__device__ __forceinline__ void node_velocity(const R d[19], double rho0, double inv_tau, R u[3])
+{
+    double rho = 0.0, jx = 0.0, jy = 0.0, jz = 0.0;
+#pragma unroll
+    for (int i = 0; i < 19; ++i) {
+        const double di = (double)d[i];
+        rho += di;
+        if (cxv(i)) jx += cxv(i) * di;
+        if (cyv(i)) jy += cyv(i) * di;
+        if (czv(i)) jz += czv(i) * di;
+    }
+    rho += rho0;
+    u[0] = (R)(jx / rho * inv_tau);
+    u[1] = (R)(jy / rho * inv_tau);
+    u[2] = (R)(jz / rho * inv_tau);
+}
+
+// dense boxes: the velocity of every node, once per LB step, so that their
+// beads' tables read 3 values per node instead of gathering 19 populations
+// (the tables of a dense box cover it several times over)
+template <typename R>
+__global__ __launch_bounds__(256) void k_node_field(const BoxDev* __restrict__ boxes,
+                                                    const int32_t* __restrict__ list, const R* __restrict__ A,
+                                                    R* __restrict__ field)
+{
+    const BoxDev& bx = boxes[list[blockIdx.y]];
+    if (!bx.dense) return;
+    const int L = bx.L;
+    const uint32_t V = (uint32_t)L * L * L;
+    const uint32_t r = blockIdx.x * 256u + threadIdx.x;
+    if (r >= V) return;
+    const Upwind up = upwind_of(r, L, bx.inv_L);
+    R d[19];
+    gather_pre<R, false>(A + bx.pop_off, up, d);
+    R u[3];
+    node_velocity<R>(d, bx.rho0, 1.0 / bx.tau_lb, u);
+    R* o = field + 3 * (bx.field_off + r);
+    o[0] = u[0]; o[1] = u[1]; o[2] = u[2];
+}
+
 template <typename R>
 __global__ __launch_bounds__(256) void k_near_nodes(const BoxDev* __restrict__ boxes,
                                                     const int32_t* __restrict__ list, const R* __restrict__ A,
-                                                    ChainArgs ca, R* __restrict__ near_u, int4* __restrict__ near_c)
+                                                    ChainArgs ca, R* __restrict__ near_u, int4* __restrict__ near_c,
+                                                    const R* __restrict__ field)
 {
     const BoxDev& bx = boxes[list[blockIdx.y]];
     const int N = bx.N, L = bx.L;
@@ -532,26 +576,20 @@ __global__ __launch_bounds__(256) void k_near_nodes(const BoxDev* __restrict__ b
     if (q == 0) near_c[g] = make_int4(n0, n1, n2, 0);
     const int ix = n0 - 1 + q % 3, iy = n1 - 1 + (q / 3) % 3, iz = n2 - 1 + q / 9;
     const uint32_t node = node_of(ix, iy, iz, L);
+    R* o = near_u + (g * NEAR + (uint64_t)q) * 3;
+    if (bx.dense) {
+        const R* fu = field + 3 * (bx.field_off + node);
+        o[0] = fu[0]; o[1] = fu[1]; o[2] = fu[2];
+        return;
+    }
     const uint32_t nz = node / ((uint32_t)L * (uint32_t)L), rem = node - nz * (uint32_t)L * (uint32_t)L;
     const uint32_t ny = rem / (uint32_t)L, nx = rem - ny * (uint32_t)L;
     const Upwind up(nx, ny, nz, (uint32_t)L);
     R d[19];
     gather_pre<R, false>(A + bx.pop_off, up, d);
-    double rho = 0.0, jx = 0.0, jy = 0.0, jz = 0.0;
-#pragma unroll
-    for (int i = 0; i < 19; ++i) {
-        const double di = (double)d[i];
-        rho += di;
-        if (cxv(i)) jx += cxv(i) * di;
-        if (cyv(i)) jy += cyv(i) * di;
-        if (czv(i)) jz += czv(i) * di;
-    }
-    rho += bx.rho0;
-    const double inv_tau = 1.0 / bx.tau_lb;
-    R* o = near_u + (g * NEAR + (uint64_t)q) * 3;
-    o[0] = (R)(jx / rho * inv_tau);
-    o[1] = (R)(jy / rho * inv_tau);
-    o[2] = (R)(jz / rho * inv_tau);
+    R u[3];
+    node_velocity<R>(d, bx.rho0, 1.0 / bx.tau_lb, u);
+    o[0] = u[0]; o[1] = u[1]; o[2] = u[2];
 }
 
 // one substep of one bead, as k_spread reads it
@@ -1200,8 +1238,11 @@ hipError_t launch_couple_big(const LaunchCtx& c, const void* A, const int32_t* l
     if (n_list == 0) return hipSuccess;
     if (c.nl_cap > NL_SLOTS || max_n > WG_MAXB || max_n <= 0) return hipErrorInvalidValue;
     const ChainArgs ca = chain_args(c);
+    if (c.dense_max_tiles)
+        hipLaunchKernelGGL(k_node_field<R>, dim3(c.dense_max_tiles, n_list), dim3(256), 0, c.stream, c.boxes, list,
+                           (const R*)A, (R*)c.field);
     hipLaunchKernelGGL(k_near_nodes<R>, dim3((max_n * NEAR + 255) / 256, n_list), dim3(256), 0, c.stream, c.boxes,
-                       list, (const R*)A, ca, (R*)c.near_u, c.near_c);
+                       list, (const R*)A, ca, (R*)c.near_u, c.near_c, (const R*)c.field);
     if (after_table) {
         const hipError_t e = hipEventRecord(after_table, c.stream);
         if (e != hipSuccess) return e;

@@ -34,6 +34,8 @@ struct LaunchCtx {
     void* near_u;                  // [total beads][27][3] node velocities around each bead (storage precision)
     int4* near_c;                  // [total beads] nearest node the table is centred on
     double* sub_rec;               // [most substeps][total beads][8] per-substep records
+    void* field;                   // dense boxes: node velocities (MD units, storage precision) [nodes][3]
+    uint32_t dense_max_tiles;      // collide tiles of the largest dense box (0: none)
 };
 
 template <typename R>

@@ -42,13 +42,16 @@ struct Layout {
     std::vector<uint64_t> pop_off, bead_off, V, node_off;
     std::vector<uint32_t> tile_begin, n_tiles;
     std::vector<uint8_t> dense;                       // per box: collide after the coupling, no fix-up
+    std::vector<uint64_t> field_off;                  // per box: first node in the velocity field (dense boxes)
+    uint64_t field_nodes = 0;                         // nodes of all dense boxes
+    uint32_t dense_max_tiles = 0;                     // collide tiles of the largest dense box
     uint64_t tiles_sparse = 0, beads_sparse = 0;      // collide tiles (first in tile order) and beads of the other boxes
     uint64_t pop_elems = 0, total_tiles = 0, total_beads = 0, total_nodes = 0;
     size_t st_popA = 0, st_popB = 0, st_x = 0, st_v = 0, st_f = 0, st_fc = 0, state_bytes = 0;
     size_t sc_ctrl = 0, sc_boxes = 0, sc_ccs = 0, sc_tilebox = 0, sc_couple = 0, sc_imp = 0, sc_claim = 0,
            sc_touched = 0, sc_tcnt = 0, sc_beadbox = 0, sc_nlcnt = 0, sc_nlidx = 0, sc_nlx0 = 0,
            sc_part = 0, sc_stat = 0, sc_chain = 0, sc_vhist = 0, sc_nlreb = 0, sc_biglist = 0, sc_alllist = 0,
-           sc_nearu = 0, sc_nearc = 0, sc_subrec = 0, scratch_bytes = 0;
+           sc_nearu = 0, sc_nearc = 0, sc_subrec = 0, sc_field = 0, scratch_bytes = 0;
     int max_N = 0;         // largest chain taking the one-workgroup path
     std::vector<int32_t> big_list;                    // boxes whose chain takes the 1024-thread kernel
     int big_max_n = 0, big_max_sub = 0;              // largest chain and most substeps among them
@@ -105,7 +108,13 @@ Layout make_layout(const lb_box_desc* b, int32_t n, int32_t prec, int32_t hist)
         // cover a quarter of the box or more: re-colliding its nodes in a
         // fix-up would cost more than colliding the box after the coupling
         Lo.dense.push_back(b[i].n_beads > BIG_CHAIN && 32 * (uint64_t)b[i].n_beads >= V ? 1 : 0);
-        if (!Lo.dense.back()) Lo.beads_sparse += (uint64_t)b[i].n_beads;
+        Lo.field_off.push_back(Lo.field_nodes);
+        if (Lo.dense.back()) {
+            Lo.field_nodes += V;
+            Lo.dense_max_tiles = std::max(Lo.dense_max_tiles, (uint32_t)((V + 255) / 256));
+        } else {
+            Lo.beads_sparse += (uint64_t)b[i].n_beads;
+        }
         Lo.bead_off.push_back(beads);
         beads += b[i].n_beads;
         Lo.node_off.push_back(nodes);
@@ -186,6 +195,7 @@ Layout make_layout(const lb_box_desc* b, int32_t n, int32_t prec, int32_t hist)
         Lo.sc_nearu = o; o = align256(o + nbig * 27 * 3 * Lo.esz);
         Lo.sc_nearc = o; o = align256(o + nbig * 4 * sizeof(int32_t));
         Lo.sc_subrec = o; o = align256(o + (uint64_t)std::max(Lo.big_max_sub, 1) * nbig * 8 * sizeof(double));
+        Lo.sc_field = o; o = align256(o + std::max<uint64_t>(Lo.field_nodes, 1) * 3 * Lo.esz);
     }
     Lo.scratch_bytes = o;
     return Lo;
@@ -424,6 +434,7 @@ lb_status lb_init(const lb_box_desc* boxes, int32_t n_boxes, int32_t precision, 
         b.chain_len = d.chain_len > 0 ? d.chain_len : std::max(d.n_beads, 1);
         b.dense = lo.dense[i];
         b.pad_ = 0;
+        b.field_off = lo.field_off[i];
         b.rho0 = d.rho0; b.gam_b = 1 - d.omega_bulk; b.gam_s = 1 - d.omega_shear; b.gam_g = 1 - d.omega_ghost;
         b.mu = 3.0 * d.kT * d.tau_lb * d.tau_lb;
         b.tau_lb = d.tau_lb; b.dt = d.md_dt; b.mass = d.bead_mass; b.zeta = d.zeta; b.k_fene = d.k_fene;
@@ -503,6 +514,8 @@ lb_status lb_init(const lb_box_desc* boxes, int32_t n_boxes, int32_t precision, 
     c.nl_cap = NL_CAP;
     c.near_u = sc(lo.sc_nearu);
     c.near_c = (int4*)sc(lo.sc_nearc);
+    c.field = sc(lo.sc_field);
+    c.dense_max_tiles = lo.dense_max_tiles;
     c.sub_rec = (double*)sc(lo.sc_subrec);
     c.vhist = hist_steps > 0 ? (double*)sc(lo.sc_vhist) : nullptr;
     c.hist_len = hist_steps > 0 ? hist_steps : 1;
