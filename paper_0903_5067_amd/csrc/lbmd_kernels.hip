@@ -11,7 +11,8 @@
 //                 atomic adds that nothing waits on (order-independent, hence
 //                 bitwise reproducible); each bead lists the nodes it touched.
 //   k_collide     fused stream + collide of every node, no impulse
-//                 (Sec. II.B, LB equation), thread per node, SoA planes.
+//                 (Sec. II.B, LB equation), thread per node; populations in
+//                 1024-node tiles of 19 planes each (pop_at).
 //                 Pull form: a buffer holds post-collision populations p,
 //                 the pre-collision population of node r is n_i(r) =
 //                 p_i(r - c_i); reads are gathered, writes aligned and
@@ -23,6 +24,10 @@
 //                 records turned into node impulses
 //   k_fixup       re-collides the nodes the beads touched, with their
 //                 impulse, and overwrites their outputs
+//   k_node_field, k_collide_forced
+//                 boxes whose beads cover much of the box: node velocities
+//                 once per step for the beads' tables, and a collide after
+//                 the coupling that takes the node impulses itself
 //   k_stats*      FP64 conserved sums, mode variances, negative-population
 //                 count; k_chain_obs: centre of mass, R_g^2, R_e^2 (Sec. III.A)
 #include "lbmd_device.hpp"
@@ -449,10 +454,11 @@ __global__ __launch_bounds__(MAXT) void k_couple(const BoxDev* __restrict__ boxe
 //   k_near_nodes  every bead's 3x3x3 nodes around its nearest node: the node
 //                 velocities (MD units), one thread per (bead, node), so all
 //                 the population loads of the stage go out in one wave;
-//   k_chain_wg    one workgroup of up to 1024 threads per chain, one thread
+//   k_chain_wg    one workgroup of up to 1024 threads per box, one thread
 //                 per bead, every MD substep in one launch.  Positions,
-//                 neighbour lists and the positions they were built at live
-//                 in LDS (144 KB); each bead's stencil velocities in
+//                 neighbour lists, the positions they were built at and the
+//                 cell buckets of the list build live in LDS (150 KB); each
+//                 bead's stencil velocities in
 //                 registers, refilled from the 3x3x3 table when the bead
 //                 changes cell.  Per substep each bead writes one record
 //                 (fractions, coupling force, base cell) instead of handing

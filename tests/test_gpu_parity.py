@@ -417,18 +417,21 @@ def _left_table(x_start, x_end, L):
 
 
 @pytest.mark.parametrize("prec", [FP64, FP32])
-def test_big_chain_beads_leaving_their_node_table(orc, prec):
+@pytest.mark.parametrize("L", [14, 40])
+def test_big_chain_beads_leaving_their_node_table(orc, prec, L):
     """Hot beads (kT = 1, LB step 0.25, no fluid noise, weak friction) move
     past the 3x3x3 node table built at the start of their LB step, so the
     chain kernel reads those stencils from the populations: 12 steps against
-    the oracle.  In the oracle a perturbation of 1e-14 in one coordinate grows
-    over these steps to ~6e-13 in positions, ~4e-12 in velocities and ~3e-14
-    in populations (~1e-12 of w_i rho0), so the FP64 bars are 1e-10 on all
-    three (about 100 x that amplification)."""
-    say("big chain, fast beads", prec)
-    p = params(L=14, N=300, kT=1.0, therm=0, md_dt=0.01, md_substeps=25, tau_lb=0.25, zeta=1.0,
+    the oracle.  In the 14^3 box the beads cover the box densely (its collide
+    follows the coupling); in the 40^3 box the collide overlaps the chain and
+    the fix-up re-collides the nodes the beads touched outside their tables.
+    In the oracle a perturbation of 1e-14 in one coordinate grows over these
+    steps to ~6e-13 in positions, ~4e-12 in velocities and ~3e-14 in
+    populations (~1e-12 of w_i rho0), so the FP64 bars are 1e-10 on all three
+    (about 100 x that amplification)."""
+    say("big chain, fast beads", prec, L)
+    p = params(L=L, N=300, kT=1.0, therm=0, md_dt=0.01, md_substeps=25, tau_lb=0.25, zeta=1.0,
                k_fene=7.0, r0_fene=2.0, seed=3, box_id=1)
-    L = int(p["L"])
     x0 = chain(p)
     n0 = initial_pops(orc, p)
     s = gpu_system([p], prec, xs=[x0])
