@@ -302,8 +302,12 @@ def precision_study(preset, ref, long_steps):
         e_o = _obs_errors(ob, ref["obs"])
         e_o["pop_rel_max"] = float(f"{err:.3e}")
         res[f"{name}_vs_oracle"] = e_o
-        s.step(long_steps - s_orc)
+        t_long, _ = time_steps(s, long_steps - s_orc, 0)
         obs_short[name + "_long"] = s.observables()[0]
+        t_k = time_collide(s, 100)
+        res[f"{name}_step_mlups"] = round(nodes * (long_steps - s_orc) / t_long / 1e6, 1)
+        res[f"{name}_collide_us"] = round(t_k * 1e6, 1)
+        res[f"{name}_collide_gbs"] = round(BYTES_PER_NODE[prec] * nodes / t_k / 1e9, 1)
         s.close()
         del s
         torch.cuda.empty_cache()
