@@ -896,6 +896,7 @@ __global__ __launch_bounds__(256) void k_spread(const BoxDev* __restrict__ boxes
                                                 Ctrl* __restrict__ ctrl)
 {
     const BoxDev& bx = boxes[list[blockIdx.y]];
+    if (bx.dense) return;   // binned and gathered instead (k_bin_runs, k_gather_imp)
     const int N = bx.N, L = bx.L;
     const int tid = (int)(blockIdx.x * blockDim.x + threadIdx.x);
     if (tid >= N * 8) return;
@@ -938,6 +939,137 @@ __global__ __launch_bounds__(256) void k_spread(const BoxDev* __restrict__ boxes
             atomicAdd(imp + 3 * (uint64_t)cur + c, (unsigned long long)(long long)llrint(q * IMP_SCALE));
         }
     }
+    if (hb) atomicOr(&ctrl->health, hb);
+}
+
+// Dense boxes hand their impulses over without atomics.  A stencil run is a
+// maximal range of substeps in which a bead keeps one base node; k_spread
+// accumulates each (run, corner) in FP64 and rounds it to fixed point once.
+// k_bin_runs sorts every bead's runs by base node (counting sort in LDS, one
+// workgroup per box); k_gather_imp then gives each node the sum over the runs
+// whose stencil holds it, with k_spread's arithmetic per (run, corner).  The
+// fixed-point sums do not depend on order, so the field equals the one the
+// atomics would build.
+constexpr uint32_t DENSE_MAXV = 32768;   // a dense box has at most 32 N <= 32768 nodes
+__global__ __launch_bounds__(WG_MAXB) void k_bin_runs(const BoxDev* __restrict__ boxes,
+                                                      const int32_t* __restrict__ list, ChainArgs ca,
+                                                      const double* __restrict__ rec,
+                                                      uint32_t* __restrict__ bin_start, uint32_t* __restrict__ items)
+{
+    __shared__ uint32_t cnt[DENSE_MAXV];        // runs per base node, then the placement cursor
+    __shared__ uint32_t wsum[WG_MAXB / 64];
+    const BoxDev& bx = boxes[list[blockIdx.x]];
+    if (!bx.dense) return;
+    const int N = bx.N, S = bx.substeps, L = bx.L;
+    const uint32_t V = (uint32_t)L * L * L;
+    const int b = (int)threadIdx.x;
+    const bool act = b < N;
+    const uint64_t g = bx.bead_off + (uint64_t)(act ? b : 0);
+    auto base_at = [&](int s) {
+        return (uint32_t)rec[((uint64_t)s * ca.total_beads + g) * REC + 6];
+    };
+    for (uint32_t i = (uint32_t)b; i < V; i += WG_MAXB) cnt[i] = 0u;
+    __syncthreads();
+    if (act) {
+        uint32_t cur = 0xffffffffu;
+        for (int s = 0; s < S; ++s) {
+            const uint32_t base = base_at(s);
+            if (base != cur) { atomicAdd(&cnt[base], 1u); cur = base; }
+        }
+    }
+    __syncthreads();
+    // exclusive prefix sum over the V counts: a chunk of C per thread, a
+    // scan per wave of the chunk totals, then the totals of the waves before
+    const uint32_t C = (V + WG_MAXB - 1) / WG_MAXB;
+    const uint32_t i0 = (uint32_t)b * C < V ? (uint32_t)b * C : V, i1 = i0 + C < V ? i0 + C : V;
+    uint32_t tot = 0;
+    for (uint32_t i = i0; i < i1; ++i) tot += cnt[i];
+    uint32_t inc = tot;
+    for (int o = 1; o < 64; o <<= 1) {
+        const uint32_t t = __shfl_up(inc, o, 64);
+        if ((b & 63) >= o) inc += t;
+    }
+    if ((b & 63) == 63) wsum[b >> 6] = inc;
+    __syncthreads();
+    uint32_t run = inc - tot;
+    for (int w = 0; w < (b >> 6); ++w) run += wsum[w];
+    uint32_t* bs = bin_start + bx.bin_off;
+    for (uint32_t i = i0; i < i1; ++i) {
+        const uint32_t c = cnt[i];
+        bs[i] = run;
+        cnt[i] = run;
+        run += c;
+    }
+    if (b == WG_MAXB - 1) bs[V] = run;
+    __syncthreads();
+    if (act) {
+        uint32_t cur = 0xffffffffu;
+        int s0 = 0;
+        for (int s = 0; s <= S; ++s) {
+            const uint32_t base = s < S ? base_at(s) : 0xffffffffu;
+            if (base != cur) {
+                if (cur != 0xffffffffu) {
+                    const uint32_t slot = atomicAdd(&cnt[cur], 1u);
+                    items[bx.item_off + slot] = ((uint32_t)b << 16) | ((uint32_t)s0 << 8) | (uint32_t)(s - 1);
+                }
+                cur = base;
+                s0 = s;
+            }
+        }
+    }
+}
+
+__global__ __launch_bounds__(256) void k_gather_imp(const BoxDev* __restrict__ boxes,
+                                                    const int32_t* __restrict__ list, ChainArgs ca,
+                                                    const double* __restrict__ rec,
+                                                    const uint32_t* __restrict__ bin_start,
+                                                    const uint32_t* __restrict__ items, Ctrl* __restrict__ ctrl)
+{
+    const BoxDev& bx = boxes[list[blockIdx.y]];
+    if (!bx.dense) return;
+    const int L = bx.L;
+    const uint32_t V = (uint32_t)L * L * L;
+    const uint32_t r = blockIdx.x * 256u + threadIdx.x;
+    if (r >= V) return;
+    const int x = (int)(r % (uint32_t)L), y = (int)((r / (uint32_t)L) % (uint32_t)L), z = (int)(r / ((uint32_t)L * L));
+    const double dt = bx.dt, tau = bx.tau_lb;
+    const uint32_t* bs = bin_start + bx.bin_off;
+    // the bins of the 8 base nodes whose corner k is this node: all bounds
+    // are loaded before any is used
+    uint32_t e0[8], e1[8];
+#pragma unroll
+    for (int k = 0; k < 8; ++k) {
+        const uint32_t base = node_of(x - (k & 1), y - ((k >> 1) & 1), z - ((k >> 2) & 1), L);
+        e0[k] = bs[base];
+        e1[k] = bs[base + 1];
+    }
+    unsigned long long sum[3] = {0ull, 0ull, 0ull};
+    uint32_t hb = 0;
+#pragma unroll
+    for (int k = 0; k < 8; ++k) {
+        const int ox = k & 1, oy = (k >> 1) & 1, oz = (k >> 2) & 1;
+        for (uint32_t e = e0[k]; e < e1[k]; ++e) {
+            const uint32_t it = items[bx.item_off + e];
+            const uint64_t g = bx.bead_off + (it >> 16);
+            const int s1 = (int)(it & 255u);
+            double acc[3] = {0.0, 0.0, 0.0};
+            for (int s = (int)((it >> 8) & 255u); s <= s1; ++s) {
+                const double* rr = rec + ((uint64_t)s * ca.total_beads + g) * REC;
+                const double wk = (ox ? rr[0] : 1.0 - rr[0]) * (oy ? rr[1] : 1.0 - rr[1]) * (oz ? rr[2] : 1.0 - rr[2]);
+                acc[0] -= wk * rr[3] * dt;
+                acc[1] -= wk * rr[4] * dt;
+                acc[2] -= wk * rr[5] * dt;
+            }
+#pragma unroll
+            for (int c = 0; c < 3; ++c) {
+                double q = acc[c] * tau;
+                if (!(fabs(q) < IMP_MAX)) { hb |= H_FIXED; q = 0.0; }
+                sum[c] += (unsigned long long)(long long)llrint(q * IMP_SCALE);
+            }
+        }
+    }
+    unsigned long long* dst = ca.imp + 3 * (bx.node_off + r);
+    dst[0] = sum[0]; dst[1] = sum[1]; dst[2] = sum[2];
     if (hb) atomicOr(&ctrl->health, hb);
 }
 
@@ -1255,8 +1387,15 @@ hipError_t launch_couple_big(const LaunchCtx& c, const void* A, const int32_t* l
     }
     hipLaunchKernelGGL(k_chain_wg<R>, dim3(n_list), dim3(WG_MAXB), 0, c.stream, c.boxes, list, (const R*)A, ca,
                        (const R*)c.near_u, (const int4*)c.near_c, c.sub_rec, c.ctrl, s_off);
-    hipLaunchKernelGGL(k_spread, dim3((max_n * 8 + 255) / 256, n_list), dim3(256), 0, c.stream, c.boxes, list, ca,
-                       (const double*)c.sub_rec, c.ctrl);
+    if (c.big_sparse)
+        hipLaunchKernelGGL(k_spread, dim3((max_n * 8 + 255) / 256, n_list), dim3(256), 0, c.stream, c.boxes, list,
+                           ca, (const double*)c.sub_rec, c.ctrl);
+    if (c.dense_max_tiles) {
+        hipLaunchKernelGGL(k_bin_runs, dim3(n_list), dim3(WG_MAXB), 0, c.stream, c.boxes, list, ca,
+                           (const double*)c.sub_rec, c.bin_start, c.items);
+        hipLaunchKernelGGL(k_gather_imp, dim3(c.dense_max_tiles, n_list), dim3(256), 0, c.stream, c.boxes, list, ca,
+                           (const double*)c.sub_rec, (const uint32_t*)c.bin_start, (const uint32_t*)c.items, c.ctrl);
+    }
     return hipGetLastError();
 }
 

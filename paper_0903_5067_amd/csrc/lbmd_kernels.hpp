@@ -36,6 +36,9 @@ struct LaunchCtx {
     double* sub_rec;               // [most substeps][total beads][8] per-substep records
     void* field;                   // dense boxes: node velocities (MD units, storage precision) [nodes][3]
     uint32_t dense_max_tiles;      // collide tiles of the largest dense box (0: none)
+    int big_sparse;                // boxes on the 1024-thread path that are not dense (k_spread's boxes)
+    uint32_t* bin_start;           // dense boxes: per base node, first binned stencil run [L^3 + 1]
+    uint32_t* items;               // dense boxes: stencil runs (bead << 16 | first substep << 8 | last)
 };
 
 template <typename R>

@@ -44,6 +44,8 @@ struct Layout {
     std::vector<uint8_t> dense;                       // per box: collide after the coupling, no fix-up
     std::vector<uint64_t> field_off;                  // per box: first node in the velocity field (dense boxes)
     uint64_t field_nodes = 0;                         // nodes of all dense boxes
+    std::vector<uint64_t> bin_off, item_off;          // per box: its run bins and binned runs (dense boxes)
+    uint64_t bin_entries = 0, item_entries = 0;
     uint32_t dense_max_tiles = 0;                     // collide tiles of the largest dense box
     uint64_t tiles_sparse = 0, beads_sparse = 0;      // collide tiles (first in tile order) and beads of the other boxes
     uint64_t pop_elems = 0, total_tiles = 0, total_beads = 0, total_nodes = 0;
@@ -51,7 +53,8 @@ struct Layout {
     size_t sc_ctrl = 0, sc_boxes = 0, sc_ccs = 0, sc_tilebox = 0, sc_couple = 0, sc_imp = 0, sc_claim = 0,
            sc_touched = 0, sc_tcnt = 0, sc_beadbox = 0, sc_nlcnt = 0, sc_nlidx = 0, sc_nlx0 = 0,
            sc_part = 0, sc_stat = 0, sc_chain = 0, sc_vhist = 0, sc_nlreb = 0, sc_biglist = 0, sc_alllist = 0,
-           sc_nearu = 0, sc_nearc = 0, sc_subrec = 0, sc_field = 0, scratch_bytes = 0;
+           sc_nearu = 0, sc_nearc = 0, sc_subrec = 0, sc_field = 0, sc_binstart = 0, sc_items = 0,
+           scratch_bytes = 0;
     int max_N = 0;         // largest chain taking the one-workgroup path
     std::vector<int32_t> big_list;                    // boxes whose chain takes the 1024-thread kernel
     int big_max_n = 0, big_max_sub = 0;              // largest chain and most substeps among them
@@ -107,10 +110,15 @@ Layout make_layout(const lb_box_desc* b, int32_t n, int32_t prec, int32_t hist)
         // a chain on the workgroup path whose stencils (8 nodes per bead)
         // cover a quarter of the box or more: re-colliding its nodes in a
         // fix-up would cost more than colliding the box after the coupling
-        Lo.dense.push_back(b[i].n_beads > BIG_CHAIN && 32 * (uint64_t)b[i].n_beads >= V ? 1 : 0);
+        Lo.dense.push_back(b[i].n_beads > BIG_CHAIN && 32 * (uint64_t)b[i].n_beads >= V && b[i].md_substeps <= 256
+                               ? 1 : 0);
         Lo.field_off.push_back(Lo.field_nodes);
+        Lo.bin_off.push_back(Lo.bin_entries);
+        Lo.item_off.push_back(Lo.item_entries);
         if (Lo.dense.back()) {
             Lo.field_nodes += V;
+            Lo.bin_entries += V + 1;
+            Lo.item_entries += (uint64_t)b[i].n_beads * (uint64_t)b[i].md_substeps;
             Lo.dense_max_tiles = std::max(Lo.dense_max_tiles, (uint32_t)((V + 255) / 256));
         } else {
             Lo.beads_sparse += (uint64_t)b[i].n_beads;
@@ -196,6 +204,8 @@ Layout make_layout(const lb_box_desc* b, int32_t n, int32_t prec, int32_t hist)
         Lo.sc_nearc = o; o = align256(o + nbig * 4 * sizeof(int32_t));
         Lo.sc_subrec = o; o = align256(o + (uint64_t)std::max(Lo.big_max_sub, 1) * nbig * 8 * sizeof(double));
         Lo.sc_field = o; o = align256(o + std::max<uint64_t>(Lo.field_nodes, 1) * 3 * Lo.esz);
+        Lo.sc_binstart = o; o = align256(o + std::max<uint64_t>(Lo.bin_entries, 1) * sizeof(uint32_t));
+        Lo.sc_items = o; o = align256(o + std::max<uint64_t>(Lo.item_entries, 1) * sizeof(uint32_t));
     }
     Lo.scratch_bytes = o;
     return Lo;
@@ -435,6 +445,8 @@ lb_status lb_init(const lb_box_desc* boxes, int32_t n_boxes, int32_t precision, 
         b.dense = lo.dense[i];
         b.pad_ = 0;
         b.field_off = lo.field_off[i];
+        b.bin_off = lo.bin_off[i];
+        b.item_off = lo.item_off[i];
         b.rho0 = d.rho0; b.gam_b = 1 - d.omega_bulk; b.gam_s = 1 - d.omega_shear; b.gam_g = 1 - d.omega_ghost;
         b.mu = 3.0 * d.kT * d.tau_lb * d.tau_lb;
         b.tau_lb = d.tau_lb; b.dt = d.md_dt; b.mass = d.bead_mass; b.zeta = d.zeta; b.k_fene = d.k_fene;
@@ -516,6 +528,10 @@ lb_status lb_init(const lb_box_desc* boxes, int32_t n_boxes, int32_t precision, 
     c.near_c = (int4*)sc(lo.sc_nearc);
     c.field = sc(lo.sc_field);
     c.dense_max_tiles = lo.dense_max_tiles;
+    c.big_sparse = 0;
+    for (int i : lo.big_list) c.big_sparse += lo.dense[i] ? 0 : 1;
+    c.bin_start = (uint32_t*)sc(lo.sc_binstart);
+    c.items = (uint32_t*)sc(lo.sc_items);
     c.sub_rec = (double*)sc(lo.sc_subrec);
     c.vhist = hist_steps > 0 ? (double*)sc(lo.sc_vhist) : nullptr;
     c.hist_len = hist_steps > 0 ? hist_steps : 1;
