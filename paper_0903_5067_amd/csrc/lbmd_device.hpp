@@ -21,7 +21,7 @@ struct BoxDev {
     uint64_t bead_off;   // first global bead index
     uint64_t field_off;  // dense boxes: first node of the box in the node-velocity field
     uint64_t bin_off;    // dense boxes: first entry of the box's run bins (L^3 + 1 entries)
-    uint64_t item_off;   // dense boxes: first slot of the box's binned stencil runs (N x substeps)
+    uint64_t item_off;   // dense boxes: first slot of the box's stencil runs (at most N x substeps)
     uint32_t tile_begin; // first collide tile of the box
     uint32_t n_tiles;
     int32_t therm;       // 0 none, 1 stress modes, 2 all non-conserved modes

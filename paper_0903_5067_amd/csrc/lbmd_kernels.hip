@@ -945,16 +945,18 @@ __global__ __launch_bounds__(256) void k_spread(const BoxDev* __restrict__ boxes
 // Dense boxes hand their impulses over without atomics.  A stencil run is a
 // maximal range of substeps in which a bead keeps one base node; k_spread
 // accumulates each (run, corner) in FP64 and rounds it to fixed point once.
-// k_bin_runs sorts every bead's runs by base node (counting sort in LDS, one
-// workgroup per box); k_gather_imp then gives each node the sum over the runs
-// whose stencil holds it, with k_spread's arithmetic per (run, corner).  The
-// fixed-point sums do not depend on order, so the field equals the one the
-// atomics would build.
+// Here k_bin_runs gives every run a slot, the slots sorted by base node
+// (counting sort in LDS, one workgroup per box); k_run_impulse, one thread
+// per (bead, corner) like k_spread, stores each (run, corner) value in its
+// run's slot; k_gather_imp gives each node the sum over the runs whose
+// stencil holds it.  The fixed-point sums do not depend on order, so the
+// field equals the one the atomics would build.
 constexpr uint32_t DENSE_MAXV = 32768;   // a dense box has at most 32 N <= 32768 nodes
 __global__ __launch_bounds__(WG_MAXB) void k_bin_runs(const BoxDev* __restrict__ boxes,
                                                       const int32_t* __restrict__ list, ChainArgs ca,
                                                       const double* __restrict__ rec,
-                                                      uint32_t* __restrict__ bin_start, uint32_t* __restrict__ items)
+                                                      uint32_t* __restrict__ bin_start,
+                                                      uint32_t* __restrict__ slot_of)
 {
     __shared__ uint32_t cnt[DENSE_MAXV];        // runs per base node, then the placement cursor
     __shared__ uint32_t wsum[WG_MAXB / 64];
@@ -1003,27 +1005,72 @@ __global__ __launch_bounds__(WG_MAXB) void k_bin_runs(const BoxDev* __restrict__
     if (b == WG_MAXB - 1) bs[V] = run;
     __syncthreads();
     if (act) {
+        // slot of the j-th run of bead b
         uint32_t cur = 0xffffffffu;
-        int s0 = 0;
-        for (int s = 0; s <= S; ++s) {
-            const uint32_t base = s < S ? base_at(s) : 0xffffffffu;
+        int j = 0;
+        for (int s = 0; s < S; ++s) {
+            const uint32_t base = base_at(s);
             if (base != cur) {
-                if (cur != 0xffffffffu) {
-                    const uint32_t slot = atomicAdd(&cnt[cur], 1u);
-                    items[bx.item_off + slot] = ((uint32_t)b << 16) | ((uint32_t)s0 << 8) | (uint32_t)(s - 1);
-                }
+                slot_of[bx.item_off + (uint64_t)b * S + j] = atomicAdd(&cnt[base], 1u);
+                ++j;
                 cur = base;
-                s0 = s;
             }
         }
     }
 }
 
+// one thread per (bead, corner): k_spread's accumulation, stored in the
+// run's slot instead of added to the field
+__global__ __launch_bounds__(256) void k_run_impulse(const BoxDev* __restrict__ boxes,
+                                                     const int32_t* __restrict__ list, ChainArgs ca,
+                                                     const double* __restrict__ rec,
+                                                     const uint32_t* __restrict__ slot_of,
+                                                     unsigned long long* __restrict__ runimp,
+                                                     Ctrl* __restrict__ ctrl)
+{
+    const BoxDev& bx = boxes[list[blockIdx.y]];
+    if (!bx.dense) return;
+    const int N = bx.N, S = bx.substeps;
+    const int tid = (int)(blockIdx.x * blockDim.x + threadIdx.x);
+    if (tid >= N * 8) return;
+    const int b = tid >> 3, k = tid & 7;
+    const uint64_t g = bx.bead_off + (uint64_t)b;
+    const double dt = bx.dt, tau = bx.tau_lb;
+    uint32_t hb = 0;
+    double acc[3] = {0, 0, 0};
+    uint32_t cur = 0xffffffffu;
+    int j = 0;
+    auto store = [&]() {
+        unsigned long long* o = runimp + (bx.item_off + slot_of[bx.item_off + (uint64_t)b * S + j]) * 24 + 3 * k;
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            double q = acc[c] * tau;
+            if (!(fabs(q) < IMP_MAX)) { hb |= H_FIXED; q = 0.0; }
+            o[c] = (unsigned long long)(long long)llrint(q * IMP_SCALE);
+        }
+    };
+    for (int s = 0; s < S; ++s) {
+        const double* r = rec + ((uint64_t)s * ca.total_beads + g) * REC;
+        const uint32_t base = (uint32_t)r[6];
+        if (base != cur) {
+            if (cur != 0xffffffffu) { store(); ++j; }
+            cur = base;
+            acc[0] = acc[1] = acc[2] = 0.0;
+        }
+        const double wk = ((k & 1) ? r[0] : 1.0 - r[0]) * (((k >> 1) & 1) ? r[1] : 1.0 - r[1]) *
+                          (((k >> 2) & 1) ? r[2] : 1.0 - r[2]);
+        acc[0] -= wk * r[3] * dt;
+        acc[1] -= wk * r[4] * dt;
+        acc[2] -= wk * r[5] * dt;
+    }
+    if (cur != 0xffffffffu) store();
+    if (hb) atomicOr(&ctrl->health, hb);
+}
+
 __global__ __launch_bounds__(256) void k_gather_imp(const BoxDev* __restrict__ boxes,
                                                     const int32_t* __restrict__ list, ChainArgs ca,
-                                                    const double* __restrict__ rec,
                                                     const uint32_t* __restrict__ bin_start,
-                                                    const uint32_t* __restrict__ items, Ctrl* __restrict__ ctrl)
+                                                    const unsigned long long* __restrict__ runimp)
 {
     const BoxDev& bx = boxes[list[blockIdx.y]];
     if (!bx.dense) return;
@@ -1032,7 +1079,6 @@ __global__ __launch_bounds__(256) void k_gather_imp(const BoxDev* __restrict__ b
     const uint32_t r = blockIdx.x * 256u + threadIdx.x;
     if (r >= V) return;
     const int x = (int)(r % (uint32_t)L), y = (int)((r / (uint32_t)L) % (uint32_t)L), z = (int)(r / ((uint32_t)L * L));
-    const double dt = bx.dt, tau = bx.tau_lb;
     const uint32_t* bs = bin_start + bx.bin_off;
     // the bins of the 8 base nodes whose corner k is this node: all bounds
     // are loaded before any is used
@@ -1044,33 +1090,14 @@ __global__ __launch_bounds__(256) void k_gather_imp(const BoxDev* __restrict__ b
         e1[k] = bs[base + 1];
     }
     unsigned long long sum[3] = {0ull, 0ull, 0ull};
-    uint32_t hb = 0;
 #pragma unroll
-    for (int k = 0; k < 8; ++k) {
-        const int ox = k & 1, oy = (k >> 1) & 1, oz = (k >> 2) & 1;
+    for (int k = 0; k < 8; ++k)
         for (uint32_t e = e0[k]; e < e1[k]; ++e) {
-            const uint32_t it = items[bx.item_off + e];
-            const uint64_t g = bx.bead_off + (it >> 16);
-            const int s1 = (int)(it & 255u);
-            double acc[3] = {0.0, 0.0, 0.0};
-            for (int s = (int)((it >> 8) & 255u); s <= s1; ++s) {
-                const double* rr = rec + ((uint64_t)s * ca.total_beads + g) * REC;
-                const double wk = (ox ? rr[0] : 1.0 - rr[0]) * (oy ? rr[1] : 1.0 - rr[1]) * (oz ? rr[2] : 1.0 - rr[2]);
-                acc[0] -= wk * rr[3] * dt;
-                acc[1] -= wk * rr[4] * dt;
-                acc[2] -= wk * rr[5] * dt;
-            }
-#pragma unroll
-            for (int c = 0; c < 3; ++c) {
-                double q = acc[c] * tau;
-                if (!(fabs(q) < IMP_MAX)) { hb |= H_FIXED; q = 0.0; }
-                sum[c] += (unsigned long long)(long long)llrint(q * IMP_SCALE);
-            }
+            const unsigned long long* q = runimp + (bx.item_off + e) * 24 + 3 * k;
+            sum[0] += q[0]; sum[1] += q[1]; sum[2] += q[2];
         }
-    }
     unsigned long long* dst = ca.imp + 3 * (bx.node_off + r);
     dst[0] = sum[0]; dst[1] = sum[1]; dst[2] = sum[2];
-    if (hb) atomicOr(&ctrl->health, hb);
 }
 
 // ---------------------------------------------------------------- fixup
@@ -1392,9 +1419,11 @@ hipError_t launch_couple_big(const LaunchCtx& c, const void* A, const int32_t* l
                            ca, (const double*)c.sub_rec, c.ctrl);
     if (c.dense_max_tiles) {
         hipLaunchKernelGGL(k_bin_runs, dim3(n_list), dim3(WG_MAXB), 0, c.stream, c.boxes, list, ca,
-                           (const double*)c.sub_rec, c.bin_start, c.items);
+                           (const double*)c.sub_rec, c.bin_start, c.slot_of);
+        hipLaunchKernelGGL(k_run_impulse, dim3((max_n * 8 + 255) / 256, n_list), dim3(256), 0, c.stream, c.boxes,
+                           list, ca, (const double*)c.sub_rec, (const uint32_t*)c.slot_of, c.runimp, c.ctrl);
         hipLaunchKernelGGL(k_gather_imp, dim3(c.dense_max_tiles, n_list), dim3(256), 0, c.stream, c.boxes, list, ca,
-                           (const double*)c.sub_rec, (const uint32_t*)c.bin_start, (const uint32_t*)c.items, c.ctrl);
+                           (const uint32_t*)c.bin_start, (const unsigned long long*)c.runimp);
     }
     return hipGetLastError();
 }

@@ -38,7 +38,8 @@ struct LaunchCtx {
     uint32_t dense_max_tiles;      // collide tiles of the largest dense box (0: none)
     int big_sparse;                // boxes on the 1024-thread path that are not dense (k_spread's boxes)
     uint32_t* bin_start;           // dense boxes: per base node, first binned stencil run [L^3 + 1]
-    uint32_t* items;               // dense boxes: stencil runs (bead << 16 | first substep << 8 | last)
+    unsigned long long* runimp;    // dense boxes: per stencil run, the fixed-point impulse to its 8 corners x 3
+    uint32_t* slot_of;             // dense boxes: per bead and run, the run's slot [N x substeps]
 };
 
 template <typename R>

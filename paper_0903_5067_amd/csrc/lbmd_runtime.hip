@@ -53,7 +53,7 @@ struct Layout {
     size_t sc_ctrl = 0, sc_boxes = 0, sc_ccs = 0, sc_tilebox = 0, sc_couple = 0, sc_imp = 0, sc_claim = 0,
            sc_touched = 0, sc_tcnt = 0, sc_beadbox = 0, sc_nlcnt = 0, sc_nlidx = 0, sc_nlx0 = 0,
            sc_part = 0, sc_stat = 0, sc_chain = 0, sc_vhist = 0, sc_nlreb = 0, sc_biglist = 0, sc_alllist = 0,
-           sc_nearu = 0, sc_nearc = 0, sc_subrec = 0, sc_field = 0, sc_binstart = 0, sc_items = 0,
+           sc_nearu = 0, sc_nearc = 0, sc_subrec = 0, sc_field = 0, sc_binstart = 0, sc_items = 0, sc_slotof = 0,
            scratch_bytes = 0;
     int max_N = 0;         // largest chain taking the one-workgroup path
     std::vector<int32_t> big_list;                    // boxes whose chain takes the 1024-thread kernel
@@ -110,8 +110,7 @@ Layout make_layout(const lb_box_desc* b, int32_t n, int32_t prec, int32_t hist)
         // a chain on the workgroup path whose stencils (8 nodes per bead)
         // cover a quarter of the box or more: re-colliding its nodes in a
         // fix-up would cost more than colliding the box after the coupling
-        Lo.dense.push_back(b[i].n_beads > BIG_CHAIN && 32 * (uint64_t)b[i].n_beads >= V && b[i].md_substeps <= 256
-                               ? 1 : 0);
+        Lo.dense.push_back(b[i].n_beads > BIG_CHAIN && 32 * (uint64_t)b[i].n_beads >= V ? 1 : 0);
         Lo.field_off.push_back(Lo.field_nodes);
         Lo.bin_off.push_back(Lo.bin_entries);
         Lo.item_off.push_back(Lo.item_entries);
@@ -205,7 +204,8 @@ Layout make_layout(const lb_box_desc* b, int32_t n, int32_t prec, int32_t hist)
         Lo.sc_subrec = o; o = align256(o + (uint64_t)std::max(Lo.big_max_sub, 1) * nbig * 8 * sizeof(double));
         Lo.sc_field = o; o = align256(o + std::max<uint64_t>(Lo.field_nodes, 1) * 3 * Lo.esz);
         Lo.sc_binstart = o; o = align256(o + std::max<uint64_t>(Lo.bin_entries, 1) * sizeof(uint32_t));
-        Lo.sc_items = o; o = align256(o + std::max<uint64_t>(Lo.item_entries, 1) * sizeof(uint32_t));
+        Lo.sc_items = o; o = align256(o + std::max<uint64_t>(Lo.item_entries, 1) * 24 * sizeof(unsigned long long));
+        Lo.sc_slotof = o; o = align256(o + std::max<uint64_t>(Lo.item_entries, 1) * sizeof(uint32_t));
     }
     Lo.scratch_bytes = o;
     return Lo;
@@ -531,7 +531,8 @@ lb_status lb_init(const lb_box_desc* boxes, int32_t n_boxes, int32_t precision, 
     c.big_sparse = 0;
     for (int i : lo.big_list) c.big_sparse += lo.dense[i] ? 0 : 1;
     c.bin_start = (uint32_t*)sc(lo.sc_binstart);
-    c.items = (uint32_t*)sc(lo.sc_items);
+    c.runimp = (unsigned long long*)sc(lo.sc_items);
+    c.slot_of = (uint32_t*)sc(lo.sc_slotof);
     c.sub_rec = (double*)sc(lo.sc_subrec);
     c.vhist = hist_steps > 0 ? (double*)sc(lo.sc_vhist) : nullptr;
     c.hist_len = hist_steps > 0 ? hist_steps : 1;
