@@ -428,13 +428,16 @@ def main():
         if args.graph_steps:
             sb.set_launch(batched=True, graph_steps=args.graph_steps)
         tb, _ = time_steps(sb, 500, 20)
+        cb = time_collide(sb, 100)
         sb.set_launch(batched=False)
         tp, _ = time_steps(sb, 100, 5)
         sec["batched256"] = {"boxes": len(bb), "nodes": nb, "beads": int(sum(b["N"] for b in bb)),
                              "batched_mlups": round(nb * 500 / tb / 1e6, 1),
                              "batched_pct_hbm_peak": round(100.0 * BYTES_PER_NODE[pb] * nb * 500 / tb / 1e9 / HBM_PEAK_GBS, 1),
                              "plain_per_box_mlups": round(nb * 100 / tp / 1e6, 1),
-                             "batched_over_plain": round((nb * 500 / tb) / (nb * 100 / tp), 3)}
+                             "batched_over_plain": round((nb * 500 / tb) / (nb * 100 / tp), 3),
+                             "collide_us": round(1e6 * cb, 1),
+                             "collide_gbs": round(BYTES_PER_NODE[pb] * nb / cb / 1e9, 1)}
         sb.close()
         sec["adjoint32"] = adjoint_secondary()
         sec["thermalization"] = thermalization_secondary()

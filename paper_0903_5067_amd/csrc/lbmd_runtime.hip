@@ -26,12 +26,6 @@ thread_local std::string g_err;
 
 size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 uint64_t round_up(uint64_t x, uint64_t m) { return (x + m - 1) / m * m; }
-uint32_t next_pow2(uint32_t x)
-{
-    uint32_t p = 1;
-    while (p < x) p <<= 1;
-    return p;
-}
 
 constexpr int NL_CAP = NL_SLOTS;   // neighbour-list entries per bead
 constexpr double MODE_B[19] = {1, 1. / 3, 1. / 3, 1. / 3, 2. / 3, 4. / 3, 4. / 9, 1. / 9, 1. / 9, 1. / 9,
