@@ -255,9 +255,24 @@ def cpu_baseline(preset, budget_s=20.0):
         t1 = time.perf_counter() - t0
         steps = more
     mlups = L ** 3 * steps / t1 / 1e6
-    rep = {"value": round(mlups, 3), "unit": "MLUPS", "cores": oracle.num_threads(), "kind": "oracle",
+    cores = oracle.num_threads()
+    # one more step on one thread, for the per-core rate
+    oracle.set_threads(1)
+    t0 = time.perf_counter()
+    st.run(1)
+    t_one = time.perf_counter() - t0
+    oracle.set_threads(cores)
+    model = ""
+    try:
+        with open("/proc/cpuinfo") as f:
+            model = next((l.split(":", 1)[1].strip() for l in f if l.startswith("model name")), "")
+    except OSError:
+        pass
+    rep = {"value": round(mlups, 3), "unit": "MLUPS", "cores": cores, "kind": "oracle",
            "sample": f"{steps} full LB step(s) of the {L}^3 box with its N={p['N']} chain (after 1 untimed), "
-                     f"FP64 oracle, {t1:.1f} s"}
+                     f"FP64 oracle, {t1:.1f} s",
+           "value_1core": round(L ** 3 / t_one / 1e6, 3), "sample_1core": f"1 further step on 1 thread, {t_one:.1f} s",
+           "cpu_model": model}
     oo = st.observables()
     ref = {"t": st.t, "n": st.n, "w": np.array(w),
            "obs": {"mass": oo[0], "p_fluid": oo[4:7], "p_total": oo[10:13], "com": oo[13:16], "rg2": oo[16],

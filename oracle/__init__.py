@@ -99,6 +99,7 @@ def lib():
         _lib.orc_observables.argtypes = [bp, dp, dp, dp, dp, dp]
         _lib.orc_window_tangent.argtypes = [bp, dp, dp, dp, dp, dp, ctypes.c_uint32, ctypes.c_int32, dp, dp]
         _lib.orc_num_threads.restype = ctypes.c_int
+        _lib.orc_set_threads.argtypes = [ctypes.c_int]
     return _lib
 
 
@@ -213,3 +214,7 @@ def initial_forces(box: Box, x: np.ndarray) -> np.ndarray:
 
 def num_threads() -> int:
     return int(lib().orc_num_threads())
+
+
+def set_threads(n: int) -> None:
+    lib().orc_set_threads(int(n))

@@ -89,6 +89,7 @@ void orc_tables(double* c, double* w, double* e, double* b);
 void orc_philox4x32_10(const uint32_t ctr[4], const uint32_t key[2], uint32_t out[4]);
 double orc_unit_noise(uint32_t word);
 int orc_num_threads(void);
+void orc_set_threads(int n);
 }
 
 typedef struct {
@@ -616,5 +617,15 @@ int orc_num_threads(void)
     return omp_get_max_threads();
 #else
     return 1;
+#endif
+}
+
+/* threads of the OpenMP loops from here on (n >= 1) */
+void orc_set_threads(int n)
+{
+#ifdef _OPENMP
+    if (n >= 1) omp_set_num_threads(n);
+#else
+    (void)n;
 #endif
 }
