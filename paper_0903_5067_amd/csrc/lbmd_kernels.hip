@@ -1111,7 +1111,7 @@ __global__ __launch_bounds__(256) void k_fixup(const BoxDev* __restrict__ boxes,
                                                const int32_t* __restrict__ bead_box, uint64_t bead0,
                                                uint32_t n_entries, ChainArgs ca, uint32_t* __restrict__ claim,
                                                const R* __restrict__ A, R* __restrict__ B,
-                                               Ctrl* __restrict__ ctrl, uint32_t s_off)
+                                               Ctrl* __restrict__ ctrl, uint32_t s_off, int keep_imp)
 {
     const uint32_t e = blockIdx.x * 256u + threadIdx.x;
     if (e >= n_entries) return;
@@ -1134,7 +1134,7 @@ __global__ __launch_bounds__(256) void k_fixup(const BoxDev* __restrict__ boxes,
 #pragma unroll
     for (int c = 0; c < 3; ++c) {
         fimp[c] = (R)((double)(long long)ca.imp[3 * node + c] * IMP_INV_SCALE);
-        ca.imp[3 * node + c] = 0ull;
+        if (!keep_imp) ca.imp[3 * node + c] = 0ull;
     }
     R o[19];
     const uint32_t h = collide<R>(d, o, fimp[0], fimp[1], fimp[2], cc, r, t, bx.seed, bx.box_id);
@@ -1370,7 +1370,7 @@ hipError_t launch_fixup(const LaunchCtx& c, const void* A, void* B, uint64_t bea
     const uint32_t n = (uint32_t)(n_beads * (uint64_t)c.touch_cap);
     hipLaunchKernelGGL(k_fixup<R>, dim3((n + 255) / 256), dim3(256), 0, c.stream, c.boxes,
                        (const CollideConst<R>*)c.ccs, c.bead_box, bead0, n, chain_args(c), c.claim,
-                       (const R*)A, (R*)B, c.ctrl, s_off);
+                       (const R*)A, (R*)B, c.ctrl, s_off, c.keep_imp);
     return hipGetLastError();
 }
 

@@ -852,6 +852,7 @@ namespace {
 struct WinLayout {
     size_t ck_pop, ck_beads, tape_pop, tape_imp, tape_sub, tape_beads, vh, dj, lam_a, lam_b, lam_dp, lbeads, gpart,
         gz, bytes;
+    size_t bspan;   // bytes of the state's x, v, f arrays, gaps included
     int nc;
 };
 
@@ -867,10 +868,11 @@ WinLayout win_layout(const lb_handle* h, int T, int k)
     size_t o = 0;
     w.ck_pop = o; o = align256(o + (size_t)(w.nc + 1) * popb);
     w.ck_beads = o; o = align256(o + (size_t)(w.nc + 1) * 12 * nb * sizeof(double));
-    w.tape_pop = o; o = align256(o + (size_t)k * popb);
+    w.tape_pop = o; o = align256(o + (size_t)(k + 1) * popb);
     w.tape_imp = o; o = align256(o + (size_t)k * 3 * nodes * sizeof(unsigned long long));
     w.tape_sub = o; o = align256(o + (size_t)k * smax * nb * TAPE_REC * sizeof(double));
-    w.tape_beads = o; o = align256(o + (size_t)k * 9 * nb * sizeof(double));
+    w.bspan = lo.st_fc - lo.st_x;   // x, v, f of the state, with their alignment gaps
+    w.tape_beads = o; o = align256(o + (size_t)k * w.bspan);
     w.vh = o; o = align256(o + (size_t)T * 3 * nb * sizeof(double));
     w.dj = o; o = align256(o + (size_t)T * 3 * nb * sizeof(double));
     w.lam_a = o; o = align256(o + 19 * nodes * sizeof(double));
@@ -918,27 +920,28 @@ lb_status ck_restore(lb_handle* h, char* ws, const WinLayout& w, int j, uint64_t
 
 // one step with the launches serialised on the main stream; optionally records
 // the impulse field before the fix-up consumes it and the chain's substep tape
-lb_status window_step(lb_handle* h, unsigned long long* imp_copy, double* tape)
+// One LB step of a window from populations A into B.  imp: where the node
+// impulses go (null: the library's field, consumed by the fix-up; else a
+// zeroed tape slot that keeps them); tape: substep tape (null: none); vh,
+// hist_len: ring of bead velocities after each step (null: the handle's own).
+lb_status window_step(lb_handle* h, const void* A, void* B, unsigned long long* imp, double* tape, double* vh,
+                      int hist_len)
 {
-    const void* A = h->pop(h->cur);
-    void* B = h->pop(1 - h->cur);
     const bool f64 = h->prec == LB_FP64;
     LaunchCtx c = h->ctx;
     c.tape = tape;
+    if (imp) { c.imp = imp; c.keep_imp = 1; }
+    if (vh) { c.vhist = vh; c.hist_len = hist_len; }
     const int nc = (int)h->couple_host.size();
     if (nc)
         HIPCHK(h, f64 ? launch_couple<double>(c, A, h->couple_list, nc, h->lo.couple_block, 0)
                       : launch_couple<float>(c, A, h->couple_list, nc, h->lo.couple_block, 0));
-    if (imp_copy && h->lo.total_beads)
-        HIPCHK(h, hipMemcpyAsync(imp_copy, c.imp, 3 * h->lo.total_nodes * sizeof(unsigned long long),
-                                 hipMemcpyDeviceToDevice, h->stream));
     HIPCHK(h, f64 ? launch_collide<double>(c, A, B, -1, 0, (uint32_t)h->lo.total_tiles, 0)
                   : launch_collide<float>(c, A, B, -1, 0, (uint32_t)h->lo.total_tiles, 0));
     if (h->lo.total_beads)
         HIPCHK(h, f64 ? launch_fixup<double>(c, A, B, 0, h->lo.total_beads, 0)
                       : launch_fixup<float>(c, A, B, 0, h->lo.total_beads, 0));
     HIPCHK(h, launch_advance(c, 1));
-    h->cur ^= 1;
     h->step += 1;
     return LB_OK;
 }
@@ -996,19 +999,26 @@ lb_status lb_window_forward(lb_handle* h, void* d_ws, size_t bytes, int32_t T, i
     h->win_T = T;
     h->win_k = k;
     h->win_step0 = h->step;
+    // the coupling kernel writes the bead velocities after step s into slot
+    // s mod T of the window's ring: slot (step0 + t) mod T holds step t
     for (int t = 0; t < T; ++t) {
         if (t % k == 0) {
             lb_status s = ck_save(h, ws, w, t / k);
             if (s != LB_OK) return s;
         }
-        lb_status s = window_step(h, nullptr, nullptr);
+        lb_status s = window_step(h, h->pop(h->cur), h->pop(1 - h->cur), nullptr, nullptr, (double*)(ws + w.vh), T);
         if (s != LB_OK) return s;
-        HIPCHK(h, hipMemcpyAsync(ws + w.vh + t * nb3 * sizeof(double), h->state + h->lo.st_v, nb3 * sizeof(double),
-                                 hipMemcpyDeviceToDevice, h->stream));
+        h->cur ^= 1;
     }
-    if (vhist_host)
-        HIPCHK(h, hipMemcpyAsync(vhist_host, ws + w.vh, (size_t)T * nb3 * sizeof(double), hipMemcpyDeviceToHost,
+    if (vhist_host) {
+        std::vector<double> ring((size_t)T * nb3);
+        HIPCHK(h, hipMemcpyAsync(ring.data(), ws + w.vh, ring.size() * sizeof(double), hipMemcpyDeviceToHost,
                                  h->stream));
+        HIPCHK(h, hipStreamSynchronize(h->stream));
+        const uint64_t r0 = h->win_step0 % (uint64_t)T;
+        for (int t = 0; t < T; ++t)
+            std::memcpy(vhist_host + (size_t)t * nb3, ring.data() + ((r0 + t) % T) * nb3, nb3 * sizeof(double));
+    }
     HIPCHK(h, hipStreamSynchronize(h->stream));
     h->win_ready = true;
     return LB_OK;
@@ -1063,18 +1073,19 @@ lb_status lb_window_backward(lb_handle* h, void* d_ws, size_t bytes, const doubl
         const int t0 = seg * k, t1 = std::min(T, t0 + k);
         st = ck_restore(h, ws, w, seg, h->win_step0 + t0);
         if (st != LB_OK) return st;
-        // replay the segment, recording what the reverse sweep needs
+        // replay the segment, recording what the reverse sweep needs: step j
+        // reads tape slot j and writes slot j + 1, and adds its impulses into
+        // its own zeroed impulse slot
+        HIPCHK(h, hipMemcpyAsync(ws + w.tape_pop, h->pop(h->cur), popb, hipMemcpyDeviceToDevice, h->stream));
+        HIPCHK(h, hipMemsetAsync(ws + w.tape_imp, 0, (size_t)(t1 - t0) * 3 * nodes * 8, h->stream));
         for (int t = t0; t < t1; ++t) {
             const int j = t - t0;
-            HIPCHK(h, hipMemcpyAsync(ws + w.tape_pop + j * popb, h->pop(h->cur), popb, hipMemcpyDeviceToDevice,
-                                     h->stream));
-            const size_t arrs[3] = {lo.st_x, lo.st_v, lo.st_f};
-            for (int a = 0; a < 3; ++a)
-                HIPCHK(h, hipMemcpyAsync(ws + w.tape_beads + ((size_t)j * 9 + 3 * a) * nbx * sizeof(double),
-                                         h->state + arrs[a], nb3 * sizeof(double), hipMemcpyDeviceToDevice,
-                                         h->stream));
-            st = window_step(h, (unsigned long long*)(ws + w.tape_imp + (size_t)j * 3 * nodes * 8),
-                             (double*)(ws + w.tape_sub + (size_t)j * smax * nbx * TAPE_REC * sizeof(double)));
+            HIPCHK(h, hipMemcpyAsync(ws + w.tape_beads + (size_t)j * w.bspan, h->state + lo.st_x, w.bspan,
+                                     hipMemcpyDeviceToDevice, h->stream));
+            st = window_step(h, ws + w.tape_pop + j * popb, ws + w.tape_pop + (j + 1) * popb,
+                             (unsigned long long*)(ws + w.tape_imp + (size_t)j * 3 * nodes * 8),
+                             (double*)(ws + w.tape_sub + (size_t)j * smax * nbx * TAPE_REC * sizeof(double)),
+                             nullptr, 0);
             if (st != LB_OK) return st;
         }
         // reverse the segment's steps
@@ -1090,8 +1101,10 @@ lb_status lb_window_backward(lb_handle* h, void* d_ws, size_t bytes, const doubl
                                                       (double*)(ws + w.lam_dp), (double*)(ws + w.gpart), nodes,
                                                       (uint32_t)lo.total_tiles, stepv));
             AdjArgsHost a;
-            const double* tb = (const double*)(ws + w.tape_beads + (size_t)j * 9 * nbx * sizeof(double));
-            a.x0 = tb; a.v0 = tb + nb3; a.f0 = tb + 2 * nb3;
+            const char* tb = ws + w.tape_beads + (size_t)j * w.bspan;   // x, v, f as laid out in the state
+            a.x0 = (const double*)tb;
+            a.v0 = (const double*)(tb + (lo.st_v - lo.st_x));
+            a.f0 = (const double*)(tb + (lo.st_f - lo.st_x));
             a.tape = (const double*)(ws + w.tape_sub + (size_t)j * smax * nbx * TAPE_REC * sizeof(double));
             a.dj = (const double*)(ws + w.dj) + (size_t)t * nb3;
             a.lx = lb; a.lv = lb + nb3; a.lf = lb + 2 * nb3;
