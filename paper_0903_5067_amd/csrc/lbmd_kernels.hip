@@ -315,7 +315,7 @@ __global__ __launch_bounds__(MAXT) void k_couple(const BoxDev* __restrict__ boxe
     __shared__ double xs[3 * BIG_CHAIN];   // chains on this path have at most BIG_CHAIN beads
     __builtin_amdgcn_s_setprio(3);   // latency-bound chain beside the bandwidth-bound collide
     const int bi = couple_list[blockIdx.x];
-    const BoxDev& bx = boxes[bi];
+    const BoxDev bx = boxes[bi];   // a copy: its fields stay in registers across the substeps
     const int N = bx.N;
     // lanes per bead depend on this chain's length alone, so a box computes
     // the same bits in any batch
@@ -1665,7 +1665,7 @@ __global__ __launch_bounds__(256) void k_adj_couple(const BoxDev* __restrict__ b
 {
     __shared__ double xs[3 * 256], lF[3 * 256], red[256];
     const int bi = couple_list[blockIdx.x];
-    const BoxDev& bx = boxes[bi];
+    const BoxDev bx = boxes[bi];   // a copy: its fields stay in registers across the substeps
     const int N = bx.N, S = bx.substeps, L = bx.L;
     const int T = bx.couple_T;
     const int b = (int)threadIdx.x / T, lane = (int)threadIdx.x % T;
