@@ -16,6 +16,7 @@ dynamic ones from the sampled centre of mass and the two innermost beads:
 and the beads' kinetic temperature <m v^2> / 3 against kT.
 
     python -m paper_0903_5067_amd.table1 --L 10 15 --boxes 128 --out result.json
+    python -m paper_0903_5067_amd.table1 --therm 1 ...   (stress modes only)
 """
 from __future__ import annotations
 
@@ -36,6 +37,8 @@ PAPER_TABLE1 = {
     25: {"nu": (0.619, 0.005), "re2": (100.20, 1.28), "rg2": (15.36, 0.11), "g1_exponent": (0.710, 0.0005),
          "d_cm": (6.959e-3, 2e-6), "tau_tr": (368.51, 2.67)},
 }
+# the same table's g1 exponents from LB runs that thermalize the stress modes only
+PAPER_G1_STRESS_ONLY = {10: (0.645, 0.0006), 15: (0.684, 0.0006), 25: (0.714, 0.0006)}
 
 
 def _say(*a):
@@ -43,13 +46,13 @@ def _say(*a):
 
 
 def run_box_size(L: int, n_boxes: int, equil_tau: float, prod_tau: float, sample_tau: float, seed: int = 1,
-                 precision: int | None = None) -> dict:
+                 precision: int | None = None, therm: int = 2) -> dict:
     import lbinputs
     import paper_0903_5067_amd as lbm
     from paper_0903_5067_amd import analysis as an
 
     prec = lbm.FP32_DEV if precision is None else precision
-    base = lbinputs.box_params("paper", L=L, seed=seed)
+    base = lbinputs.box_params("paper", L=L, seed=seed, therm=therm)
     boxes = [dict(base, box_id=i) for i in range(n_boxes)]
     N = int(base["N"])
     x0 = np.concatenate([lbinputs.saw_chain(N, L, seed + 7919 * i) for i in range(n_boxes)])
@@ -98,6 +101,7 @@ def run_box_size(L: int, n_boxes: int, equil_tau: float, prod_tau: float, sample
         return float(m.mean()), float(m.std(ddof=1) / np.sqrt(len(m)))
 
     res = {"L": L, "boxes": n_boxes, "precision": "fp32_dev" if prec == lbm.FP32_DEV else "fp64",
+           "thermalize": "all modes" if therm == 2 else ("stress modes" if therm == 1 else "none"),
            "equil_tau": n_eq * every * tau, "prod_tau": n_s * every * tau, "sample_tau": every * tau,
            "lb_steps": (n_eq + n_s) * every, "wall_s": round(wall, 1), "health": int(health)}
     res["re2"] = box_mean(re2)
@@ -126,7 +130,9 @@ def run_box_size(L: int, n_boxes: int, equil_tau: float, prod_tau: float, sample
     res["curves"] = {"t": t.tolist(), "g1": g1.tolist(), "g2": g2.tolist(), "g3": g3.tolist(),
                      "k": ks.tolist(), "S": sk.tolist()}
     if L in PAPER_TABLE1:
-        res["paper"] = PAPER_TABLE1[L]
+        res["paper"] = dict(PAPER_TABLE1[L])
+        if therm == 1:
+            res["paper"]["g1_exponent"] = PAPER_G1_STRESS_ONLY[L]
     return res
 
 
@@ -138,6 +144,8 @@ def main(argv=None):
     ap.add_argument("--prod-tau", type=float, default=10000.0)
     ap.add_argument("--sample-tau", type=float, default=1.0)
     ap.add_argument("--seed", type=int, default=1)
+    ap.add_argument("--therm", type=int, default=2, choices=[0, 1, 2],
+                    help="thermalized modes: 2 all non-conserved, 1 stress only, 0 none")
     ap.add_argument("--out", default=None)
     a = ap.parse_args(argv)
     root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
@@ -145,7 +153,7 @@ def main(argv=None):
         sys.path.insert(0, root)
     out = []
     for L in a.L:
-        r = run_box_size(L, a.boxes, a.equil_tau, a.prod_tau, a.sample_tau, a.seed)
+        r = run_box_size(L, a.boxes, a.equil_tau, a.prod_tau, a.sample_tau, a.seed, therm=a.therm)
         brief = {k: v for k, v in r.items() if k != "curves"}
         _say(json.dumps(brief))
         out.append(r)
