@@ -87,3 +87,35 @@ def test_block_error():
     s = rng.normal(size=(20000, 4))
     # independent samples: close to sigma / sqrt(n)
     assert an.block_error(s) == pytest.approx(1 / np.sqrt(s.size), rel=0.5)
+
+
+def test_rouse_analysis_recovers_rouse_chain_relaxation_times():
+    """Sec. III.B validates its Rouse-mode analysis on a Gaussian Rouse chain
+    of N = 8 without hydrodynamics or excluded volume.  Here: 400 such chains
+    (harmonic springs k, friction zeta, overdamped Langevin, Euler-Maruyama).
+    The X_p of the paper's definition are the exact normal modes of this
+    chain, with <X_p(t) . X_p(0)> / <X_p^2> = exp(-t / tau_p) and
+    tau_p = zeta / (4 k sin^2(p pi / 2N)).  The analysis functions give tau_p
+    to the statistical error."""
+    rng = np.random.default_rng(11)
+    n_ch, N, k, zeta, kT, dt = 400, 8, 1.0, 1.0, 1.0, 0.005
+    every, n_samp = 10, 2000
+    x = np.cumsum(rng.normal(scale=np.sqrt(kT / k), size=(n_ch, N, 3)), axis=1)   # equilibrium bonds
+    amp = np.sqrt(2 * kT * dt / zeta)
+    series = np.empty((n_samp, n_ch, N, 3))
+    for i in range(n_samp):
+        for _ in range(every):
+            f = np.zeros_like(x)
+            bond = x[:, 1:] - x[:, :-1]
+            f[:, :-1] += k * bond
+            f[:, 1:] -= k * bond
+            x = x + f * (dt / zeta) + amp * rng.normal(size=x.shape)
+        series[i] = x
+    modes = an.rouse_modes(series, 5)                       # [T, chains, 5, 3]
+    t_s = every * dt
+    for p in range(1, 6):
+        tau = zeta / (4 * k * np.sin(p * np.pi / (2 * N)) ** 2)
+        lags = np.arange(0, int(tau / t_s) + 1)             # the ACF from 1 down to ~1/e
+        c = an.autocorrelation(modes[:, :, p - 1], lags)
+        slope = np.polyfit(lags * t_s, np.log(c), 1)[0]
+        assert -1.0 / slope == pytest.approx(tau, rel=0.03), p
