@@ -4,6 +4,7 @@ boundaries.  Plain numpy; no GPU work happens here.
 
 Definitions (Sec. III.A static properties, Sec. III.B dynamic properties):
   * R_g^2 = (1 / 2N^2) sum_ij r_ij^2 and R_e^2 = (r_N - r_1)^2;
+  * <1/R_H> = (1/N^2) sum_{i != j} <1/r_ij>;
   * S(k) = (1/N) sum_ij sin(k r_ij) / (k r_ij), and the Flory exponent nu
     from S(k) ~ k^(-1/nu) in the scaling regime;
   * g1(t): mean-square displacement of a monomer (the two innermost), g2(t):
@@ -23,6 +24,16 @@ def rg2(x: np.ndarray) -> np.ndarray:
     d = x[..., :, None, :] - x[..., None, :, :]
     n = x.shape[-2]
     return np.sum(d * d, axis=(-1, -2, -3)) / (2.0 * n * n)
+
+
+def inverse_hydrodynamic_radius(x: np.ndarray) -> np.ndarray:
+    """<1/R_H> = (1/N^2) sum_{i != j} 1/r_ij (Sec. III.A, the chain's
+    hydrodynamic radius in an infinite medium); x [..., N, 3]."""
+    n = x.shape[-2]
+    d = x[..., :, None, :] - x[..., None, :, :]
+    r = np.sqrt(np.sum(d * d, axis=-1))
+    off = ~np.eye(n, dtype=bool)
+    return np.sum(np.where(off, 1.0 / np.where(off, r, 1.0), 0.0), axis=(-1, -2)) / (n * n)
 
 
 def re2(x: np.ndarray) -> np.ndarray:

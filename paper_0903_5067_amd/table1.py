@@ -8,7 +8,7 @@ Each box has its own Philox stream (key (seed, box)) and its own starting
 walk. Boxes are equilibrated, then sampled every `sample_tau` (LJ time).
 Static averages and their errors come from the spread of per-box time
 averages, since the boxes are independent:
-  <R_e^2>, <R_g^2> (GPU FP64 sums), nu from S(k) ~ k^(-1/nu),
+  <R_e^2>, <R_g^2> (GPU FP64 sums), <1/R_H> (snapshots), nu from S(k) ~ k^(-1/nu),
 dynamic ones from the sampled centre of mass and the two innermost beads:
   g1 exponent over t in [20, 80], D_CM from g3 = 6 D t over the same window
   and over [100, 1000], tau_tr = <R_g^2> / (6 D_CM), the first Rouse mode's
@@ -30,11 +30,14 @@ import numpy as np
 
 # LB columns of the paper's Table 1 (N = 32; LB time step 0.02): value, error
 PAPER_TABLE1 = {
-    10: {"nu": (0.615, 0.005), "re2": (94.56, 1.20), "rg2": (14.83, 0.10), "g1_exponent": (0.640, 0.0005),
+    10: {"nu": (0.615, 0.005), "re2": (94.56, 1.20), "rg2": (14.83, 0.10), "inv_rh": (0.291, 0.0005),
+         "g1_exponent": (0.640, 0.0005),
          "d_cm": (3.914e-3, 1e-6), "tau_tr": (631.36, 4.43)},
-    15: {"nu": (0.617, 0.005), "re2": (100.05, 1.26), "rg2": (15.31, 0.11), "g1_exponent": (0.675, 0.0005),
+    15: {"nu": (0.617, 0.005), "re2": (100.05, 1.26), "rg2": (15.31, 0.11), "inv_rh": (0.290, 0.0005),
+         "g1_exponent": (0.675, 0.0005),
          "d_cm": (5.162e-3, 1e-6), "tau_tr": (492.01, 3.56)},
-    25: {"nu": (0.619, 0.005), "re2": (100.20, 1.28), "rg2": (15.36, 0.11), "g1_exponent": (0.710, 0.0005),
+    25: {"nu": (0.619, 0.005), "re2": (100.20, 1.28), "rg2": (15.36, 0.11), "inv_rh": (0.289, 0.0005),
+         "g1_exponent": (0.710, 0.0005),
          "d_cm": (6.959e-3, 2e-6), "tau_tr": (368.51, 2.67)},
 }
 # the same table's g1 exponents from LB runs that thermalize the stress modes only
@@ -108,6 +111,8 @@ def run_box_size(L: int, n_boxes: int, equil_tau: float, prod_tau: float, sample
     res["rg2"] = box_mean(rg2)
     ks = np.geomspace(0.3, 3.0, 24)
     sk = np.mean([an.structure_factor(c, ks) for c in snaps], axis=0)
+    rh_box = np.mean([an.inverse_hydrodynamic_radius(c) for c in snaps], axis=0)   # per box
+    res["inv_rh"] = (float(rh_box.mean()), float(rh_box.std(ddof=1) / np.sqrt(n_boxes)))
     res["nu"] = an.flory_exponent(ks, sk, 0.8, 2.0)
     lags = np.unique(np.round(np.geomspace(1, n_s // 4, 40)).astype(int))
     t = lags * every * tau

@@ -21,6 +21,15 @@ def test_rg2_re2_of_a_straight_chain():
         assert an.re2(x) == pytest.approx(0.97 ** 2 * (n - 1) ** 2, rel=1e-13)
 
 
+def test_inverse_hydrodynamic_radius_of_a_rod():
+    """Rod of N beads spaced a: (1/N^2) sum_{i != j} 1/(a |i - j|)
+    = 2 (N H_{N-1} - (N - 1)) / (a N^2), H the harmonic number."""
+    for n in (2, 7, 32):
+        x = _straight(n, 0.97)
+        h = sum(1.0 / m for m in range(1, n))
+        assert an.inverse_hydrodynamic_radius(x) == pytest.approx(2 * (n * h - (n - 1)) / (0.97 * n * n), rel=1e-13)
+
+
 def test_rg2_pair_form_equals_centre_of_mass_form():
     rng = np.random.default_rng(1)
     x = rng.normal(size=(5, 32, 3))
