@@ -196,6 +196,41 @@ def adjoint_secondary():
             "grad_finite": bool(np.all(np.isfinite(g)))}
 
 
+def single64_secondary(graph_steps=20):
+    """The 64^3 box with its 64-bead chain: step rate and collide kernel."""
+    s64, b64, n64, p64 = make_system("single64")
+    if graph_steps:
+        s64.set_launch(batched=True, graph_steps=graph_steps)
+    t64, _ = time_steps(s64, 2000, 50)
+    c64 = time_collide(s64, 200)
+    o64 = s64.observables()[0]
+    s64.close()
+    return {"mlups": round(n64 * 2000 / t64 / 1e6, 1), "ms_per_step": round(1e3 * t64 / 2000, 4),
+            "collide_us": round(1e6 * c64, 2),
+            "collide_gbs": round(BYTES_PER_NODE[p64] * n64 / c64 / 1e9, 1),
+            "rg2_after_2050_steps": round(o64["rg2"], 4), "re2_after_2050_steps": round(o64["re2"], 4)}
+
+
+def batched256_secondary(graph_steps=20):
+    """256 boxes of mixed size, one launch per kernel, against the same boxes
+    launched box by box."""
+    sb, bb, nb, pb = make_system("batched256")
+    if graph_steps:
+        sb.set_launch(batched=True, graph_steps=graph_steps)
+    tb, _ = time_steps(sb, 500, 20)
+    cb = time_collide(sb, 100)
+    sb.set_launch(batched=False)
+    tp, _ = time_steps(sb, 100, 5)
+    sb.close()
+    return {"boxes": len(bb), "nodes": nb, "beads": int(sum(b["N"] for b in bb)),
+            "batched_mlups": round(nb * 500 / tb / 1e6, 1),
+            "batched_pct_hbm_peak": round(100.0 * BYTES_PER_NODE[pb] * nb * 500 / tb / 1e9 / HBM_PEAK_GBS, 1),
+            "plain_per_box_mlups": round(nb * 100 / tp / 1e6, 1),
+            "batched_over_plain": round((nb * 500 / tb) / (nb * 100 / tp), 3),
+            "collide_us": round(1e6 * cb, 1),
+            "collide_gbs": round(BYTES_PER_NODE[pb] * nb / cb / 1e9, 1)}
+
+
 def semidilute_secondary(steps=300, graph_steps=20):
     """Semidilute solution (Sec. III.C): a batch of 20^3 boxes, each holding 32
     chains of 32 beads (1024 beads, the 1024-thread coupling path), at the
@@ -345,10 +380,17 @@ def main():
                     help="force this collide launch shape instead of autotuning")
     ap.add_argument("--collide-launches", type=int, default=0,
                     help="launches of the collide kernel timed for the roofline (0: ~0.5 s worth)")
+    ap.add_argument("--fixup-after-collide", action="store_true",
+                    help="re-collide the chain's nodes after the collide instead of colliding their tiles "
+                         "beside it (same results; for comparison)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run the plain copy used to scale the HBM byte counters")
     ap.add_argument("--only-semidilute", action="store_true",
                     help="only run the semidilute secondary and print it")
+    ap.add_argument("--only-single64", action="store_true",
+                    help="only run the 64^3 secondary and print it")
+    ap.add_argument("--only-batched256", action="store_true",
+                    help="only run the 256-box secondary and print it")
     ap.add_argument("--only-adjoint", action="store_true",
                     help="only run the adjoint-window secondary and print it")
     args = ap.parse_args()
@@ -366,13 +408,21 @@ def main():
     if args.only_semidilute:
         print(json.dumps(semidilute_secondary()), flush=True)
         return
+    if args.only_single64:
+        print(json.dumps(single64_secondary(args.graph_steps)), flush=True)
+        return
+    if args.only_batched256:
+        print(json.dumps(batched256_secondary(args.graph_steps)), flush=True)
+        return
     if args.only_adjoint:
         print(json.dumps(adjoint_secondary()), flush=True)
         return
     log("workload", args.workload)
     s, boxes, nodes, prec = make_system(args.workload)
     if args.graph_steps:
-        s.set_launch(batched=True, graph_steps=args.graph_steps)
+        s.set_launch(batched=True, graph_steps=args.graph_steps, overlap=not args.fixup_after_collide)
+    elif args.fixup_after_collide:
+        s.set_launch(batched=True, graph_steps=0, overlap=False)
     tune = None
     if args.variant >= 0:
         s.set_collide_variant(args.variant)
@@ -428,32 +478,8 @@ def main():
 
     if not args.no_secondary:
         sec = {}
-        s64, b64, n64, p64 = make_system("single64")
-        if args.graph_steps:
-            s64.set_launch(batched=True, graph_steps=args.graph_steps)
-        t64, _ = time_steps(s64, 2000, 50)
-        c64 = time_collide(s64, 200)
-        o64 = s64.observables()[0]
-        sec["single64"] = {"mlups": round(n64 * 2000 / t64 / 1e6, 1), "ms_per_step": round(1e3 * t64 / 2000, 4),
-                           "collide_us": round(1e6 * c64, 2),
-                           "collide_gbs": round(BYTES_PER_NODE[p64] * n64 / c64 / 1e9, 1),
-                           "rg2_after_2050_steps": round(o64["rg2"], 4), "re2_after_2050_steps": round(o64["re2"], 4)}
-        s64.close()
-        sb, bb, nb, pb = make_system("batched256")
-        if args.graph_steps:
-            sb.set_launch(batched=True, graph_steps=args.graph_steps)
-        tb, _ = time_steps(sb, 500, 20)
-        cb = time_collide(sb, 100)
-        sb.set_launch(batched=False)
-        tp, _ = time_steps(sb, 100, 5)
-        sec["batched256"] = {"boxes": len(bb), "nodes": nb, "beads": int(sum(b["N"] for b in bb)),
-                             "batched_mlups": round(nb * 500 / tb / 1e6, 1),
-                             "batched_pct_hbm_peak": round(100.0 * BYTES_PER_NODE[pb] * nb * 500 / tb / 1e9 / HBM_PEAK_GBS, 1),
-                             "plain_per_box_mlups": round(nb * 100 / tp / 1e6, 1),
-                             "batched_over_plain": round((nb * 500 / tb) / (nb * 100 / tp), 3),
-                             "collide_us": round(1e6 * cb, 1),
-                             "collide_gbs": round(BYTES_PER_NODE[pb] * nb / cb / 1e9, 1)}
-        sb.close()
+        sec["single64"] = single64_secondary(args.graph_steps)
+        sec["batched256"] = batched256_secondary(args.graph_steps)
         sec["adjoint32"] = adjoint_secondary()
         sec["thermalization"] = thermalization_secondary()
         sec["semidilute"] = semidilute_secondary()

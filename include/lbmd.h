@@ -170,9 +170,14 @@ lb_status lb_velocity_history(lb_handle* h, int64_t step, double* host_out, size
 lb_status lb_bead_positions(lb_handle* h, double* host_out, size_t bytes);
 
 /* Launch structure: batched = 1 advances every box with one launch per kernel
- * (the default); batched = 0 launches per box (the plain form).
+ * (the default); batched = 0 launches per box (the plain form).  In batched
+ * steps the collide tiles around chains above 256 beads in boxes they do not
+ * cover densely are collided beside the other tiles once the chain's
+ * impulses are in; batched = 2 re-collides the chain's nodes after the
+ * collide instead.  All forms compute the same bits.
  * graph_steps > 0 records that many LB steps (rounded up to even) in a HIP
- * graph and replays it; 0 launches kernels directly. */
+ * graph and replays it; 0 launches kernels directly.  LB_EINVAL for batched
+ * outside 0..2 or graph_steps < 0. */
 lb_status lb_set_launch(lb_handle* h, int32_t batched, int32_t graph_steps);
 
 /* ---- adjoint window (gradient of a loss of the bead velocities) ----------

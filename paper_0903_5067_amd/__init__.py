@@ -171,8 +171,9 @@ class LBSystem:
     def step(self, n: int = 1):
         _check(lib().lb_step(self.h, int(n)), self.h)
 
-    def set_launch(self, batched: bool = True, graph_steps: int = 0):
-        _check(lib().lb_set_launch(self.h, 1 if batched else 0, int(graph_steps)), self.h)
+    def set_launch(self, batched: bool = True, graph_steps: int = 0, overlap: bool = True):
+        mode = (1 if overlap else 2) if batched else 0
+        _check(lib().lb_set_launch(self.h, mode, int(graph_steps)), self.h)
 
     def collide_only(self, n: int = 1):
         """n launches of the fused collide+stream kernel, state not advanced."""

@@ -57,7 +57,8 @@ __host__ __device__ __forceinline__ uint64_t pop_elems_of(uint64_t V)
 struct Ctrl {
     uint32_t step;
     uint32_t health;
-    uint32_t pad[2];
+    uint32_t defer_cnt;   // collide tiles deferred this step (reset at the step's end)
+    uint32_t ovf_cnt;     // impulses of this step outside the deferred tiles
 };
 
 enum : uint32_t {

@@ -24,6 +24,12 @@
 //                 records turned into node impulses
 //   k_fixup       re-collides the nodes the beads touched, with their
 //                 impulse, and overwrites their outputs
+//   k_collide_deferred, k_overflow
+//                 batched steps with chains of 257..1024 beads in sparse
+//                 boxes: the tiles holding the beads' node tables skip the
+//                 plain collide and are collided with their impulses beside
+//                 it, after the coupling; nodes outside them that got an
+//                 impulse are fixed up after the collide
 //   k_node_field, k_collide_forced
 //                 boxes whose beads cover much of the box: node velocities
 //                 once per step for the beads' tables, and a collide after
@@ -85,9 +91,18 @@ template <typename R>
 __device__ __forceinline__ void collide_tile(const BoxDev* __restrict__ boxes, const CollideConst<R>* __restrict__ ccs,
                                              const uint32_t* __restrict__ tile_box, int fixed_box, uint32_t tile,
                                              const R* __restrict__ A, R* __restrict__ B, Ctrl* __restrict__ ctrl,
-                                             uint32_t t)
+                                             uint32_t t, const uint32_t* __restrict__ defer)
 {
-    const int bi = fixed_box >= 0 ? fixed_box : (int)tile_box[tile];
+    int bi;
+    if (defer) {   // batched steps (every tile's box from tile_box)
+        // a deferred tile is collided after the coupling, with its impulses
+        // (k_collide_deferred); the flag load goes out beside the box load
+        const uint32_t deferred = defer[tile];
+        bi = (int)tile_box[tile];
+        if (deferred) return;
+    } else {
+        bi = fixed_box >= 0 ? fixed_box : (int)tile_box[tile];
+    }
     const BoxDev& bx = boxes[bi];
     const int L = bx.L;
     const uint32_t V = (uint32_t)L * L * L;
@@ -112,14 +127,14 @@ template <typename R, int W, bool PERSIST>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, W))) void k_collide(
     const BoxDev* __restrict__ boxes, const CollideConst<R>* __restrict__ ccs, const uint32_t* __restrict__ tile_box,
     int fixed_box, uint32_t tile0, uint32_t n_tiles, const R* __restrict__ A, R* __restrict__ B,
-    Ctrl* __restrict__ ctrl, uint32_t s_off)
+    Ctrl* __restrict__ ctrl, uint32_t s_off, const uint32_t* __restrict__ defer)
 {
     const uint32_t t = ctrl->step + s_off;
     if (PERSIST) {
         for (uint32_t k = blockIdx.x; k < n_tiles; k += gridDim.x)
-            collide_tile<R>(boxes, ccs, tile_box, fixed_box, tile0 + k, A, B, ctrl, t);
+            collide_tile<R>(boxes, ccs, tile_box, fixed_box, tile0 + k, A, B, ctrl, t, defer);
     } else {
-        collide_tile<R>(boxes, ccs, tile_box, fixed_box, tile0 + blockIdx.x, A, B, ctrl, t);
+        collide_tile<R>(boxes, ccs, tile_box, fixed_box, tile0 + blockIdx.x, A, B, ctrl, t, defer);
     }
 }
 
@@ -135,6 +150,9 @@ struct ChainArgs {
     double* vhist; int hist_len; uint64_t total_beads;
     double* tape;              // non-null while replaying a window segment: per substep and bead,
                                // TAPE_REC doubles (see k_couple)
+    uint32_t* defer;           // non-null when the step defers tiles: per collide tile, 1 if deferred
+    uint32_t* defer_list; uint32_t defer_cap;
+    uint32_t* ovf; uint32_t ovf_cap;   // (bead, local node) pairs outside the deferred tiles
 };
 
 // node velocities (MD units) of the 8 stencil nodes from the frozen populations;
@@ -568,7 +586,7 @@ template <typename R>
 __global__ __launch_bounds__(256) void k_near_nodes(const BoxDev* __restrict__ boxes,
                                                     const int32_t* __restrict__ list, const R* __restrict__ A,
                                                     ChainArgs ca, R* __restrict__ near_u, int4* __restrict__ near_c,
-                                                    const R* __restrict__ field)
+                                                    const R* __restrict__ field, Ctrl* __restrict__ ctrl)
 {
     const BoxDev& bx = boxes[list[blockIdx.y]];
     const int N = bx.N, L = bx.L;
@@ -593,6 +611,18 @@ __global__ __launch_bounds__(256) void k_near_nodes(const BoxDev* __restrict__ b
     const Upwind up(nx, ny, nz, (uint32_t)L);
     R d[19];
     gather_pre<R, false>(A + bx.pop_off, up, d);
+    if (ca.defer) {
+        // the bead's stencil stays on its table's nodes while it moves less
+        // than half a cell from its nearest node: their tiles wait for the
+        // impulses.  The first thread to flag a tile lists it.  Issued after
+        // the population loads, so the round trips overlap.
+        const uint32_t tile = bx.tile_begin + node / 256u;
+        if (atomicExch(&ca.defer[tile], 1u) == 0u) {
+            const uint32_t k = atomicAdd(&ctrl->defer_cnt, 1u);
+            if (k < ca.defer_cap) ca.defer_list[k] = tile;
+            else atomicOr(&ctrl->health, H_TABLE);
+        }
+    }
     R u[3];
     node_velocity<R>(d, bx.rho0, 1.0 / bx.tau_lb, u);
     o[0] = u[0]; o[1] = u[1]; o[2] = u[2];
@@ -887,6 +917,19 @@ __global__ __launch_bounds__(WG_MAXB) void k_chain_wg(const BoxDev* __restrict__
     if (b == 0 && rebuilds) atomicAdd(&ca.nl_rebuilds[bi], (uint32_t)rebuilds);
 }
 
+// an impulse on a node whose tile is not deferred (the bead left its table):
+// listed for the end-of-step fix-up
+__device__ __forceinline__ uint32_t list_overflow(const ChainArgs& ca, const BoxDev& bx, uint64_t g, uint32_t node,
+                                                  Ctrl* __restrict__ ctrl)
+{
+    if (!ca.defer || ca.defer[bx.tile_begin + node / 256u]) return 0u;
+    const uint32_t k = atomicAdd(&ctrl->ovf_cnt, 1u);
+    if (k >= ca.ovf_cap) return H_TABLE;
+    ca.ovf[2 * (uint64_t)k] = (uint32_t)g;
+    ca.ovf[2 * (uint64_t)k + 1] = node;
+    return 0u;
+}
+
 // node impulses from the substep records: thread (bead, corner k) accumulates
 // -w_k (F_fric + F_rand) dt over the substeps that share a stencil, in MD
 // units and in substep order, and hands each stencil's sum over when the
@@ -921,6 +964,7 @@ __global__ __launch_bounds__(256) void k_spread(const BoxDev* __restrict__ boxes
                     if (!(fabs(q) < IMP_MAX)) { hb |= H_FIXED; q = 0.0; }
                     atomicAdd(imp + 3 * (uint64_t)cur + c, (unsigned long long)(long long)llrint(q * IMP_SCALE));
                 }
+                hb |= list_overflow(ca, bx, g, cur, ctrl);
             }
             cur = node;
             acc[0] = acc[1] = acc[2] = 0.0;
@@ -938,6 +982,7 @@ __global__ __launch_bounds__(256) void k_spread(const BoxDev* __restrict__ boxes
             if (!(fabs(q) < IMP_MAX)) { hb |= H_FIXED; q = 0.0; }
             atomicAdd(imp + 3 * (uint64_t)cur + c, (unsigned long long)(long long)llrint(q * IMP_SCALE));
         }
+        hb |= list_overflow(ca, bx, g, cur, ctrl);
     }
     if (hb) atomicOr(&ctrl->health, hb);
 }
@@ -1101,68 +1146,103 @@ __global__ __launch_bounds__(256) void k_gather_imp(const BoxDev* __restrict__ b
 }
 
 // ---------------------------------------------------------------- fixup
-// One thread per touched-node slot of the launched beads.  A node touched by
-// several beads is claimed by one thread through a step stamp; that thread
-// takes the node's impulse out of the dense field, collides the node with it
-// and overwrites the node's streamed outputs.
+// Collide node r of box bi with its impulse from the dense field and
+// overwrite its streamed outputs.  The claim stamp makes one caller per node
+// and step do it: the populations and the impulse are loaded before the
+// claim returns, so the three latencies overlap.
 template <typename R>
-__global__ __launch_bounds__(256) void k_fixup(const BoxDev* __restrict__ boxes,
-                                               const CollideConst<R>* __restrict__ ccs,
-                                               const int32_t* __restrict__ bead_box, uint64_t bead0,
-                                               uint32_t n_entries, ChainArgs ca, uint32_t* __restrict__ claim,
-                                               const R* __restrict__ A, R* __restrict__ B,
-                                               Ctrl* __restrict__ ctrl, uint32_t s_off, int keep_imp)
+__device__ __forceinline__ void fixup_node(const BoxDev& bx, const CollideConst<R>* __restrict__ ccs, int bi,
+                                           uint32_t r, unsigned long long* __restrict__ imp,
+                                           uint32_t* __restrict__ claim, const R* __restrict__ A,
+                                           R* __restrict__ B, Ctrl* __restrict__ ctrl, uint32_t t, int keep_imp)
 {
-    const uint32_t e = blockIdx.x * 256u + threadIdx.x;
-    if (e >= n_entries) return;
-    const uint64_t g = bead0 + e / (uint32_t)ca.touch_cap;
-    const int k = (int)(e % (uint32_t)ca.touch_cap);
-    if (k >= ca.touched_cnt[g]) return;
-    const int bi = bead_box[g];
-    const BoxDev& bx = boxes[bi];
-    if (bx.dense) return;   // its collide takes the impulses itself
-    const uint32_t r = ca.touched[g * ca.touch_cap + k];
     const uint64_t node = bx.node_off + r;
-    const uint32_t t = ctrl->step + s_off;
-    if (atomicExch(&claim[node], t + 1u) == t + 1u) return;   // another slot took this node
-    const int L = bx.L;
-    const CollideConst<R> cc = ccs[bi];
-    const Upwind up = upwind_of(r, L, bx.inv_L);
+    const Upwind up = upwind_of(r, bx.L, bx.inv_L);
     R d[19];
     gather_pre<R, false>(A + bx.pop_off, up, d);
-    R fimp[3];
-#pragma unroll
-    for (int c = 0; c < 3; ++c) {
-        fimp[c] = (R)((double)(long long)ca.imp[3 * node + c] * IMP_INV_SCALE);
-        if (!keep_imp) ca.imp[3 * node + c] = 0ull;
-    }
+    unsigned long long* q = imp + 3 * node;
+    const unsigned long long q0 = q[0], q1 = q[1], q2 = q[2];
+    if (atomicExch(&claim[node], t + 1u) == t + 1u) return;   // another caller took this node
+    if (!keep_imp) { q[0] = 0ull; q[1] = 0ull; q[2] = 0ull; }
+    const CollideConst<R> cc = ccs[bi];
+    const R fx = (R)((double)(long long)q0 * IMP_INV_SCALE), fy = (R)((double)(long long)q1 * IMP_INV_SCALE),
+            fz = (R)((double)(long long)q2 * IMP_INV_SCALE);
     R o[19];
-    const uint32_t h = collide<R>(d, o, fimp[0], fimp[1], fimp[2], cc, r, t, bx.seed, bx.box_id);
+    const uint32_t h = collide<R>(d, o, fx, fy, fz, cc, r, t, bx.seed, bx.box_id);
     R* b = B + bx.pop_off;
 #pragma unroll
     for (int i = 0; i < 19; ++i) b[pop_at(i, r)] = o[i];
     if (h) atomicOr(&ctrl->health, h);
 }
 
-// Collide and stream every node of a dense box after its coupling stage: the
-// node's impulse comes straight from the fixed-point field, which is cleared
-// where it was set.  Same arithmetic as the fix-up, over whole tiles.
+// One thread per touched-node slot of the launched beads.  A node touched by
+// several beads is fixed once (claim stamp).  skip_big: the beads of chains
+// above BIG_CHAIN have their nodes in deferred tiles or in the overflow list.
 template <typename R>
-__global__ __launch_bounds__(256) void k_collide_forced(const BoxDev* __restrict__ boxes,
-                                                        const CollideConst<R>* __restrict__ ccs,
-                                                        const uint32_t* __restrict__ tile_box, int fixed_box,
-                                                        uint32_t tile0, unsigned long long* __restrict__ imp,
-                                                        const R* __restrict__ A, R* __restrict__ B,
-                                                        Ctrl* __restrict__ ctrl, uint32_t s_off)
+__global__ __launch_bounds__(256) void k_fixup(const BoxDev* __restrict__ boxes,
+                                               const CollideConst<R>* __restrict__ ccs,
+                                               const int32_t* __restrict__ bead_box, uint64_t bead0,
+                                               uint32_t n_entries, ChainArgs ca, uint32_t* __restrict__ claim,
+                                               const R* __restrict__ A, R* __restrict__ B,
+                                               Ctrl* __restrict__ ctrl, uint32_t s_off, int keep_imp, int skip_big)
 {
-    const uint32_t tile = tile0 + blockIdx.x;
+    const uint32_t e = blockIdx.x * 256u + threadIdx.x;
+    if (e >= n_entries) return;
+    const uint64_t g = bead0 + e / (uint32_t)ca.touch_cap;
+    const int k = (int)(e % (uint32_t)ca.touch_cap);
+    // independent loads together: the slot count, the box, the slot (read
+    // for every slot, used below the count) and the step
+    const int cnt = ca.touched_cnt[g];
+    const int bi = bead_box[g];
+    const uint32_t r = ca.touched[g * ca.touch_cap + k];
+    const uint32_t t = ctrl->step + s_off;
+    if (k >= cnt) return;
+    const BoxDev& bx = boxes[bi];
+    if (bx.dense) return;   // its collide takes the impulses itself
+    if (skip_big && bx.N > BIG_CHAIN) return;
+    fixup_node<R>(bx, ccs, bi, r, ca.imp, claim, A, B, ctrl, t, keep_imp);
+}
+
+// End of a step that deferred tiles (one workgroup): fix the listed nodes
+// outside the deferred tiles, then clear the deferral for the next step.  Runs
+// after the plain collide, the deferred tiles' collide and the coupling.
+template <typename R>
+__global__ __launch_bounds__(256) void k_overflow(const BoxDev* __restrict__ boxes,
+                                                   const CollideConst<R>* __restrict__ ccs,
+                                                   const int32_t* __restrict__ bead_box, ChainArgs ca,
+                                                   uint32_t* __restrict__ claim, const R* __restrict__ A,
+                                                   R* __restrict__ B, Ctrl* __restrict__ ctrl, uint32_t s_off)
+{
+    const uint32_t t = ctrl->step + s_off;
+    const uint32_t n_ovf = min(ctrl->ovf_cnt, ca.ovf_cap), n_def = min(ctrl->defer_cnt, ca.defer_cap);
+    for (uint32_t e = threadIdx.x; e < n_ovf; e += blockDim.x) {
+        const uint64_t g = ca.ovf[2 * (uint64_t)e];
+        const uint32_t r = ca.ovf[2 * (uint64_t)e + 1];
+        const int bi = bead_box[g];
+        fixup_node<R>(boxes[bi], ccs, bi, r, ca.imp, claim, A, B, ctrl, t, 0);
+    }
+    for (uint32_t k = threadIdx.x; k < n_def; k += blockDim.x) ca.defer[ca.defer_list[k]] = 0u;
+    __syncthreads();   // every thread has read both counts
+    if (threadIdx.x == 0) { ctrl->defer_cnt = 0u; ctrl->ovf_cnt = 0u; }
+}
+
+// Collide and stream one 256-node tile after the coupling stage: each node's
+// impulse comes straight from the fixed-point field, which is cleared where
+// it was set.  Same arithmetic as the fix-up, over a whole tile.
+template <typename R>
+__device__ __forceinline__ void collide_forced_tile(const BoxDev* __restrict__ boxes,
+                                                    const CollideConst<R>* __restrict__ ccs,
+                                                    const uint32_t* __restrict__ tile_box, int fixed_box,
+                                                    uint32_t tile, unsigned long long* __restrict__ imp,
+                                                    const R* __restrict__ A, R* __restrict__ B,
+                                                    Ctrl* __restrict__ ctrl, uint32_t t)
+{
     const int bi = fixed_box >= 0 ? fixed_box : (int)tile_box[tile];
     const BoxDev& bx = boxes[bi];
     const int L = bx.L;
     const uint32_t V = (uint32_t)L * L * L;
     const uint32_t r = (tile - bx.tile_begin) * 256u + threadIdx.x;
     if (r >= V) return;
-    const uint32_t t = ctrl->step + s_off;
     const CollideConst<R> cc = ccs[bi];
     const Upwind up = upwind_of(r, L, bx.inv_L);
     R d[19];
@@ -1178,6 +1258,37 @@ __global__ __launch_bounds__(256) void k_collide_forced(const BoxDev* __restrict
 #pragma unroll
     for (int i = 0; i < 19; ++i) __builtin_nontemporal_store(o[i], b + pop_at(i, r));
     if (h) atomicOr(&ctrl->health, h);
+}
+
+// every node of a dense box, after its coupling stage
+template <typename R>
+__global__ __launch_bounds__(256) void k_collide_forced(const BoxDev* __restrict__ boxes,
+                                                        const CollideConst<R>* __restrict__ ccs,
+                                                        const uint32_t* __restrict__ tile_box, int fixed_box,
+                                                        uint32_t tile0, unsigned long long* __restrict__ imp,
+                                                        const R* __restrict__ A, R* __restrict__ B,
+                                                        Ctrl* __restrict__ ctrl, uint32_t s_off)
+{
+    collide_forced_tile<R>(boxes, ccs, tile_box, fixed_box, tile0 + blockIdx.x, imp, A, B, ctrl,
+                           ctrl->step + s_off);
+}
+
+// the deferred tiles of a step, after its coupling stage, beside the plain
+// collide of the other tiles (both only read the current state and write
+// disjoint nodes)
+template <typename R>
+__global__ __launch_bounds__(256) void k_collide_deferred(const BoxDev* __restrict__ boxes,
+                                                          const CollideConst<R>* __restrict__ ccs,
+                                                          const uint32_t* __restrict__ tile_box,
+                                                          const uint32_t* __restrict__ defer_list, uint32_t cap,
+                                                          unsigned long long* __restrict__ imp,
+                                                          const R* __restrict__ A, R* __restrict__ B,
+                                                          Ctrl* __restrict__ ctrl, uint32_t s_off)
+{
+    const uint32_t t = ctrl->step + s_off;
+    const uint32_t n = min(ctrl->defer_cnt, cap);
+    for (uint32_t k = blockIdx.x; k < n; k += gridDim.x)
+        collide_forced_tile<R>(boxes, ccs, tile_box, -1, defer_list[k], imp, A, B, ctrl, t);
 }
 
 // --------------------------------------------------------------- advance
@@ -1329,7 +1440,8 @@ __global__ __launch_bounds__(256) void k_chain_obs(const BoxDev* __restrict__ bo
 static ChainArgs chain_args(const LaunchCtx& c)
 {
     return ChainArgs{c.x, c.v, c.f, c.fc, c.nl_cnt, c.nl_idx, c.nl_x0, c.nl_cap, c.imp, c.touched,
-                     c.touched_cnt, c.touch_cap, c.nl_rebuilds, c.vhist, c.hist_len, c.total_beads, c.tape};
+                     c.touched_cnt, c.touch_cap, c.nl_rebuilds, c.vhist, c.hist_len, c.total_beads, c.tape,
+                     c.defer_on ? c.defer : nullptr, c.defer_list, c.defer_cap, c.ovf, c.ovf_cap};
 }
 
 template <typename R, int W, bool PERSIST>
@@ -1339,7 +1451,7 @@ static void launch_collide_v(const LaunchCtx& c, const void* A, void* B, int fix
     const uint32_t grid = PERSIST ? std::min<uint32_t>(n_tiles, (uint32_t)(c.n_cu * W)) : n_tiles;
     hipLaunchKernelGGL((k_collide<R, W, PERSIST>), dim3(grid), dim3(256), 0, c.stream, c.boxes,
                        (const CollideConst<R>*)c.ccs, c.tile_box, fixed_box, tile0, n_tiles, (const R*)A, (R*)B,
-                       c.ctrl, s_off);
+                       c.ctrl, s_off, c.defer_on ? (const uint32_t*)c.defer : nullptr);
 }
 
 template <typename R>
@@ -1370,7 +1482,29 @@ hipError_t launch_fixup(const LaunchCtx& c, const void* A, void* B, uint64_t bea
     const uint32_t n = (uint32_t)(n_beads * (uint64_t)c.touch_cap);
     hipLaunchKernelGGL(k_fixup<R>, dim3((n + 255) / 256), dim3(256), 0, c.stream, c.boxes,
                        (const CollideConst<R>*)c.ccs, c.bead_box, bead0, n, chain_args(c), c.claim,
-                       (const R*)A, (R*)B, c.ctrl, s_off, c.keep_imp);
+                       (const R*)A, (R*)B, c.ctrl, s_off, c.keep_imp, c.defer_on);
+    return hipGetLastError();
+}
+
+template <typename R>
+hipError_t launch_collide_deferred(const LaunchCtx& c, const void* A, void* B, uint32_t s_off)
+{
+    if (!c.defer_on || c.defer_cap == 0) return hipErrorInvalidValue;
+    // a grid of a few blocks per CU strides over the list (its length is
+    // known on the device only)
+    const uint32_t grid = std::min<uint32_t>(c.defer_cap, (uint32_t)(4 * c.n_cu));
+    hipLaunchKernelGGL(k_collide_deferred<R>, dim3(grid), dim3(256), 0, c.stream, c.boxes,
+                       (const CollideConst<R>*)c.ccs, c.tile_box, (const uint32_t*)c.defer_list, c.defer_cap, c.imp,
+                       (const R*)A, (R*)B, c.ctrl, s_off);
+    return hipGetLastError();
+}
+
+template <typename R>
+hipError_t launch_overflow(const LaunchCtx& c, const void* A, void* B, uint32_t s_off)
+{
+    if (!c.defer_on) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(k_overflow<R>, dim3(1), dim3(256), 0, c.stream, c.boxes, (const CollideConst<R>*)c.ccs,
+                       c.bead_box, chain_args(c), c.claim, (const R*)A, (R*)B, c.ctrl, s_off);
     return hipGetLastError();
 }
 
@@ -1407,7 +1541,7 @@ hipError_t launch_couple_big(const LaunchCtx& c, const void* A, const int32_t* l
         hipLaunchKernelGGL(k_node_field<R>, dim3(c.dense_max_tiles, n_list), dim3(256), 0, c.stream, c.boxes, list,
                            (const R*)A, (R*)c.field);
     hipLaunchKernelGGL(k_near_nodes<R>, dim3((max_n * NEAR + 255) / 256, n_list), dim3(256), 0, c.stream, c.boxes,
-                       list, (const R*)A, ca, (R*)c.near_u, c.near_c, (const R*)c.field);
+                       list, (const R*)A, ca, (R*)c.near_u, c.near_c, (const R*)c.field, c.ctrl);
     if (after_table) {
         const hipError_t e = hipEventRecord(after_table, c.stream);
         if (e != hipSuccess) return e;
@@ -1891,6 +2025,10 @@ template hipError_t launch_collide<float>(const LaunchCtx&, const void*, void*, 
 template hipError_t launch_collide<double>(const LaunchCtx&, const void*, void*, int, uint32_t, uint32_t, uint32_t);
 template hipError_t launch_fixup<float>(const LaunchCtx&, const void*, void*, uint64_t, uint64_t, uint32_t);
 template hipError_t launch_fixup<double>(const LaunchCtx&, const void*, void*, uint64_t, uint64_t, uint32_t);
+template hipError_t launch_collide_deferred<float>(const LaunchCtx&, const void*, void*, uint32_t);
+template hipError_t launch_collide_deferred<double>(const LaunchCtx&, const void*, void*, uint32_t);
+template hipError_t launch_overflow<float>(const LaunchCtx&, const void*, void*, uint32_t);
+template hipError_t launch_overflow<double>(const LaunchCtx&, const void*, void*, uint32_t);
 template hipError_t launch_collide_forced<float>(const LaunchCtx&, const void*, void*, int, uint32_t, uint32_t,
                                                  uint32_t);
 template hipError_t launch_collide_forced<double>(const LaunchCtx&, const void*, void*, int, uint32_t, uint32_t,

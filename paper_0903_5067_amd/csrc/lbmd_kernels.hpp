@@ -41,6 +41,16 @@ struct LaunchCtx {
     uint32_t* bin_start;           // dense boxes: per base node, first binned stencil run [L^3 + 1]
     unsigned long long* runimp;    // dense boxes: per stencil run, the fixed-point impulse to its 8 corners x 3
     uint32_t* slot_of;             // dense boxes: per bead and run, the run's slot [N x substeps]
+    // deferred tiles: in a batched step the collide tiles that hold a node of
+    // any table of a sparse box's large chain are left out of the plain
+    // collide and collided with their impulses beside it, once the coupling
+    // is done; impulses that land outside them are listed for a fix-up
+    int defer_on;                  // this launch defers (the pointers below are always set)
+    uint32_t* defer;               // per collide tile: 1 while deferred
+    uint32_t* defer_list;          // the deferred tiles, Ctrl::defer_cnt of them
+    uint32_t defer_cap;
+    uint32_t* ovf;                 // (bead, local node) pairs, Ctrl::ovf_cnt of them
+    uint32_t ovf_cap;
 };
 
 template <typename R>
@@ -49,6 +59,13 @@ hipError_t launch_collide(const LaunchCtx& c, const void* A, void* B, int fixed_
 template <typename R>
 hipError_t launch_fixup(const LaunchCtx& c, const void* A, void* B, uint64_t bead0, uint64_t n_beads,
                         uint32_t s_off);
+// the deferred tiles' collide (after the coupling, beside the plain
+// collide) and the end-of-step pass: fix-up of the listed impulses outside
+// them, then the deferral cleared
+template <typename R>
+hipError_t launch_collide_deferred(const LaunchCtx& c, const void* A, void* B, uint32_t s_off);
+template <typename R>
+hipError_t launch_overflow(const LaunchCtx& c, const void* A, void* B, uint32_t s_off);
 template <typename R>
 hipError_t launch_collide_forced(const LaunchCtx& c, const void* A, void* B, int fixed_box, uint32_t tile0,
                                  uint32_t n_tiles, uint32_t s_off);

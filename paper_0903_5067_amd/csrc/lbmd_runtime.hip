@@ -48,7 +48,9 @@ struct Layout {
            sc_touched = 0, sc_tcnt = 0, sc_beadbox = 0, sc_nlcnt = 0, sc_nlidx = 0, sc_nlx0 = 0,
            sc_part = 0, sc_stat = 0, sc_chain = 0, sc_vhist = 0, sc_nlreb = 0, sc_biglist = 0, sc_alllist = 0,
            sc_nearu = 0, sc_nearc = 0, sc_subrec = 0, sc_field = 0, sc_binstart = 0, sc_items = 0, sc_slotof = 0,
-           scratch_bytes = 0;
+           sc_defer = 0, sc_dlist = 0, sc_ovf = 0, scratch_bytes = 0;
+    uint64_t beads_big_sparse = 0;                    // beads of the chains above BIG_CHAIN in the other boxes
+    uint32_t defer_cap = 0, ovf_cap = 0;              // deferred-tile list and overflow list entries
     int max_N = 0;         // largest chain taking the one-workgroup path
     std::vector<int32_t> big_list;                    // boxes whose chain takes the 1024-thread kernel
     int big_max_n = 0, big_max_sub = 0;              // largest chain and most substeps among them
@@ -122,6 +124,7 @@ Layout make_layout(const lb_box_desc* b, int32_t n, int32_t prec, int32_t hist)
         nodes += V;
         const int N = b[i].n_beads;
         if (N > BIG_CHAIN) {
+            if (!Lo.dense.back()) Lo.beads_big_sparse += (uint64_t)N;
             Lo.big_list.push_back(i);
             Lo.big_max_n = std::max(Lo.big_max_n, N);
             Lo.big_max_sub = std::max(Lo.big_max_sub, b[i].md_substeps);
@@ -200,6 +203,14 @@ Layout make_layout(const lb_box_desc* b, int32_t n, int32_t prec, int32_t hist)
         Lo.sc_binstart = o; o = align256(o + std::max<uint64_t>(Lo.bin_entries, 1) * sizeof(uint32_t));
         Lo.sc_items = o; o = align256(o + std::max<uint64_t>(Lo.item_entries, 1) * 24 * sizeof(unsigned long long));
         Lo.sc_slotof = o; o = align256(o + std::max<uint64_t>(Lo.item_entries, 1) * sizeof(uint32_t));
+        // deferred tiles: a flag per collide tile; a tile is listed once, and
+        // a bead's table spans at most 27 tiles.  A bead hands impulses to at
+        // most 8 new nodes per substep.
+        Lo.defer_cap = (uint32_t)(27 * Lo.beads_big_sparse);
+        Lo.ovf_cap = (uint32_t)(8 * (uint64_t)std::max(Lo.big_max_sub, 1) * Lo.beads_big_sparse);
+        Lo.sc_defer = o; o = align256(o + (Lo.beads_big_sparse ? tiles : 1) * sizeof(uint32_t));
+        Lo.sc_dlist = o; o = align256(o + std::max<uint32_t>(Lo.defer_cap, 1) * sizeof(uint32_t));
+        Lo.sc_ovf = o; o = align256(o + std::max<uint32_t>(Lo.ovf_cap, 1) * 2 * sizeof(uint32_t));
     }
     Lo.scratch_bytes = o;
     return Lo;
@@ -248,6 +259,7 @@ struct lb_handle {
     uint64_t step = 0;                // host mirror of the device step counter
     bool pending = false;             // lb_couple done, impulses not yet consumed
     int batched = 1;
+    int overlap = 1;                  // batched steps defer the tiles around large chains (see enqueue_step)
     int graph_steps = 0;
     hipGraphExec_t gexec[2] = {nullptr, nullptr};
     hipGraph_t graph[2] = {nullptr, nullptr};
@@ -288,10 +300,17 @@ lb_status enqueue_step(lb_handle* h, int from, uint32_t s_off, bool couple)
     if (h->batched) {
         const bool fork = couple && any_beads;
         const int nbig = (int)h->lo.big_list.size();
+        // chains above BIG_CHAIN beads in sparse boxes: the tiles around
+        // them are collided beside the plain collide once their impulses are
+        // in, instead of re-collided after it (same bits either way)
+        const bool defer = fork && h->overlap && h->lo.beads_big_sparse > 0 && !c.keep_imp && !c.tape;
+        LaunchCtx c1 = c;
+        c1.defer_on = defer ? 1 : 0;
         if (fork) {
             HIPCHK(h, hipEventRecord(h->ev_fork, h->stream));
             HIPCHK(h, hipStreamWaitEvent(h->stream2, h->ev_fork, 0));
-            const LaunchCtx& c2 = h->ctx2;
+            LaunchCtx c2 = h->ctx2;
+            c2.defer_on = c1.defer_on;
             // a chain above 256 beads needs a whole CU (1024 threads, the full
             // register file): the collide waits for its short node-table
             // kernel, so the chain kernel queued right behind it is dispatched
@@ -302,16 +321,21 @@ lb_status enqueue_step(lb_handle* h, int from, uint32_t s_off, bool couple)
             if (nc)
                 HIPCHK(h, f64 ? launch_couple<double>(c2, A, h->couple_list, nc, h->lo.couple_block, s_off)
                               : launch_couple<float>(c2, A, h->couple_list, nc, h->lo.couple_block, s_off));
+            if (defer)
+                HIPCHK(h, f64 ? launch_collide_deferred<double>(c2, A, B, s_off)
+                              : launch_collide_deferred<float>(c2, A, B, s_off));
             HIPCHK(h, hipEventRecord(h->ev_join, h->stream2));
             if (nbig) HIPCHK(h, hipStreamWaitEvent(h->stream, h->ev_table, 0));
         }
         const uint32_t ts = (uint32_t)h->lo.tiles_sparse, td = (uint32_t)(h->lo.total_tiles - h->lo.tiles_sparse);
-        HIPCHK(h, f64 ? launch_collide<double>(c, A, B, -1, 0, ts, s_off)
-                      : launch_collide<float>(c, A, B, -1, 0, ts, s_off));
+        HIPCHK(h, f64 ? launch_collide<double>(c1, A, B, -1, 0, ts, s_off)
+                      : launch_collide<float>(c1, A, B, -1, 0, ts, s_off));
         if (fork) HIPCHK(h, hipStreamWaitEvent(h->stream, h->ev_join, 0));
-        if (h->lo.beads_sparse)
-            HIPCHK(h, f64 ? launch_fixup<double>(c, A, B, 0, h->lo.total_beads, s_off)
-                          : launch_fixup<float>(c, A, B, 0, h->lo.total_beads, s_off));
+        if (h->lo.beads_sparse > (defer ? h->lo.beads_big_sparse : 0))
+            HIPCHK(h, f64 ? launch_fixup<double>(c1, A, B, 0, h->lo.total_beads, s_off)
+                          : launch_fixup<float>(c1, A, B, 0, h->lo.total_beads, s_off));
+        if (defer)
+            HIPCHK(h, f64 ? launch_overflow<double>(c1, A, B, s_off) : launch_overflow<float>(c1, A, B, s_off));
         HIPCHK(h, f64 ? launch_collide_forced<double>(c, A, B, -1, ts, td, s_off)
                       : launch_collide_forced<float>(c, A, B, -1, ts, td, s_off));
     } else {
@@ -528,6 +552,12 @@ lb_status lb_init(const lb_box_desc* boxes, int32_t n_boxes, int32_t precision, 
     c.runimp = (unsigned long long*)sc(lo.sc_items);
     c.slot_of = (uint32_t*)sc(lo.sc_slotof);
     c.sub_rec = (double*)sc(lo.sc_subrec);
+    c.defer_on = 0;
+    c.defer = (uint32_t*)sc(lo.sc_defer);
+    c.defer_list = (uint32_t*)sc(lo.sc_dlist);
+    c.defer_cap = lo.defer_cap;
+    c.ovf = (uint32_t*)sc(lo.sc_ovf);
+    c.ovf_cap = lo.ovf_cap;
     c.vhist = hist_steps > 0 ? (double*)sc(lo.sc_vhist) : nullptr;
     c.hist_len = hist_steps > 0 ? hist_steps : 1;
     c.total_beads = nb;
@@ -835,10 +865,12 @@ lb_status lb_set_launch(lb_handle* h, int32_t batched, int32_t graph_steps)
 {
     if (!h) return fail(nullptr, LB_EINVAL, "null handle");
     if (graph_steps < 0) return fail(h, LB_EINVAL, "graph_steps must be >= 0");
+    if (batched < 0 || batched > 2) return fail(h, LB_EINVAL, "batched must be 0, 1 or 2");
     if (h->pending) return fail(h, LB_ESTATE, "impulses pending from lb_couple");
     HIPCHK(h, hipStreamSynchronize(h->stream));
     drop_graphs(h);
     h->batched = batched ? 1 : 0;
+    h->overlap = batched == 2 ? 0 : 1;
     h->graph_steps = graph_steps + (graph_steps & 1);
     return LB_OK;
 }

@@ -8,7 +8,9 @@ outputs it computes one by one from the GPU's own inputs:
   * the post-collision populations of sampled nodes (random nodes, the box's
     corners and faces, and every node that received an impulse), each found
     after streaming at r + c_i in the next GPU state;
-  * mass, momentum invariant and health after the graph replays."""
+  * mass, momentum invariant and health after the graph replays;
+  * the step with its coupling inside (the chain's tiles collided beside the
+    others) equals the checked step bit for bit."""
 from __future__ import annotations
 
 import numpy as np
@@ -68,6 +70,12 @@ def test_prec256_sampled_parity(orc, prec, pop_tol, dp_tol, bead_tol, f_tol):
     bg = s.export_state()["boxes"][0]
     s.step(1)
     nB = s.export_state()["boxes"][0]["n"]
+    # the same step with the coupling inside it: the collide tiles around the
+    # chain are collided beside the others, after the coupling (same bits)
+    say("prec256: the step from the same state with its coupling inside")
+    s.import_state(A)
+    s.step(1)
+    assert np.array_equal(s.export_state()["boxes"][0]["n"], nB)
     s.close()
 
     o = orc.State(orc.make_box(**p), nA, A["boxes"][0]["x"])

@@ -298,6 +298,14 @@ def test_health_flag_from_nan():
     assert o["health"] & (lbm.HEALTH["density"] | lbm.HEALTH["mach"])
 
 
+def _left_table(x_start, x_end, L):
+    """Beads whose end-of-step base cell lies outside the 3x3x3 node table
+    centred on their start-of-step nearest node (any axis)."""
+    nrst = np.floor(np.mod(x_start, L) + 0.5)
+    base = np.floor(np.mod(x_end, L))
+    return np.any(np.mod(base - nrst + 1, L) > 1, axis=1)
+
+
 # ------------------------------------------------ chains above 256 beads
 @pytest.mark.parametrize("prec", [FP64, FP32])
 @pytest.mark.parametrize("L,N", [(16, 257), (20, 1024), (40, 300)])
@@ -347,6 +355,41 @@ def test_big_chain_in_batch_bitwise():
         single = si.export_state()["boxes"][0]
         for k in ("n", "x", "v", "f", "fc"):
             assert np.array_equal(batch[i][k], single[k]), (i, k)
+
+
+@pytest.mark.parametrize("prec", [FP64, FP32])
+@pytest.mark.parametrize("graph_steps", [0, 4])
+def test_deferred_tiles_equal_fixup_after_collide_bitwise(prec, graph_steps):
+    """Batched steps collide the tiles around a sparse box's large chain beside
+    the other tiles, after the coupling; the other form re-collides the
+    chain's nodes after the collide.  A batch holding every coupling path
+    (sparse large chain, hot sparse large chain whose beads leave their node
+    tables, dense large chain, small chain) gives the same bits both ways."""
+    say("deferred tiles vs fix-up", prec, graph_steps)
+    hot = dict(kT=1.0, therm=0, md_dt=0.01, md_substeps=25, tau_lb=0.25, zeta=1.0, k_fene=7.0, r0_fene=2.0)
+    boxes = [params(L=40, N=300, kT=1e-2, seed=5, box_id=0),
+             params(L=40, N=300, seed=5, box_id=1, **hot),
+             params(L=16, N=300, kT=1e-2, seed=5, box_id=2),
+             params(L=12, N=16, kT=1e-2, seed=5, box_id=3)]
+    xs = [chain(b) for b in boxes]
+    out = []
+    for overlap in (True, False):
+        s = gpu_system(boxes, prec, xs=xs)
+        s.set_launch(batched=True, graph_steps=graph_steps, overlap=overlap)
+        if overlap and graph_steps == 0:
+            left = 0   # the hot box's beads that left their tables (overflow fix-up)
+            for _ in range(12):
+                x_a = s.bead_positions()[300:600]
+                s.step(1)
+                left += int(_left_table(x_a, s.bead_positions()[300:600], 40).sum())
+            assert left > 0
+        else:
+            s.step(12)
+        assert all(o["health"] == 0 for o in s.observables())
+        out.append(s.export_state()["boxes"])
+    for i in range(len(boxes)):
+        for k in ("n", "x", "v", "f", "fc"):
+            assert np.array_equal(out[0][i][k], out[1][i][k]), (i, k)
 
 
 # ------------------------------------------------ several chains per box
@@ -408,14 +451,6 @@ def test_several_chains_in_batch_bitwise():
 
 
 # ------------------------------------------------ fast beads, paper parameters
-def _left_table(x_start, x_end, L):
-    """Beads whose end-of-step base cell lies outside the 3x3x3 node table
-    centred on their start-of-step nearest node (any axis)."""
-    nrst = np.floor(np.mod(x_start, L) + 0.5)
-    base = np.floor(np.mod(x_end, L))
-    return np.any(np.mod(base - nrst + 1, L) > 1, axis=1)
-
-
 @pytest.mark.parametrize("prec", [FP64, FP32])
 @pytest.mark.parametrize("L", [14, 40])
 def test_big_chain_beads_leaving_their_node_table(orc, prec, L):
