@@ -150,7 +150,12 @@ lb_status lb_observables(lb_handle* h, lb_obs* out);
 /* Canonical state as FP64 host data, per box in order: 19 planes of L^3 full
  * populations n_i (plane-major, node r = x + L (y + L z)), then N x 3 each of
  * bead x, v, last total force, last coupling force; preceded by one uint64 step
- * count.  lb_state_host_bytes gives the size.  Synchronises the stream. */
+ * count.  lb_state_host_bytes gives the size.  Synchronises the stream.
+ * Both storages keep deviations n_i - w_i rho0 on the device: an import of
+ * exported FP32 deviations restores them exactly; FP64 deviations come back
+ * to the last bit of n_i (import then export returns the same n_i wherever
+ * n_i lies within a factor 2 of w_i rho0, where the subtraction is exact).
+ * lb_import_state restarts the neighbour lists and fix-up stamps. */
 size_t lb_state_host_bytes(const lb_handle* h);
 lb_status lb_export_state(lb_handle* h, void* host_buf, size_t bytes);
 lb_status lb_import_state(lb_handle* h, const void* host_buf, size_t bytes);
