@@ -61,6 +61,11 @@ struct Ctrl {
     uint32_t ovf_cnt;     // impulses of this step outside the deferred tiles
 };
 
+// Tag of step t in the per-tile deferral stamps: never 0 (the cleared value),
+// so a tile is deferred in step t exactly when its stamp equals this.  Stamps
+// repeat every 2^31 steps; restoring an earlier step count clears them.
+__device__ __forceinline__ uint32_t defer_stamp(uint32_t t) { return t | 0x80000000u; }
+
 enum : uint32_t {
     H_DENSITY = 1u << 0,   // rho <= 0 or NaN at a node
     H_MACH = 1u << 1,      // |u| > 0.3 (lattice units) or NaN

@@ -96,10 +96,10 @@ __device__ __forceinline__ void collide_tile(const BoxDev* __restrict__ boxes, c
     int bi;
     if (defer) {   // batched steps (every tile's box from tile_box)
         // a deferred tile is collided after the coupling, with its impulses
-        // (k_collide_deferred); the flag load goes out beside the box load
-        const uint32_t deferred = defer[tile];
+        // (k_collide_deferred); the stamp load goes out beside the box load
+        const uint32_t st = defer[tile];
         bi = (int)tile_box[tile];
-        if (deferred) return;
+        if (st == defer_stamp(t)) return;
     } else {
         bi = fixed_box >= 0 ? fixed_box : (int)tile_box[tile];
     }
@@ -150,7 +150,9 @@ struct ChainArgs {
     double* vhist; int hist_len; uint64_t total_beads;
     double* tape;              // non-null while replaying a window segment: per substep and bead,
                                // TAPE_REC doubles (see k_couple)
-    uint32_t* defer;           // non-null when the step defers tiles: per collide tile, 1 if deferred
+    uint32_t* defer;           // non-null when the step defers tiles: per collide tile, the stamp of
+                               // the last step that deferred it
+    uint32_t* dclaim;          // per collide tile: stamp of the last step that listed it
     uint32_t* defer_list; uint32_t defer_cap;
     uint32_t* ovf; uint32_t ovf_cap;   // (bead, local node) pairs outside the deferred tiles
 };
@@ -586,7 +588,8 @@ template <typename R>
 __global__ __launch_bounds__(256) void k_near_nodes(const BoxDev* __restrict__ boxes,
                                                     const int32_t* __restrict__ list, const R* __restrict__ A,
                                                     ChainArgs ca, R* __restrict__ near_u, int4* __restrict__ near_c,
-                                                    const R* __restrict__ field, Ctrl* __restrict__ ctrl)
+                                                    const R* __restrict__ field, Ctrl* __restrict__ ctrl,
+                                                    uint32_t s_off)
 {
     const BoxDev& bx = boxes[list[blockIdx.y]];
     const int N = bx.N, L = bx.L;
@@ -611,18 +614,10 @@ __global__ __launch_bounds__(256) void k_near_nodes(const BoxDev* __restrict__ b
     const Upwind up(nx, ny, nz, (uint32_t)L);
     R d[19];
     gather_pre<R, false>(A + bx.pop_off, up, d);
-    if (ca.defer) {
-        // the bead's stencil stays on its table's nodes while it moves less
-        // than half a cell from its nearest node: their tiles wait for the
-        // impulses.  The first thread to flag a tile lists it.  Issued after
-        // the population loads, so the round trips overlap.
-        const uint32_t tile = bx.tile_begin + node / 256u;
-        if (atomicExch(&ca.defer[tile], 1u) == 0u) {
-            const uint32_t k = atomicAdd(&ctrl->defer_cnt, 1u);
-            if (k < ca.defer_cap) ca.defer_list[k] = tile;
-            else atomicOr(&ctrl->health, H_TABLE);
-        }
-    }
+    if (ca.defer)   // the bead's stencil stays on its table's nodes while it moves less
+                    // than half a cell from its nearest node: their tiles wait for the
+                    // impulses (a plain store: every writer stores the same stamp)
+        ca.defer[bx.tile_begin + node / 256u] = defer_stamp(ctrl->step + s_off);
     R u[3];
     node_velocity<R>(d, bx.rho0, 1.0 / bx.tau_lb, u);
     o[0] = u[0]; o[1] = u[1]; o[2] = u[2];
@@ -920,9 +915,9 @@ __global__ __launch_bounds__(WG_MAXB) void k_chain_wg(const BoxDev* __restrict__
 // an impulse on a node whose tile is not deferred (the bead left its table):
 // listed for the end-of-step fix-up
 __device__ __forceinline__ uint32_t list_overflow(const ChainArgs& ca, const BoxDev& bx, uint64_t g, uint32_t node,
-                                                  Ctrl* __restrict__ ctrl)
+                                                  Ctrl* __restrict__ ctrl, uint32_t stamp)
 {
-    if (!ca.defer || ca.defer[bx.tile_begin + node / 256u]) return 0u;
+    if (!ca.defer || ca.defer[bx.tile_begin + node / 256u] == stamp) return 0u;
     const uint32_t k = atomicAdd(&ctrl->ovf_cnt, 1u);
     if (k >= ca.ovf_cap) return H_TABLE;
     ca.ovf[2 * (uint64_t)k] = (uint32_t)g;
@@ -936,7 +931,7 @@ __device__ __forceinline__ uint32_t list_overflow(const ChainArgs& ca, const Box
 // stencil changes and after the last substep (lattice units, fixed point)
 __global__ __launch_bounds__(256) void k_spread(const BoxDev* __restrict__ boxes, const int32_t* __restrict__ list,
                                                 ChainArgs ca, const double* __restrict__ rec,
-                                                Ctrl* __restrict__ ctrl)
+                                                Ctrl* __restrict__ ctrl, uint32_t s_off)
 {
     const BoxDev& bx = boxes[list[blockIdx.y]];
     if (bx.dense) return;   // binned and gathered instead (k_bin_runs, k_gather_imp)
@@ -946,6 +941,7 @@ __global__ __launch_bounds__(256) void k_spread(const BoxDev* __restrict__ boxes
     const int b = tid >> 3, k = tid & 7;
     const uint64_t g = bx.bead_off + (uint64_t)b;
     const double dt = bx.dt, tau = bx.tau_lb;
+    const uint32_t stamp = defer_stamp(ctrl->step + s_off);
     unsigned long long* imp = ca.imp + 3 * bx.node_off;
     uint32_t hb = 0;
     double acc[3] = {0, 0, 0};
@@ -964,7 +960,7 @@ __global__ __launch_bounds__(256) void k_spread(const BoxDev* __restrict__ boxes
                     if (!(fabs(q) < IMP_MAX)) { hb |= H_FIXED; q = 0.0; }
                     atomicAdd(imp + 3 * (uint64_t)cur + c, (unsigned long long)(long long)llrint(q * IMP_SCALE));
                 }
-                hb |= list_overflow(ca, bx, g, cur, ctrl);
+                hb |= list_overflow(ca, bx, g, cur, ctrl, stamp);
             }
             cur = node;
             acc[0] = acc[1] = acc[2] = 0.0;
@@ -982,7 +978,7 @@ __global__ __launch_bounds__(256) void k_spread(const BoxDev* __restrict__ boxes
             if (!(fabs(q) < IMP_MAX)) { hb |= H_FIXED; q = 0.0; }
             atomicAdd(imp + 3 * (uint64_t)cur + c, (unsigned long long)(long long)llrint(q * IMP_SCALE));
         }
-        hb |= list_overflow(ca, bx, g, cur, ctrl);
+        hb |= list_overflow(ca, bx, g, cur, ctrl, stamp);
     }
     if (hb) atomicOr(&ctrl->health, hb);
 }
@@ -1204,8 +1200,9 @@ __global__ __launch_bounds__(256) void k_fixup(const BoxDev* __restrict__ boxes,
 }
 
 // End of a step that deferred tiles (one workgroup): fix the listed nodes
-// outside the deferred tiles, then clear the deferral for the next step.  Runs
-// after the plain collide, the deferred tiles' collide and the coupling.
+// outside the deferred tiles, then reset both list counts for the next step
+// (the per-tile stamps need no clearing).  Runs after the plain collide, the
+// deferred tiles' collide and the coupling.
 template <typename R>
 __global__ __launch_bounds__(256) void k_overflow(const BoxDev* __restrict__ boxes,
                                                    const CollideConst<R>* __restrict__ ccs,
@@ -1214,15 +1211,14 @@ __global__ __launch_bounds__(256) void k_overflow(const BoxDev* __restrict__ box
                                                    R* __restrict__ B, Ctrl* __restrict__ ctrl, uint32_t s_off)
 {
     const uint32_t t = ctrl->step + s_off;
-    const uint32_t n_ovf = min(ctrl->ovf_cnt, ca.ovf_cap), n_def = min(ctrl->defer_cnt, ca.defer_cap);
+    const uint32_t n_ovf = min(ctrl->ovf_cnt, ca.ovf_cap);
     for (uint32_t e = threadIdx.x; e < n_ovf; e += blockDim.x) {
         const uint64_t g = ca.ovf[2 * (uint64_t)e];
         const uint32_t r = ca.ovf[2 * (uint64_t)e + 1];
         const int bi = bead_box[g];
         fixup_node<R>(boxes[bi], ccs, bi, r, ca.imp, claim, A, B, ctrl, t, 0);
     }
-    for (uint32_t k = threadIdx.x; k < n_def; k += blockDim.x) ca.defer[ca.defer_list[k]] = 0u;
-    __syncthreads();   // every thread has read both counts
+    __syncthreads();   // every thread has read the count
     if (threadIdx.x == 0) { ctrl->defer_cnt = 0u; ctrl->ovf_cnt = 0u; }
 }
 
@@ -1271,6 +1267,41 @@ __global__ __launch_bounds__(256) void k_collide_forced(const BoxDev* __restrict
 {
     collide_forced_tile<R>(boxes, ccs, tile_box, fixed_box, tile0 + blockIdx.x, imp, A, B, ctrl,
                            ctrl->step + s_off);
+}
+
+// The deferred tiles of a step as a list, built after the coupling on the
+// chain's stream: thread (bead, table node) of a sparse box claims the node's
+// tile for this step; each wave appends its new tiles with one atomic.
+__global__ __launch_bounds__(256) void k_defer_list(const BoxDev* __restrict__ boxes,
+                                                    const int32_t* __restrict__ list, ChainArgs ca,
+                                                    const int4* __restrict__ near_c, Ctrl* __restrict__ ctrl,
+                                                    uint32_t s_off)
+{
+    const BoxDev& bx = boxes[list[blockIdx.y]];
+    if (bx.dense) return;
+    const int tid = (int)(blockIdx.x * blockDim.x + threadIdx.x);
+    const uint32_t stamp = defer_stamp(ctrl->step + s_off);
+    bool win = false;
+    uint32_t tile = 0;
+    if (tid < bx.N * NEAR) {
+        const int b = tid / NEAR, q = tid - b * NEAR;
+        const int4 nc = near_c[bx.bead_off + (uint64_t)b];
+        const uint32_t node = node_of(nc.x - 1 + q % 3, nc.y - 1 + (q / 3) % 3, nc.z - 1 + q / 9, bx.L);
+        tile = bx.tile_begin + node / 256u;
+        win = ca.dclaim[tile] != stamp && atomicExch(&ca.dclaim[tile], stamp) != stamp;
+    }
+    const unsigned long long m = __ballot(win);
+    if (m == 0ull) return;
+    const int lane = (int)(threadIdx.x & 63u);
+    const int lead = __ffsll((long long)m) - 1;
+    uint32_t base = 0;
+    if (lane == lead) base = atomicAdd(&ctrl->defer_cnt, (uint32_t)__popcll(m));
+    base = __shfl(base, lead);
+    if (win) {
+        const uint32_t k = base + (uint32_t)__popcll(m & ((1ull << lane) - 1ull));
+        if (k < ca.defer_cap) ca.defer_list[k] = tile;
+        else atomicOr(&ctrl->health, H_TABLE);
+    }
 }
 
 // the deferred tiles of a step, after its coupling stage, beside the plain
@@ -1441,7 +1472,7 @@ static ChainArgs chain_args(const LaunchCtx& c)
 {
     return ChainArgs{c.x, c.v, c.f, c.fc, c.nl_cnt, c.nl_idx, c.nl_x0, c.nl_cap, c.imp, c.touched,
                      c.touched_cnt, c.touch_cap, c.nl_rebuilds, c.vhist, c.hist_len, c.total_beads, c.tape,
-                     c.defer_on ? c.defer : nullptr, c.defer_list, c.defer_cap, c.ovf, c.ovf_cap};
+                     c.defer_on ? c.defer : nullptr, c.dclaim, c.defer_list, c.defer_cap, c.ovf, c.ovf_cap};
 }
 
 template <typename R, int W, bool PERSIST>
@@ -1541,7 +1572,7 @@ hipError_t launch_couple_big(const LaunchCtx& c, const void* A, const int32_t* l
         hipLaunchKernelGGL(k_node_field<R>, dim3(c.dense_max_tiles, n_list), dim3(256), 0, c.stream, c.boxes, list,
                            (const R*)A, (R*)c.field);
     hipLaunchKernelGGL(k_near_nodes<R>, dim3((max_n * NEAR + 255) / 256, n_list), dim3(256), 0, c.stream, c.boxes,
-                       list, (const R*)A, ca, (R*)c.near_u, c.near_c, (const R*)c.field, c.ctrl);
+                       list, (const R*)A, ca, (R*)c.near_u, c.near_c, (const R*)c.field, c.ctrl, s_off);
     if (after_table) {
         const hipError_t e = hipEventRecord(after_table, c.stream);
         if (e != hipSuccess) return e;
@@ -1550,7 +1581,10 @@ hipError_t launch_couple_big(const LaunchCtx& c, const void* A, const int32_t* l
                        (const R*)c.near_u, (const int4*)c.near_c, c.sub_rec, c.ctrl, s_off);
     if (c.big_sparse)
         hipLaunchKernelGGL(k_spread, dim3((max_n * 8 + 255) / 256, n_list), dim3(256), 0, c.stream, c.boxes, list,
-                           ca, (const double*)c.sub_rec, c.ctrl);
+                           ca, (const double*)c.sub_rec, c.ctrl, s_off);
+    if (c.defer_on && c.big_sparse)
+        hipLaunchKernelGGL(k_defer_list, dim3((max_n * NEAR + 255) / 256, n_list), dim3(256), 0, c.stream, c.boxes,
+                           list, ca, (const int4*)c.near_c, c.ctrl, s_off);
     if (c.dense_max_tiles) {
         hipLaunchKernelGGL(k_bin_runs, dim3(n_list), dim3(WG_MAXB), 0, c.stream, c.boxes, list, ca,
                            (const double*)c.sub_rec, c.bin_start, c.slot_of);

@@ -46,7 +46,8 @@ struct LaunchCtx {
     // collide and collided with their impulses beside it, once the coupling
     // is done; impulses that land outside them are listed for a fix-up
     int defer_on;                  // this launch defers (the pointers below are always set)
-    uint32_t* defer;               // per collide tile: 1 while deferred
+    uint32_t* defer;               // per collide tile: stamp of the last step that deferred it
+    uint32_t* dclaim;              // per collide tile: stamp of the last step that listed it
     uint32_t* defer_list;          // the deferred tiles, Ctrl::defer_cnt of them
     uint32_t defer_cap;
     uint32_t* ovf;                 // (bead, local node) pairs, Ctrl::ovf_cnt of them

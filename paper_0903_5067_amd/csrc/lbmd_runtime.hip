@@ -48,7 +48,7 @@ struct Layout {
            sc_touched = 0, sc_tcnt = 0, sc_beadbox = 0, sc_nlcnt = 0, sc_nlidx = 0, sc_nlx0 = 0,
            sc_part = 0, sc_stat = 0, sc_chain = 0, sc_vhist = 0, sc_nlreb = 0, sc_biglist = 0, sc_alllist = 0,
            sc_nearu = 0, sc_nearc = 0, sc_subrec = 0, sc_field = 0, sc_binstart = 0, sc_items = 0, sc_slotof = 0,
-           sc_defer = 0, sc_dlist = 0, sc_ovf = 0, scratch_bytes = 0;
+           sc_defer = 0, sc_dclaim = 0, sc_dlist = 0, sc_ovf = 0, scratch_bytes = 0;
     uint64_t beads_big_sparse = 0;                    // beads of the chains above BIG_CHAIN in the other boxes
     uint32_t defer_cap = 0, ovf_cap = 0;              // deferred-tile list and overflow list entries
     int max_N = 0;         // largest chain taking the one-workgroup path
@@ -203,12 +203,13 @@ Layout make_layout(const lb_box_desc* b, int32_t n, int32_t prec, int32_t hist)
         Lo.sc_binstart = o; o = align256(o + std::max<uint64_t>(Lo.bin_entries, 1) * sizeof(uint32_t));
         Lo.sc_items = o; o = align256(o + std::max<uint64_t>(Lo.item_entries, 1) * 24 * sizeof(unsigned long long));
         Lo.sc_slotof = o; o = align256(o + std::max<uint64_t>(Lo.item_entries, 1) * sizeof(uint32_t));
-        // deferred tiles: a flag per collide tile; a tile is listed once, and
-        // a bead's table spans at most 27 tiles.  A bead hands impulses to at
-        // most 8 new nodes per substep.
+        // deferred tiles: two step stamps per collide tile; a tile is listed
+        // once, and a bead's table spans at most 27 tiles.  A bead hands
+        // impulses to at most 8 new nodes per substep.
         Lo.defer_cap = (uint32_t)(27 * Lo.beads_big_sparse);
         Lo.ovf_cap = (uint32_t)(8 * (uint64_t)std::max(Lo.big_max_sub, 1) * Lo.beads_big_sparse);
         Lo.sc_defer = o; o = align256(o + (Lo.beads_big_sparse ? tiles : 1) * sizeof(uint32_t));
+        Lo.sc_dclaim = o; o = align256(o + (Lo.beads_big_sparse ? tiles : 1) * sizeof(uint32_t));
         Lo.sc_dlist = o; o = align256(o + std::max<uint32_t>(Lo.defer_cap, 1) * sizeof(uint32_t));
         Lo.sc_ovf = o; o = align256(o + std::max<uint32_t>(Lo.ovf_cap, 1) * 2 * sizeof(uint32_t));
     }
@@ -287,6 +288,20 @@ lb_status fail(lb_handle* h, lb_status s, const std::string& msg)
         if (e_ != hipSuccess)                                                                   \
             return fail(h, LB_EDEVICE, std::string(#call) + ": " + hipGetErrorString(e_));     \
     } while (0)
+
+// zero every per-node and per-tile step stamp (after the step count is set
+// back); synchronous, outside any graph
+hipError_t clear_step_stamps(lb_handle* h)
+{
+    const Layout& lo = h->lo;
+    if (!lo.total_beads) return hipSuccess;
+    hipError_t e = hipMemset(h->scratch + lo.sc_claim, 0, lo.total_nodes * sizeof(uint32_t));
+    if (e == hipSuccess && lo.beads_big_sparse) {
+        e = hipMemset(h->scratch + lo.sc_defer, 0, lo.total_tiles * sizeof(uint32_t));
+        if (e == hipSuccess) e = hipMemset(h->scratch + lo.sc_dclaim, 0, lo.total_tiles * sizeof(uint32_t));
+    }
+    return e;
+}
 
 // one LB step's launches with relative step offset s_off, from buffer `from`
 lb_status enqueue_step(lb_handle* h, int from, uint32_t s_off, bool couple)
@@ -554,6 +569,7 @@ lb_status lb_init(const lb_box_desc* boxes, int32_t n_boxes, int32_t precision, 
     c.sub_rec = (double*)sc(lo.sc_subrec);
     c.defer_on = 0;
     c.defer = (uint32_t*)sc(lo.sc_defer);
+    c.dclaim = (uint32_t*)sc(lo.sc_dclaim);
     c.defer_list = (uint32_t*)sc(lo.sc_dlist);
     c.defer_cap = lo.defer_cap;
     c.ovf = (uint32_t*)sc(lo.sc_ovf);
@@ -807,8 +823,9 @@ lb_status lb_import_state(lb_handle* h, const void* host_buf, size_t bytes)
     HIPCHK(h, hipMemcpy(h->scratch + lo.sc_ctrl, &ctrl, sizeof ctrl, hipMemcpyHostToDevice));
     std::vector<int32_t> nlcnt(std::max<uint64_t>(lo.total_beads, 1), -2);
     HIPCHK(h, hipMemcpy(h->scratch + lo.sc_nlcnt, nlcnt.data(), nlcnt.size() * sizeof(int32_t), hipMemcpyHostToDevice));
-    // fix-up claims are step stamps: a restored step count must not meet stale ones
-    if (lo.total_beads) HIPCHK(h, hipMemset(h->scratch + lo.sc_claim, 0, lo.total_nodes * sizeof(uint32_t)));
+    // fix-up claims and deferral stamps are step stamps: a restored step
+    // count must not meet stale ones
+    HIPCHK(h, clear_step_stamps(h));
     h->step = stepv;
     return LB_OK;
 }
@@ -945,7 +962,7 @@ lb_status ck_restore(lb_handle* h, char* ws, const WinLayout& w, int j, uint64_t
     HIPCHK(h, hipMemcpy(&ctrl, h->scratch + lo.sc_ctrl, sizeof ctrl, hipMemcpyDeviceToHost));
     ctrl.step = (uint32_t)step;
     HIPCHK(h, hipMemcpy(h->scratch + lo.sc_ctrl, &ctrl, sizeof ctrl, hipMemcpyHostToDevice));
-    if (lo.total_beads) HIPCHK(h, hipMemset(h->scratch + lo.sc_claim, 0, lo.total_nodes * sizeof(uint32_t)));
+    HIPCHK(h, clear_step_stamps(h));
     h->step = step;
     return LB_OK;
 }

@@ -25,11 +25,12 @@ def _gpu():
 
 
 # ---------------------------------------------------------------- fluid only
-@pytest.mark.parametrize("L", [3, 7, 16])
+@pytest.mark.parametrize("L", [2, 3, 7, 16])
 @pytest.mark.parametrize("therm", [2, 1, 0])
 def test_fluid_fp64_matches_oracle(orc, L, therm):
     """Collide+stream of every node, ragged last tile (7^3 = 343 nodes), tiny
-    periodic lattice (3^3), non-unit rates, all thermalization modes."""
+    periodic lattices (2^3, where a node's +c and -c neighbours coincide, and
+    3^3), non-unit rates, all thermalization modes."""
     say("fluid fp64", L, therm)
     p = params(L=L, N=0, kT=0.05, omega_s=1.3, omega_b=0.7, omega_g=1.6, therm=therm, seed=9, box_id=4)
     n0 = initial_pops(orc, p, amp=0.05, seed=L)
