@@ -196,11 +196,10 @@ def adjoint_secondary():
             "grad_finite": bool(np.all(np.isfinite(g)))}
 
 
-def single64_secondary(graph_steps=20):
+def single64_secondary(graph_steps=20, overlap=True):
     """The 64^3 box with its 64-bead chain: step rate and collide kernel."""
     s64, b64, n64, p64 = make_system("single64")
-    if graph_steps:
-        s64.set_launch(batched=True, graph_steps=graph_steps)
+    s64.set_launch(batched=True, graph_steps=graph_steps, overlap=overlap)
     t64, _ = time_steps(s64, 2000, 50)
     c64 = time_collide(s64, 200)
     o64 = s64.observables()[0]
@@ -211,12 +210,11 @@ def single64_secondary(graph_steps=20):
             "rg2_after_2050_steps": round(o64["rg2"], 4), "re2_after_2050_steps": round(o64["re2"], 4)}
 
 
-def batched256_secondary(graph_steps=20):
+def batched256_secondary(graph_steps=20, overlap=True):
     """256 boxes of mixed size, one launch per kernel, against the same boxes
     launched box by box."""
     sb, bb, nb, pb = make_system("batched256")
-    if graph_steps:
-        sb.set_launch(batched=True, graph_steps=graph_steps)
+    sb.set_launch(batched=True, graph_steps=graph_steps, overlap=overlap)
     tb, _ = time_steps(sb, 500, 20)
     cb = time_collide(sb, 100)
     sb.set_launch(batched=False)
@@ -409,10 +407,10 @@ def main():
         print(json.dumps(semidilute_secondary()), flush=True)
         return
     if args.only_single64:
-        print(json.dumps(single64_secondary(args.graph_steps)), flush=True)
+        print(json.dumps(single64_secondary(args.graph_steps, not args.fixup_after_collide)), flush=True)
         return
     if args.only_batched256:
-        print(json.dumps(batched256_secondary(args.graph_steps)), flush=True)
+        print(json.dumps(batched256_secondary(args.graph_steps, not args.fixup_after_collide)), flush=True)
         return
     if args.only_adjoint:
         print(json.dumps(adjoint_secondary()), flush=True)
@@ -478,8 +476,8 @@ def main():
 
     if not args.no_secondary:
         sec = {}
-        sec["single64"] = single64_secondary(args.graph_steps)
-        sec["batched256"] = batched256_secondary(args.graph_steps)
+        sec["single64"] = single64_secondary(args.graph_steps, not args.fixup_after_collide)
+        sec["batched256"] = batched256_secondary(args.graph_steps, not args.fixup_after_collide)
         sec["adjoint32"] = adjoint_secondary()
         sec["thermalization"] = thermalization_secondary()
         sec["semidilute"] = semidilute_secondary()
