@@ -393,6 +393,27 @@ def test_deferred_tiles_equal_fixup_after_collide_bitwise(prec, graph_steps):
             assert np.array_equal(out[0][i][k], out[1][i][k]), (i, k)
 
 
+@pytest.mark.parametrize("prec", [FP64, FP32])
+def test_deferred_tiles_after_restoring_an_earlier_step(prec):
+    """The deferral stamps of later steps must not survive an import that
+    sets the step count back: steps 4..9 replayed from an imported step-3
+    state give the same bits twice, with graph replays in between."""
+    say("deferred tiles, restored step", prec)
+    p = params(L=40, N=300, kT=1e-2, seed=6, box_id=0)
+    s = gpu_system([p], prec, xs=[chain(p)])
+    s.set_launch(batched=True, graph_steps=4)
+    s.step(3)
+    A = s.export_state()
+    runs = []
+    for _ in range(2):
+        s.import_state(A)
+        s.step(6)
+        assert s.observables()[0]["health"] == 0
+        runs.append(s.export_state()["boxes"][0])
+    for k in ("n", "x", "v", "f", "fc"):
+        assert np.array_equal(runs[0][k], runs[1][k]), k
+
+
 # ------------------------------------------------ several chains per box
 @pytest.mark.parametrize("prec", [FP64, FP32])
 @pytest.mark.parametrize("L,M,n", [(12, 6, 8), (16, 20, 16)])
