@@ -66,7 +66,7 @@ typedef enum { LB_THERM_OFF = 0, LB_THERM_STRESS = 1, LB_THERM_ALL = 2 } lb_ther
 #define LB_HEALTH_DENSITY 0x1u  /* rho <= 0 or NaN at some node */
 #define LB_HEALTH_MACH 0x2u     /* |u| > 0.3 lattice units (or NaN) at some node */
 #define LB_HEALTH_FENE 0x4u     /* a bond reached R0 */
-#define LB_HEALTH_TABLE 0x8u    /* node-impulse table overflow */
+#define LB_HEALTH_TABLE 0x8u    /* a node-impulse list overflowed (touched nodes, impulses outside deferred tiles) */
 #define LB_HEALTH_FIXED 0x10u   /* node impulse outside the fixed-point range */
 
 /* One box.  An array of these is a batch of independent boxes. */
