@@ -31,13 +31,13 @@ import numpy as np
 # LB columns of the paper's Table 1 (N = 32; LB time step 0.02): value, error
 PAPER_TABLE1 = {
     10: {"nu": (0.615, 0.005), "re2": (94.56, 1.20), "rg2": (14.83, 0.10), "inv_rh": (0.291, 0.0005),
-         "g1_exponent": (0.640, 0.0005),
+         "g1_exponent": (0.640, 0.0005), "g3_exponent": (1.008, 0.0008),
          "d_cm": (3.914e-3, 1e-6), "tau_tr": (631.36, 4.43)},
     15: {"nu": (0.617, 0.005), "re2": (100.05, 1.26), "rg2": (15.31, 0.11), "inv_rh": (0.290, 0.0005),
-         "g1_exponent": (0.675, 0.0005),
+         "g1_exponent": (0.675, 0.0005), "g3_exponent": (1.020, 0.0008),
          "d_cm": (5.162e-3, 1e-6), "tau_tr": (492.01, 3.56)},
     25: {"nu": (0.619, 0.005), "re2": (100.20, 1.28), "rg2": (15.36, 0.11), "inv_rh": (0.289, 0.0005),
-         "g1_exponent": (0.710, 0.0005),
+         "g1_exponent": (0.710, 0.0005), "g3_exponent": (1.050, 0.0008),
          "d_cm": (6.959e-3, 2e-6), "tau_tr": (368.51, 2.67)},
 }
 # the same table's g1 exponents from LB runs that thermalize the stress modes only
