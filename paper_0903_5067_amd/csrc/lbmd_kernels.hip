@@ -1171,9 +1171,12 @@ __device__ __forceinline__ void fixup_node(const BoxDev& bx, const CollideConst<
     if (h) atomicOr(&ctrl->health, h);
 }
 
-// One thread per touched-node slot of the launched beads.  A node touched by
-// several beads is fixed once (claim stamp).  skip_big: the beads of chains
-// above BIG_CHAIN have their nodes in deferred tiles or in the overflow list.
+// FIX_LANES threads per launched bead; thread j fixes the bead's touched-node
+// slots j, j + FIX_LANES, ... (a bead that keeps its cell fills 8 slots, so
+// one pass is the rule).  A node touched by several beads is fixed once
+// (claim stamp).  skip_big: the beads of chains above BIG_CHAIN have their
+// nodes in deferred tiles or in the overflow list.
+constexpr int FIX_LANES = 16;   // <= touch_cap = 8 (substeps + 1)
 template <typename R>
 __global__ __launch_bounds__(256) void k_fixup(const BoxDev* __restrict__ boxes,
                                                const CollideConst<R>* __restrict__ ccs,
@@ -1184,19 +1187,21 @@ __global__ __launch_bounds__(256) void k_fixup(const BoxDev* __restrict__ boxes,
 {
     const uint32_t e = blockIdx.x * 256u + threadIdx.x;
     if (e >= n_entries) return;
-    const uint64_t g = bead0 + e / (uint32_t)ca.touch_cap;
-    const int k = (int)(e % (uint32_t)ca.touch_cap);
-    // independent loads together: the slot count, the box, the slot (read
-    // for every slot, used below the count) and the step
+    const uint64_t g = bead0 + e / (uint32_t)FIX_LANES;
+    const int j = (int)(e % (uint32_t)FIX_LANES);
+    // independent loads together: the slot count, the box, the first slot
+    // (read for every thread, used below the count) and the step
     const int cnt = ca.touched_cnt[g];
     const int bi = bead_box[g];
-    const uint32_t r = ca.touched[g * ca.touch_cap + k];
+    const uint32_t r0 = ca.touched[g * ca.touch_cap + j];
     const uint32_t t = ctrl->step + s_off;
-    if (k >= cnt) return;
+    if (j >= cnt) return;
     const BoxDev& bx = boxes[bi];
     if (bx.dense) return;   // its collide takes the impulses itself
     if (skip_big && bx.N > BIG_CHAIN) return;
-    fixup_node<R>(bx, ccs, bi, r, ca.imp, claim, A, B, ctrl, t, keep_imp);
+    fixup_node<R>(bx, ccs, bi, r0, ca.imp, claim, A, B, ctrl, t, keep_imp);
+    for (int k = j + FIX_LANES; k < cnt; k += FIX_LANES)
+        fixup_node<R>(bx, ccs, bi, ca.touched[g * ca.touch_cap + k], ca.imp, claim, A, B, ctrl, t, keep_imp);
 }
 
 // End of a step that deferred tiles (one workgroup): fix the listed nodes
@@ -1510,7 +1515,8 @@ hipError_t launch_fixup(const LaunchCtx& c, const void* A, void* B, uint64_t bea
                         uint32_t s_off)
 {
     if (n_beads == 0) return hipSuccess;
-    const uint32_t n = (uint32_t)(n_beads * (uint64_t)c.touch_cap);
+    if (c.touch_cap < FIX_LANES) return hipErrorInvalidValue;
+    const uint32_t n = (uint32_t)(n_beads * (uint64_t)FIX_LANES);
     hipLaunchKernelGGL(k_fixup<R>, dim3((n + 255) / 256), dim3(256), 0, c.stream, c.boxes,
                        (const CollideConst<R>*)c.ccs, c.bead_box, bead0, n, chain_args(c), c.claim,
                        (const R*)A, (R*)B, c.ctrl, s_off, c.keep_imp, c.defer_on);
