@@ -967,14 +967,14 @@ lb_status ck_restore(lb_handle* h, char* ws, const WinLayout& w, int j, uint64_t
     return LB_OK;
 }
 
-// one step with the launches serialised on the main stream; optionally records
-// the impulse field before the fix-up consumes it and the chain's substep tape
-// One LB step of a window from populations A into B.  imp: where the node
+// One LB step of a window from populations A into B, its launches serialised
+// on the main stream: step number = device step counter + s_off (the caller
+// advances the counter once after a run of steps).  imp: where the node
 // impulses go (null: the library's field, consumed by the fix-up; else a
 // zeroed tape slot that keeps them); tape: substep tape (null: none); vh,
 // hist_len: ring of bead velocities after each step (null: the handle's own).
 lb_status window_step(lb_handle* h, const void* A, void* B, unsigned long long* imp, double* tape, double* vh,
-                      int hist_len)
+                      int hist_len, uint32_t s_off)
 {
     const bool f64 = h->prec == LB_FP64;
     LaunchCtx c = h->ctx;
@@ -983,14 +983,13 @@ lb_status window_step(lb_handle* h, const void* A, void* B, unsigned long long* 
     if (vh) { c.vhist = vh; c.hist_len = hist_len; }
     const int nc = (int)h->couple_host.size();
     if (nc)
-        HIPCHK(h, f64 ? launch_couple<double>(c, A, h->couple_list, nc, h->lo.couple_block, 0)
-                      : launch_couple<float>(c, A, h->couple_list, nc, h->lo.couple_block, 0));
-    HIPCHK(h, f64 ? launch_collide<double>(c, A, B, -1, 0, (uint32_t)h->lo.total_tiles, 0)
-                  : launch_collide<float>(c, A, B, -1, 0, (uint32_t)h->lo.total_tiles, 0));
+        HIPCHK(h, f64 ? launch_couple<double>(c, A, h->couple_list, nc, h->lo.couple_block, s_off)
+                      : launch_couple<float>(c, A, h->couple_list, nc, h->lo.couple_block, s_off));
+    HIPCHK(h, f64 ? launch_collide<double>(c, A, B, -1, 0, (uint32_t)h->lo.total_tiles, s_off)
+                  : launch_collide<float>(c, A, B, -1, 0, (uint32_t)h->lo.total_tiles, s_off));
     if (h->lo.total_beads)
-        HIPCHK(h, f64 ? launch_fixup<double>(c, A, B, 0, h->lo.total_beads, 0)
-                      : launch_fixup<float>(c, A, B, 0, h->lo.total_beads, 0));
-    HIPCHK(h, launch_advance(c, 1));
+        HIPCHK(h, f64 ? launch_fixup<double>(c, A, B, 0, h->lo.total_beads, s_off)
+                      : launch_fixup<float>(c, A, B, 0, h->lo.total_beads, s_off));
     h->step += 1;
     return LB_OK;
 }
@@ -1050,14 +1049,20 @@ lb_status lb_window_forward(lb_handle* h, void* d_ws, size_t bytes, int32_t T, i
     h->win_step0 = h->step;
     // the coupling kernel writes the bead velocities after step s into slot
     // s mod T of the window's ring: slot (step0 + t) mod T holds step t
+    int t_adv = 0;   // steps the device counter has been advanced by
     for (int t = 0; t < T; ++t) {
         if (t % k == 0) {
             lb_status s = ck_save(h, ws, w, t / k);
             if (s != LB_OK) return s;
         }
-        lb_status s = window_step(h, h->pop(h->cur), h->pop(1 - h->cur), nullptr, nullptr, (double*)(ws + w.vh), T);
+        lb_status s = window_step(h, h->pop(h->cur), h->pop(1 - h->cur), nullptr, nullptr, (double*)(ws + w.vh), T,
+                                  (uint32_t)(t - t_adv));
         if (s != LB_OK) return s;
         h->cur ^= 1;
+        if ((t + 1) % k == 0 || t + 1 == T) {   // the device counter catches up before a checkpoint
+            HIPCHK(h, launch_advance(h->ctx, (uint32_t)(t + 1 - t_adv)));
+            t_adv = t + 1;
+        }
     }
     if (vhist_host) {
         std::vector<double> ring((size_t)T * nb3);
@@ -1134,9 +1139,10 @@ lb_status lb_window_backward(lb_handle* h, void* d_ws, size_t bytes, const doubl
             st = window_step(h, ws + w.tape_pop + j * popb, ws + w.tape_pop + (j + 1) * popb,
                              (unsigned long long*)(ws + w.tape_imp + (size_t)j * 3 * nodes * 8),
                              (double*)(ws + w.tape_sub + (size_t)j * smax * nbx * TAPE_REC * sizeof(double)),
-                             nullptr, 0);
+                             nullptr, 0, (uint32_t)j);
             if (st != LB_OK) return st;
         }
+        HIPCHK(h, launch_advance(h->ctx, (uint32_t)(t1 - t0)));
         // reverse the segment's steps
         for (int t = t1 - 1; t >= t0; --t) {
             const int j = t - t0;
