@@ -150,6 +150,8 @@ struct ChainArgs {
     double* vhist; int hist_len; uint64_t total_beads;
     double* tape;              // non-null while replaying a window segment: per substep and bead,
                                // TAPE_REC doubles (see k_couple)
+    double* tape_x0;           // with tape: the step's starting x, v (at tape_vo), f (at tape_fo)
+    uint64_t tape_vo, tape_fo;
     uint32_t* defer;           // non-null when the step defers tiles: per collide tile, the stamp of
                                // the last step that deferred it
     uint32_t* dclaim;          // per collide tile: stamp of the last step that listed it
@@ -357,6 +359,13 @@ __global__ __launch_bounds__(MAXT) void k_couple(const BoxDev* __restrict__ boxe
     if (act) {
 #pragma unroll
         for (int c = 0; c < 3; ++c) { x[c] = ca.x[3 * g + c]; v[c] = ca.v[3 * g + c]; f[c] = ca.f[3 * g + c]; }
+        if (ca.tape_x0 && lane == 0)   // the step's starting beads, for the adjoint
+#pragma unroll
+            for (int c = 0; c < 3; ++c) {
+                ca.tape_x0[3 * g + c] = x[c];
+                ca.tape_x0[ca.tape_vo + 3 * g + c] = v[c];
+                ca.tape_x0[ca.tape_fo + 3 * g + c] = f[c];
+            }
     }
     int cb[3] = {-1, -1, -1};     // base cell of the cached stencil
     // node velocities of the cached stencil (MD units), kept in the storage
@@ -1477,6 +1486,7 @@ static ChainArgs chain_args(const LaunchCtx& c)
 {
     return ChainArgs{c.x, c.v, c.f, c.fc, c.nl_cnt, c.nl_idx, c.nl_x0, c.nl_cap, c.imp, c.touched,
                      c.touched_cnt, c.touch_cap, c.nl_rebuilds, c.vhist, c.hist_len, c.total_beads, c.tape,
+                     c.tape_x0, c.tape_vo, c.tape_fo,
                      c.defer_on ? c.defer : nullptr, c.dclaim, c.defer_list, c.defer_cap, c.ovf, c.ovf_cap};
 }
 

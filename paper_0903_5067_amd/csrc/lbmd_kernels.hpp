@@ -30,6 +30,8 @@ struct LaunchCtx {
     int32_t* nl_cnt; uint16_t* nl_idx; double* nl_x0; int nl_cap;
     double* vhist; int hist_len; uint64_t total_beads;
     double* tape;                  // substep tape while replaying an adjoint window segment (else null)
+    double* tape_x0;               // with tape: the step's starting bead x; v and f follow at tape_vo, tape_fo
+    uint64_t tape_vo, tape_fo;     // (in doubles), the state's own layout
     int keep_imp;                  // 1: the fix-up leaves the node impulses in place (adjoint replay records them)
     // chains above BIG_CHAIN beads
     void* near_u;                  // [total beads][27][3] node velocities around each bead (storage precision)

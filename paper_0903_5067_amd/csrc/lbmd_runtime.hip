@@ -971,14 +971,18 @@ lb_status ck_restore(lb_handle* h, char* ws, const WinLayout& w, int j, uint64_t
 // on the main stream: step number = device step counter + s_off (the caller
 // advances the counter once after a run of steps).  imp: where the node
 // impulses go (null: the library's field, consumed by the fix-up; else a
-// zeroed tape slot that keeps them); tape: substep tape (null: none); vh,
-// hist_len: ring of bead velocities after each step (null: the handle's own).
-lb_status window_step(lb_handle* h, const void* A, void* B, unsigned long long* imp, double* tape, double* vh,
-                      int hist_len, uint32_t s_off)
+// zeroed tape slot that keeps them); tape: substep tape (null: none), with
+// tape_beads the step's starting x, v, f in the state's layout; vh, hist_len:
+// ring of bead velocities after each step (null: the handle's own).
+lb_status window_step(lb_handle* h, const void* A, void* B, unsigned long long* imp, double* tape,
+                      double* tape_beads, double* vh, int hist_len, uint32_t s_off)
 {
     const bool f64 = h->prec == LB_FP64;
     LaunchCtx c = h->ctx;
     c.tape = tape;
+    c.tape_x0 = tape ? tape_beads : nullptr;
+    c.tape_vo = (h->lo.st_v - h->lo.st_x) / sizeof(double);
+    c.tape_fo = (h->lo.st_f - h->lo.st_x) / sizeof(double);
     if (imp) { c.imp = imp; c.keep_imp = 1; }
     if (vh) { c.vhist = vh; c.hist_len = hist_len; }
     const int nc = (int)h->couple_host.size();
@@ -1055,8 +1059,8 @@ lb_status lb_window_forward(lb_handle* h, void* d_ws, size_t bytes, int32_t T, i
             lb_status s = ck_save(h, ws, w, t / k);
             if (s != LB_OK) return s;
         }
-        lb_status s = window_step(h, h->pop(h->cur), h->pop(1 - h->cur), nullptr, nullptr, (double*)(ws + w.vh), T,
-                                  (uint32_t)(t - t_adv));
+        lb_status s = window_step(h, h->pop(h->cur), h->pop(1 - h->cur), nullptr, nullptr, nullptr,
+                                  (double*)(ws + w.vh), T, (uint32_t)(t - t_adv));
         if (s != LB_OK) return s;
         h->cur ^= 1;
         if ((t + 1) % k == 0 || t + 1 == T) {   // the device counter catches up before a checkpoint
@@ -1134,12 +1138,11 @@ lb_status lb_window_backward(lb_handle* h, void* d_ws, size_t bytes, const doubl
         HIPCHK(h, hipMemsetAsync(ws + w.tape_imp, 0, (size_t)(t1 - t0) * 3 * nodes * 8, h->stream));
         for (int t = t0; t < t1; ++t) {
             const int j = t - t0;
-            HIPCHK(h, hipMemcpyAsync(ws + w.tape_beads + (size_t)j * w.bspan, h->state + lo.st_x, w.bspan,
-                                     hipMemcpyDeviceToDevice, h->stream));
+            // the coupling kernel records the step's starting beads in slot j
             st = window_step(h, ws + w.tape_pop + j * popb, ws + w.tape_pop + (j + 1) * popb,
                              (unsigned long long*)(ws + w.tape_imp + (size_t)j * 3 * nodes * 8),
                              (double*)(ws + w.tape_sub + (size_t)j * smax * nbx * TAPE_REC * sizeof(double)),
-                             nullptr, 0, (uint32_t)j);
+                             (double*)(ws + w.tape_beads + (size_t)j * w.bspan), nullptr, 0, (uint32_t)j);
             if (st != LB_OK) return st;
         }
         HIPCHK(h, launch_advance(h->ctx, (uint32_t)(t1 - t0)));
