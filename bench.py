@@ -266,8 +266,11 @@ def cpu_baseline(preset, budget_s=20.0):
     same box and chain, as many as fit a ~20 s budget (at least one).
     Returns the report and, for the precision study, the oracle's results as
     plain arrays: step count, populations, observables, weights."""
+    import tempfile
     import lbinputs
     import oracle
+    build_dir = tempfile.mkdtemp(prefix="lbmd_oracle_")
+    oracle.use_tuned_build(build_dir)
     p = lbinputs.box_params(preset)
     L = int(p["L"])
     c, w, e, b = oracle.tables()
@@ -295,15 +298,11 @@ def cpu_baseline(preset, budget_s=20.0):
     st.run(1)
     t_one = time.perf_counter() - t0
     oracle.set_threads(cores)
-    model = ""
-    try:
-        with open("/proc/cpuinfo") as f:
-            model = next((l.split(":", 1)[1].strip() for l in f if l.startswith("model name")), "")
-    except OSError:
-        pass
+    model = host_cpu()
     rep = {"value": round(mlups, 3), "unit": "MLUPS", "cores": cores, "kind": "oracle",
            "sample": f"{steps} full LB step(s) of the {L}^3 box with its N={p['N']} chain (after 1 untimed), "
-                     f"FP64 oracle, {t1:.1f} s",
+                     f"FP64 oracle built g++ {' '.join(oracle.TUNED_FLAGS)} -ffp-contract=off on this host, "
+                     f"OpenMP over z-planes, {t1:.1f} s",
            "value_1core": round(L ** 3 / t_one / 1e6, 3), "sample_1core": f"1 further step on 1 thread, {t_one:.1f} s",
            "cpu_model": model}
     oo = st.observables()
@@ -311,6 +310,30 @@ def cpu_baseline(preset, budget_s=20.0):
            "obs": {"mass": oo[0], "p_fluid": oo[4:7], "p_total": oo[10:13], "com": oo[13:16], "rg2": oo[16],
                    "re2": oo[17], "mode_sq": oo[19:38]}}
     return rep, ref
+
+
+def host_cpu() -> str:
+    """The host CPU as lscpu names it (model, family/model/stepping, sockets,
+    cores, threads), or /proc/cpuinfo's model name without lscpu."""
+    import subprocess
+    keep = ("Model name", "Vendor ID", "CPU family", "Model:", "Stepping", "Socket(s)",
+            "Core(s) per socket", "Thread(s) per core", "CPU(s):", "CPU max MHz")
+    try:
+        out = subprocess.run(["lscpu"], capture_output=True, text=True, timeout=20).stdout
+        parts = []
+        for line in out.splitlines():
+            if line.strip().startswith(keep) and ":" in line:
+                k, v = line.split(":", 1)
+                parts.append(f"{k.strip()}: {v.strip()}")
+        if parts:
+            return "; ".join(parts)
+    except (OSError, subprocess.SubprocessError):
+        pass
+    try:
+        with open("/proc/cpuinfo") as f:
+            return next((l.split(":", 1)[1].strip() for l in f if l.startswith("model name")), "")
+    except OSError:
+        return ""
 
 
 def _obs_errors(a, b):

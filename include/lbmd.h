@@ -118,39 +118,76 @@ typedef struct {
     uint64_t step;        /* LB steps taken since init */
 } lb_obs;
 
-/* Device bytes the caller must provide.  hist_steps >= 0: depth of the ring
- * of bead velocities kept at the end of each LB step (0 = none).  Fails with
- * LB_EINVAL on an invalid box description. */
+/* Device bytes the caller must provide for the boxes (Sec. II.E: a cubic
+ * periodic box of L^3 sites per chain; Sec. III.C: several such boxes).
+ * state_bytes: two population buffers of 19 values per site (the D3Q19
+ * velocity set of Sec. II.B, stored as deviations n_i - w_i rho0, FP64 or
+ * FP32 per `precision`) plus bead x, v, F and coupling force; scratch_bytes:
+ * node impulses, tables, reduction partials.  hist_steps >= 0: depth of the
+ * ring of bead velocities kept at the end of each LB step (0 = none).  Both
+ * outputs are host size_t the caller owns.  Fails with LB_EINVAL on an invalid
+ * box description (ranges listed in lb_box_desc) or a NULL output pointer;
+ * nothing is written then. */
 lb_status lb_query_sizes(const lb_box_desc* boxes, int32_t n_boxes, int32_t precision,
                          int32_t hist_steps, size_t* state_bytes, size_t* scratch_bytes);
 
-/* Set up the boxes: fluid at rest at n_i = w_i rho0 (deviations zero), beads
- * at bead_x0 (host, [sum N][3] FP64, boxes in order, unwrapped coordinates),
- * velocities zero, last force = conservative force.  bead_x0 may be NULL only
- * when every box has N = 0.  LB_EINVAL if any initial bond is >= R0.
+/* Set up the boxes of Sec. II.E (cubic, periodic, fluid density rho0, the
+ * relaxation rates and kT of Sec. II.B, FENE and LJ parameters of Sec. II.A,
+ * MD step md_dt and LB step tau_lb): fluid at rest at n_i = w_i rho0
+ * (deviations zero), beads at bead_x0 (host, [sum N][3] FP64, boxes in order,
+ * unwrapped coordinates, read once and not kept), velocities zero, last force
+ * = conservative force (the FENE + LJ force of Sec. II.A).  d_state and
+ * d_scratch: caller-owned device buffers of lb_query_sizes bytes, 256-byte
+ * aligned; both are cleared here.  bead_x0 may be NULL only when every box has
+ * N = 0.  LB_EINVAL for an invalid box, NULL or unaligned buffers, or an
+ * initial bond >= R0 (the FENE potential is undefined there); LB_EDEVICE if a
+ * HIP call fails.  On failure *out is NULL and nothing needs freeing.
  * stream: hipStream_t as void*, NULL = the library creates one. */
 lb_status lb_init(const lb_box_desc* boxes, int32_t n_boxes, int32_t precision, int32_t hist_steps,
                   const double* bead_x0, void* d_state, void* d_scratch, void* stream,
                   lb_handle** out);
 
-/* Run the md_substeps MD steps of the current LB step in the fluid frozen at
- * the current (pre-collision) state and accumulate the node impulses; the
- * fluid is not updated.  The next lb_step consumes these impulses instead of
- * coupling again.  LB_ESTATE if called twice without an lb_step between. */
+/* The coupling of Sec. II.B (coupling paragraph) for one LB step: the
+ * md_substeps MD steps (Sec. II.E, time steps) of every chain in the fluid
+ * velocity frozen at the current (pre-collision) state, interpolated
+ * trilinearly from the surrounding sites; the friction force -zeta (v - u)
+ * and the Langevin force act on each bead, and their momentum is taken from
+ * the same sites.  The node impulses accumulate on the device; the fluid is
+ * not updated.  The next lb_step consumes these impulses instead of coupling
+ * again.  Asynchronous on the handle's stream.  LB_ESTATE if called twice
+ * without an lb_step between, LB_EDEVICE on a launch failure. */
 lb_status lb_couple(lb_handle* h);
 
-/* n_steps full LB steps: [couple ; collide with the impulses ; stream] each.
- * Asynchronous on the handle's stream. */
+/* n_steps full LB steps, each the coupling above followed by the LB equation
+ * of Sec. II.B: every site's populations are collided in mode space (stress
+ * modes relaxed toward the second-order equilibrium, ghost modes relaxed,
+ * each non-conserved mode given noise of the variance the
+ * fluctuation-dissipation theorem fixes, the node impulse applied), then
+ * moved to the neighbour along c_i (periodic).  One LB step is tau_lb =
+ * md_substeps * md_dt (Sec. II.E, time steps).  n_steps >= 0.  Asynchronous on
+ * the handle's stream; numeric trouble sets the health word.  LB_EINVAL for
+ * n_steps < 0, LB_EDEVICE on a launch or graph failure. */
 lb_status lb_step(lb_handle* h, int64_t n_steps);
 
-/* Compute observables of every box into out[n_boxes] (host); synchronises the
- * stream.  Returns LB_ENUMERIC (and still fills out) if a health bit is set. */
+/* Observables of every box into out[n_boxes] (host, caller-owned): the
+ * conserved mass and momentum of the LB equation (Sec. II.B: the collision
+ * conserves rho and the momentum; the coupling conserves the total), the
+ * chain's R_g^2 and R_e^2 and centre of mass (Sec. III.A), mode sums and the
+ * count of negative populations (Sec. II.E, choice of parameters: the step is
+ * chosen so that they stay rare).  FP64 sums in a fixed order, so repeated
+ * calls on one state give identical bits.  Synchronises the stream.  Returns
+ * LB_ENUMERIC (and still fills out) if a health bit is set, LB_EINVAL for
+ * NULL arguments, LB_EDEVICE on a HIP failure. */
 lb_status lb_observables(lb_handle* h, lb_obs* out);
 
 /* Canonical state as FP64 host data, per box in order: 19 planes of L^3 full
- * populations n_i (plane-major, node r = x + L (y + L z)), then N x 3 each of
- * bead x, v, last total force, last coupling force; preceded by one uint64 step
- * count.  lb_state_host_bytes gives the size.  Synchronises the stream.
+ * populations n_i(r, t) of the LB equation (Sec. II.B; pre-collision, plane-
+ * major, node r = x + L (y + L z)), then N x 3 each of bead x, v, last total
+ * force, last coupling force; preceded by one uint64 step count.
+ * lb_state_host_bytes gives the size; host_buf is caller-owned.  LB_ENOMEM if
+ * bytes is too small, LB_ESTATE (import) with impulses pending, LB_ENUMERIC
+ * (export, buffer still filled) if a health bit is set.  Synchronises the
+ * stream.
  * Both storages keep deviations n_i - w_i rho0 on the device: an import of
  * exported FP32 deviations restores them exactly; FP64 deviations come back
  * to the last bit of n_i (import then export returns the same n_i wherever
@@ -160,12 +197,18 @@ size_t lb_state_host_bytes(const lb_handle* h);
 lb_status lb_export_state(lb_handle* h, void* host_buf, size_t bytes);
 lb_status lb_import_state(lb_handle* h, const void* host_buf, size_t bytes);
 
-/* Node impulses pending after lb_couple, scattered into dense host arrays
- * [3][L^3] (lattice units) per box in order; zero where no bead acted. */
+/* Node impulses pending after lb_couple (the momentum the coupling of
+ * Sec. II.B takes from the sites around each bead), scattered into dense host
+ * arrays [3][L^3] (lattice units) per box in order; zero where no bead acted.
+ * host_dense is caller-owned; LB_ENOMEM if bytes is too small.  Synchronises
+ * the stream. */
 lb_status lb_pending_impulse(lb_handle* h, double* host_dense, size_t bytes);
 
 /* Bead velocities stored at the end of LB step `step` (0-based), [sum N][3]
- * FP64 host.  LB_EINVAL if that step is no longer in the ring. */
+ * FP64 host, caller-owned: the samples of the velocity autocorrelation that
+ * Sec. III.B's dynamics are built from.  LB_ESTATE without a ring
+ * (hist_steps = 0 at init), LB_EINVAL if that step is no longer in the ring,
+ * LB_ENOMEM if bytes is too small.  Synchronises the stream. */
 lb_status lb_velocity_history(lb_handle* h, int64_t step, double* host_out, size_t bytes);
 
 /* Bead positions at the current LB-step boundary, unwrapped (a chain's
@@ -174,15 +217,19 @@ lb_status lb_velocity_history(lb_handle* h, int64_t step, double* host_out, size
  * LB_ESTATE between lb_couple and lb_step (the positions are mid-step). */
 lb_status lb_bead_positions(lb_handle* h, double* host_out, size_t bytes);
 
-/* Launch structure: batched = 1 advances every box with one launch per kernel
+/* Launch structure of lb_step (the arithmetic is that of lb_step, Sec. II.B,
+ * in every form): batched = 1 advances every box with one launch per kernel
  * (the default); batched = 0 launches per box (the plain form).  In batched
  * steps the collide tiles around chains above 256 beads in boxes they do not
  * cover densely are collided beside the other tiles once the chain's
  * impulses are in; batched = 2 re-collides the chain's nodes after the
  * collide instead.  All forms compute the same bits.
  * graph_steps > 0 records that many LB steps (rounded up to even) in a HIP
- * graph and replays it; 0 launches kernels directly.  LB_EINVAL for batched
- * outside 0..2 or graph_steps < 0. */
+ * graph and replays it; 0 launches kernels directly.  The graphs of both
+ * buffer parities are recorded and instantiated here, before returning
+ * (synchronous), so that lb_step only replays them.  LB_EINVAL for batched
+ * outside 0..2 or graph_steps < 0, LB_ESTATE with impulses pending,
+ * LB_EDEVICE if capture or instantiation fails. */
 lb_status lb_set_launch(lb_handle* h, int32_t batched, int32_t graph_steps);
 
 /* ---- adjoint window (gradient of a loss of the bead velocities) ----------
@@ -197,23 +244,34 @@ lb_status lb_set_launch(lb_handle* h, int32_t batched, int32_t graph_steps);
  * memory owned by the caller, lb_window_bytes(h, T, k) bytes, 256-aligned,
  * kept unchanged between the forward and backward calls. */
 size_t lb_window_bytes(const lb_handle* h, int32_t T, int32_t k);
-/* Run T steps from the current state, checkpointing every k steps; bead
- * velocities after each step go to vhist_host [T][sum N][3] (may be NULL). */
+/* Run T steps (the lb_step of Sec. II.B) from the current state,
+ * checkpointing every k steps into d_ws; bead velocities after each step go to
+ * vhist_host [T][sum N][3] (host, caller-owned, may be NULL).  Synchronous.
+ * LB_EINVAL for T or k <= 0 or a chain above 256 beads, LB_ENOMEM for a short
+ * workspace, LB_ESTATE with impulses pending. */
 lb_status lb_window_forward(lb_handle* h, void* d_ws, size_t bytes, int32_t T, int32_t k, double* vhist_host);
-/* dj_host [T][sum N][3] = dJ/dv; grad_host [n_boxes][3].  Leaves the state at
- * the end of the window.  LB_ESTATE without a recorded forward window. */
+/* Reverse sweep of the recorded window: dj_host [T][sum N][3] = dJ/dv (host,
+ * read), grad_host [n_boxes][3] = dJ/d(omega_shear, omega_bulk, zeta) (host,
+ * written).  The adjoint of each step reverses the LB equation and the
+ * coupling of Sec. II.B in FP64.  Leaves the state at the end of the window.
+ * Synchronous.  LB_ESTATE without a recorded forward window, LB_ENOMEM for a
+ * short workspace. */
 lb_status lb_window_backward(lb_handle* h, void* d_ws, size_t bytes, const double* dj_host, double* grad_host);
-/* Restore the state at the start of the recorded window. */
+/* Restore the state at the start of the recorded window (from the first
+ * checkpoint in d_ws).  LB_ESTATE without a recorded window. */
 lb_status lb_window_rewind(lb_handle* h, void* d_ws, size_t bytes);
-/* Change a box's shear and bulk rates and bead friction (same ranges as in
- * lb_box_desc). */
+/* Change a box's shear and bulk relaxation rates (the stress-mode rates of
+ * the collision, Sec. II.B) and bead friction zeta_bare (Sec. II.B, coupling
+ * paragraph); the ranges are those of lb_box_desc (LB_EINVAL otherwise).
+ * Synchronises the stream; takes effect at the next step. */
 lb_status lb_set_rates(lb_handle* h, int32_t box, double omega_shear, double omega_bulk, double zeta);
 
-/* Benchmark aid: enqueue n launches of the fused collide+stream kernel of
- * every box from the current state into the other buffer, with no impulses
- * and without advancing the state (the other buffer is overwritten by the
- * next step anyway).  Lets a caller time the dominant kernel with events on
- * the handle's stream. */
+/* Benchmark aid: enqueue n launches of the fused collide+stream kernel (the
+ * LB equation of Sec. II.B at every site) of every box from the current state
+ * into the other buffer, with no impulses and without advancing the state
+ * (the other buffer is overwritten by the next step anyway).  Lets a caller
+ * time the dominant kernel with events on the handle's stream.  LB_EINVAL for
+ * n < 0. */
 lb_status lb_collide_only(lb_handle* h, int32_t n);
 
 /* ---- launch-shape autotuning of the collide+stream kernel ---------------
@@ -224,14 +282,20 @@ lb_status lb_collide_only(lb_handle* h, int32_t n);
  * lb_autotune times every variant on the handle's own state (two sweeps; in
  * each, reps launches per variant after two untimed ones, HIP events on the
  * handle's stream, no state change), selects the fastest, drops recorded
- * graphs, and writes each variant's faster sweep average in microseconds per
- * launch to times_us[LB_N_COLLIDE_VARIANTS] (may be NULL) and the choice to
- * *chosen (may be NULL).  lb_set_collide_variant forces one. */
+ * graphs (recording them again for the chosen shape), and writes each
+ * variant's faster sweep average in microseconds per launch to
+ * times_us[LB_N_COLLIDE_VARIANTS] (may be NULL) and the choice to *chosen (may
+ * be NULL).  lb_set_collide_variant forces one (LB_EINVAL out of range).
+ * The arithmetic is the LB equation of Sec. II.B in every shape. */
 #define LB_N_COLLIDE_VARIANTS 10
 lb_status lb_autotune(lb_handle* h, int32_t reps, float* times_us, int32_t* chosen);
 lb_status lb_set_collide_variant(lb_handle* h, int32_t variant);
 
-/* The stream the handle enqueues on (hipStream_t as void*). */
+/* Plumbing, no paper passage: the stream the handle enqueues on (hipStream_t
+ * as void*); lb_free waits for the handle's work and releases its host
+ * metadata, graphs and own streams (never caller memory; NULL is a no-op);
+ * lb_last_error gives the message of the last failing call on h (NULL: of
+ * the calling thread's last lb_query_sizes / lb_init failure). */
 void* lb_stream(const lb_handle* h);
 
 void lb_free(lb_handle* h);

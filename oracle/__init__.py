@@ -17,12 +17,16 @@ Parity status per function (what pins it is listed in the test files):
   collide_stream       pinned (brute force, equilibrium, conservation,
                                equipartition, shear and sound damping)
   couple               pinned (force = -grad V, exact linear interpolation,
-                               momentum invariant, bead equipartition; several
-                               chains per box: -grad V with bonds along each
-                               chain only, far-apart chains move bit for bit
-                               as they do alone)
+                               momentum invariant, bead equipartition; the
+                               substep order: a free chain's energy has no
+                               drift and second-order fluctuation, which
+                               planted reorderings fail; several chains per
+                               box: -grad V with bonds along each chain only,
+                               far-apart chains move bit for bit as they do
+                               alone)
   observables          pinned (closed forms on hand-made states, one chain
-                               and several rods)
+                               and several rods; negative-population count on
+                               states with a known count)
   window_tangent       pinned (central finite differences of the oracle's own
                                window; values identical to run())
   specific noise realisations / long trajectories: parity unpinned beyond the
@@ -48,15 +52,24 @@ OBS = {
 }
 
 
-def build(verbose: bool = False) -> str:
-    """Compile the oracle with g++ (plain -O2, no fast-math, no FMA contraction)."""
-    cmd = ["g++", "-O2", "-std=c++17", "-fopenmp", "-ffp-contract=off", "-fPIC", "-shared",
-           "-o", _LIB + ".tmp", _SRC, "-lm"]
+TUNED_FLAGS = ["-O3", "-march=native"]
+
+
+def build(verbose: bool = False, out: str | None = None, tuned: bool = False) -> str:
+    """Compile the oracle with g++: plain -O2 (the portable build the tests
+    load), or with ``tuned`` -O3 -march=native for the host it is built on
+    (the timed CPU baseline; built where it runs, since the instruction set
+    differs between hosts).  Never fast-math, never FMA contraction, so both
+    builds compute the same bits."""
+    dst = out or _LIB
+    opt = TUNED_FLAGS if tuned else ["-O2"]
+    cmd = ["g++", *opt, "-std=c++17", "-fopenmp", "-ffp-contract=off", "-fPIC", "-shared",
+           "-o", dst + ".tmp", _SRC, "-lm"]
     if verbose:
         print(" ".join(cmd))
     subprocess.run(cmd, check=True)
-    os.replace(_LIB + ".tmp", _LIB)
-    return _LIB
+    os.replace(dst + ".tmp", dst)
+    return dst
 
 
 class Box(ctypes.Structure):
@@ -78,12 +91,25 @@ class Box(ctypes.Structure):
 _lib = None
 
 
-def lib():
+def use_tuned_build(directory: str) -> str:
+    """Build the -O3 -march=native oracle into ``directory`` and route every
+    later call of this module to it (for timing on the host that runs it).
+    Returns the library path."""
+    global _lib
+    path = build(out=os.path.join(directory, "liblbmd_oracle_tuned.so"), tuned=True)
+    _lib = None
+    lib(path)
+    return path
+
+
+def lib(path: str | None = None):
     global _lib
     if _lib is None:
-        if not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
-            build()
-        _lib = ctypes.CDLL(_LIB)
+        if path is None:
+            path = _LIB
+            if not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
+                build()
+        _lib = ctypes.CDLL(path)
         dp = ctypes.POINTER(ctypes.c_double)
         u32p = ctypes.POINTER(ctypes.c_uint32)
         bp = ctypes.POINTER(Box)

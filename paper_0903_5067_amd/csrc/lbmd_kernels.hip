@@ -1346,14 +1346,43 @@ __global__ void k_advance(Ctrl* ctrl, uint32_t n)
 // Per tile of 256 nodes: FP64 sums of mass deviation, momentum, squared modes,
 // negative population count.  Layout of a record: [0] sum drho, [1..3] j,
 // [4] neg count, [5..23] sum m_k^2 (m of the deviations; m_0 = drho).
-constexpr int NSTAT = 24;
+// Every sum is a fixed tree (butterfly within each wavefront, then the four
+// wavefronts in order, then fixed chunks of a box's tiles, then the chunks in
+// order), so a state gives the same bits on every call and in any batch.
+constexpr int NSTAT = NSTAT_REC;
+
+// sum over the 64 lanes of a wavefront by xor butterfly: every lane ends with
+// the same bits (each stage adds the same two values in either order)
+__device__ __forceinline__ double wave_sum(double v)
+{
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+    return v;
+}
+
+// sum of acc[0..NV-1] over a 256-thread block: per wavefront, then wavefronts
+// 0..3 in order; the result is valid in threads 0..NV-1 (thread k holds sum k)
+template <int NV>
+__device__ __forceinline__ double block_sum256(double acc[NV], double (*lds)[NV])
+{
+    const int wv_ = threadIdx.x >> 6, ln = threadIdx.x & 63;
+#pragma unroll
+    for (int k = 0; k < NV; ++k) {
+        const double s = wave_sum(acc[k]);
+        if (ln == 0) lds[wv_][k] = s;
+    }
+    __syncthreads();
+    double r = 0.0;
+    if ((int)threadIdx.x < NV) r = ((lds[0][threadIdx.x] + lds[1][threadIdx.x]) + lds[2][threadIdx.x]) + lds[3][threadIdx.x];
+    return r;
+}
 
 template <typename R>
 __global__ __launch_bounds__(256) void k_stats(const BoxDev* __restrict__ boxes,
                                                const uint32_t* __restrict__ tile_box,
                                                const R* __restrict__ A, double* __restrict__ part)
 {
-    __shared__ double red[NSTAT][256];
+    __shared__ double red[4][NSTAT];
     const uint32_t tile = blockIdx.x;
     const int bi = (int)tile_box[tile];
     const BoxDev& bx = boxes[bi];
@@ -1377,35 +1406,40 @@ __global__ __launch_bounds__(256) void k_stats(const BoxDev* __restrict__ boxes,
 #pragma unroll
         for (int k = 0; k < 19; ++k) acc[5 + k] = m[k] * m[k];
     }
-#pragma unroll
-    for (int k = 0; k < NSTAT; ++k) red[k][threadIdx.x] = acc[k];
-    __syncthreads();
-    for (int w = 128; w > 0; w >>= 1) {
-        if ((int)threadIdx.x < w)
-            for (int k = 0; k < NSTAT; ++k) red[k][threadIdx.x] += red[k][threadIdx.x + w];
-        __syncthreads();
-    }
-    if (threadIdx.x < NSTAT) part[(uint64_t)tile * NSTAT + threadIdx.x] = red[threadIdx.x][0];
+    const double s = block_sum256<NSTAT>(acc, red);
+    if (threadIdx.x < NSTAT) part[(uint64_t)tile * NSTAT + threadIdx.x] = s;
 }
 
-// one block per box: reduce the box's tile records in a fixed order
-__global__ __launch_bounds__(256) void k_stats_final(const BoxDev* __restrict__ boxes,
-                                                     const double* __restrict__ part, double* __restrict__ out)
+// grid (STAT_CHUNKS, boxes): block (c, box) sums the tile records of chunk c
+// of the box (a fixed split of its tiles into STAT_CHUNKS ranges)
+__global__ __launch_bounds__(256) void k_stats_mid(const BoxDev* __restrict__ boxes,
+                                                   const double* __restrict__ part, double* __restrict__ mid)
 {
-    __shared__ double red[NSTAT][256];
-    const BoxDev& bx = boxes[blockIdx.x];
+    __shared__ double red[4][NSTAT];
+    const BoxDev& bx = boxes[blockIdx.y];
+    const uint32_t per = (bx.n_tiles + STAT_CHUNKS - 1) / STAT_CHUNKS;
+    const uint32_t t0 = blockIdx.x * per, t1 = min(bx.n_tiles, t0 + per);
     double acc[NSTAT];
+#pragma unroll
     for (int k = 0; k < NSTAT; ++k) acc[k] = 0.0;
-    for (uint32_t tt = threadIdx.x; tt < bx.n_tiles; tt += 256)
-        for (int k = 0; k < NSTAT; ++k) acc[k] += part[(uint64_t)(bx.tile_begin + tt) * NSTAT + k];
-    for (int k = 0; k < NSTAT; ++k) red[k][threadIdx.x] = acc[k];
-    __syncthreads();
-    for (int w = 128; w > 0; w >>= 1) {
-        if ((int)threadIdx.x < w)
-            for (int k = 0; k < NSTAT; ++k) red[k][threadIdx.x] += red[k][threadIdx.x + w];
-        __syncthreads();
+    for (uint32_t tt = t0 + threadIdx.x; tt < t1; tt += 256) {
+        const double* rec = part + (uint64_t)(bx.tile_begin + tt) * NSTAT;
+#pragma unroll
+        for (int k = 0; k < NSTAT; ++k) acc[k] += rec[k];
     }
-    if (threadIdx.x < NSTAT) out[(uint64_t)blockIdx.x * NSTAT + threadIdx.x] = red[threadIdx.x][0];
+    const double s = block_sum256<NSTAT>(acc, red);
+    if (threadIdx.x < NSTAT) mid[((uint64_t)blockIdx.y * STAT_CHUNKS + blockIdx.x) * NSTAT + threadIdx.x] = s;
+}
+
+// one wavefront per box: the box's STAT_CHUNKS chunk sums, in chunk order
+__global__ __launch_bounds__(64) void k_stats_final(const double* __restrict__ mid, double* __restrict__ out)
+{
+    const int k = threadIdx.x;
+    if (k >= NSTAT) return;
+    const double* m = mid + (uint64_t)blockIdx.x * STAT_CHUNKS * NSTAT;
+    double s = 0.0;
+    for (int c = 0; c < STAT_CHUNKS; ++c) s += m[c * NSTAT + k];
+    out[(uint64_t)blockIdx.x * NSTAT + k] = s;
 }
 
 // one block per box: chain sums.  Record: [0..2] sum x, [3..5] sum m v,
@@ -1416,7 +1450,8 @@ constexpr int NCHAIN = 11;
 __global__ __launch_bounds__(256) void k_chain_obs(const BoxDev* __restrict__ boxes, ChainArgs ca,
                                                    double* __restrict__ out)
 {
-    __shared__ double red[9][256];
+    __shared__ double red[4][9];
+    __shared__ double red1[4][1];
     __shared__ double sums[9];
     __shared__ double ccom[3 * MAXB];   // per-chain centres of mass (several chains)
     const BoxDev& bx = boxes[blockIdx.x];
@@ -1432,14 +1467,8 @@ __global__ __launch_bounds__(256) void k_chain_obs(const BoxDev* __restrict__ bo
             acc[6 + c] += ca.fc[3 * g + c];
         }
     }
-    for (int k = 0; k < 9; ++k) red[k][threadIdx.x] = acc[k];
-    __syncthreads();
-    for (int w = 128; w > 0; w >>= 1) {
-        if ((int)threadIdx.x < w)
-            for (int k = 0; k < 9; ++k) red[k][threadIdx.x] += red[k][threadIdx.x + w];
-        __syncthreads();
-    }
-    if (threadIdx.x < 9) sums[threadIdx.x] = red[threadIdx.x][0];
+    const double s9 = block_sum256<9>(acc, red);
+    if (threadIdx.x < 9) sums[threadIdx.x] = s9;
     // several chains: each chain's centre of mass, in bead order
     if (M > 1)
         for (int ch = threadIdx.x; ch < M; ch += 256) {
@@ -1459,16 +1488,12 @@ __global__ __launch_bounds__(256) void k_chain_obs(const BoxDev* __restrict__ bo
             s += d * d;
         }
     }
-    red[0][threadIdx.x] = s;
-    __syncthreads();
-    for (int w = 128; w > 0; w >>= 1) {
-        if ((int)threadIdx.x < w) red[0][threadIdx.x] += red[0][threadIdx.x + w];
-        __syncthreads();
-    }
+    double s1[1] = {s};
+    const double sg = block_sum256<1>(s1, red1);
     if (threadIdx.x == 0) {
         double* o = out + (uint64_t)blockIdx.x * NCHAIN;
         for (int k = 0; k < 9; ++k) o[k] = sums[k];
-        o[10] = red[0][0];
+        o[10] = sg;
         double e2 = 0.0;
         for (int ch = 0; ch < M; ++ch) {
             const uint64_t g0 = bx.bead_off + (uint64_t)ch * n, g1 = g0 + n - 1;
@@ -1626,11 +1651,13 @@ hipError_t launch_advance(const LaunchCtx& c, uint32_t n)
 }
 
 template <typename R>
-hipError_t launch_stats(const LaunchCtx& c, const void* A, uint32_t total_tiles, double* part, double* out)
+hipError_t launch_stats(const LaunchCtx& c, const void* A, uint32_t total_tiles, double* part, double* mid,
+                        double* out)
 {
     hipLaunchKernelGGL(k_stats<R>, dim3(total_tiles), dim3(256), 0, c.stream, c.boxes, c.tile_box, (const R*)A,
                        part);
-    hipLaunchKernelGGL(k_stats_final, dim3(c.n_boxes), dim3(256), 0, c.stream, c.boxes, part, out);
+    hipLaunchKernelGGL(k_stats_mid, dim3(STAT_CHUNKS, c.n_boxes), dim3(256), 0, c.stream, c.boxes, part, mid);
+    hipLaunchKernelGGL(k_stats_final, dim3(c.n_boxes), dim3(64), 0, c.stream, mid, out);
     return hipGetLastError();
 }
 
@@ -2089,7 +2116,7 @@ template hipError_t launch_couple_big<float>(const LaunchCtx&, const void*, cons
                                             hipEvent_t);
 template hipError_t launch_couple_big<double>(const LaunchCtx&, const void*, const int32_t*, int, int, uint32_t,
                                              hipEvent_t);
-template hipError_t launch_stats<float>(const LaunchCtx&, const void*, uint32_t, double*, double*);
-template hipError_t launch_stats<double>(const LaunchCtx&, const void*, uint32_t, double*, double*);
+template hipError_t launch_stats<float>(const LaunchCtx&, const void*, uint32_t, double*, double*, double*);
+template hipError_t launch_stats<double>(const LaunchCtx&, const void*, uint32_t, double*, double*, double*);
 
 }  // namespace lbd

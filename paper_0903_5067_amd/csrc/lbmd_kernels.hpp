@@ -85,8 +85,12 @@ hipError_t launch_couple_big(const LaunchCtx& c, const void* A, const int32_t* l
 constexpr int BIG_CHAIN = 256;   // chains above this many beads take the one-workgroup-per-chain kernel
 hipError_t launch_advance(const LaunchCtx& c, uint32_t n);
 hipError_t launch_init_forces(const LaunchCtx& c, const int32_t* list, int n_list, int block);
+// observables of the state A: per-tile records in part [total_tiles][NSTAT_REC],
+// per-chunk sums in mid [n_boxes][STAT_CHUNKS][NSTAT_REC], per-box sums in out
+// [n_boxes][NSTAT_REC]
 template <typename R>
-hipError_t launch_stats(const LaunchCtx& c, const void* A, uint32_t total_tiles, double* part, double* out);
+hipError_t launch_stats(const LaunchCtx& c, const void* A, uint32_t total_tiles, double* part, double* mid,
+                        double* out);
 hipError_t launch_chain_obs(const LaunchCtx& c, double* out);
 
 // device pointers of one reverse step of the adjoint window
@@ -108,6 +112,7 @@ hipError_t launch_adj_couple(const LaunchCtx& c, const int32_t* list, int n_list
 constexpr int N_COLLIDE_VARIANTS = 10;
 constexpr int DEFAULT_COLLIDE_VARIANT = 3;   // one block per tile, at most 7 waves per SIMD
 constexpr int NSTAT_REC = 24;
+constexpr int STAT_CHUNKS = 64;   // per box, the tile records are summed in this many fixed ranges first
 constexpr int NCHAIN_REC = 11;
 constexpr int NL_SLOTS = 32;
 constexpr int TAPE_REC = 40;     // doubles per bead and substep in the adjoint tape

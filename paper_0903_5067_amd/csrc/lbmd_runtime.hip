@@ -46,7 +46,7 @@ struct Layout {
     size_t st_popA = 0, st_popB = 0, st_x = 0, st_v = 0, st_f = 0, st_fc = 0, state_bytes = 0;
     size_t sc_ctrl = 0, sc_boxes = 0, sc_ccs = 0, sc_tilebox = 0, sc_couple = 0, sc_imp = 0, sc_claim = 0,
            sc_touched = 0, sc_tcnt = 0, sc_beadbox = 0, sc_nlcnt = 0, sc_nlidx = 0, sc_nlx0 = 0,
-           sc_part = 0, sc_stat = 0, sc_chain = 0, sc_vhist = 0, sc_nlreb = 0, sc_biglist = 0, sc_alllist = 0,
+           sc_part = 0, sc_mid = 0, sc_stat = 0, sc_chain = 0, sc_vhist = 0, sc_nlreb = 0, sc_biglist = 0, sc_alllist = 0,
            sc_nearu = 0, sc_nearc = 0, sc_subrec = 0, sc_field = 0, sc_binstart = 0, sc_items = 0, sc_slotof = 0,
            sc_defer = 0, sc_dclaim = 0, sc_dlist = 0, sc_ovf = 0, scratch_bytes = 0;
     uint64_t beads_big_sparse = 0;                    // beads of the chains above BIG_CHAIN in the other boxes
@@ -188,6 +188,7 @@ Layout make_layout(const lb_box_desc* b, int32_t n, int32_t prec, int32_t hist)
     Lo.sc_nlidx = o; o = align256(o + nbx * NL_CAP * sizeof(uint16_t));
     Lo.sc_nlx0 = o; o = align256(o + std::max<uint64_t>(beads, 1) * 3 * sizeof(double));
     Lo.sc_part = o; o = align256(o + tiles * NSTAT_REC * sizeof(double));
+    Lo.sc_mid = o; o = align256(o + (size_t)n * STAT_CHUNKS * NSTAT_REC * sizeof(double));
     Lo.sc_stat = o; o = align256(o + n * NSTAT_REC * sizeof(double));
     Lo.sc_chain = o; o = align256(o + n * NCHAIN_REC * sizeof(double));
     Lo.sc_vhist = o; o = align256(o + (size_t)hist * std::max<uint64_t>(beads, 1) * 3 * sizeof(double));
@@ -403,6 +404,24 @@ lb_status build_graph(lb_handle* h, int parity)
     if (e != hipSuccess) return fail(h, LB_EDEVICE, std::string("graph capture: ") + hipGetErrorString(e));
     h->graph[parity] = g;
     HIPCHK(h, hipGraphInstantiate(&h->gexec[parity], g, nullptr, nullptr, 0));
+    // move the executable graph to the device now rather than at its first
+    // launch; a runtime without the call keeps the lazy upload
+    if (hipGraphUpload(h->gexec[parity], h->stream) != hipSuccess) (void)hipGetLastError();
+    return LB_OK;
+}
+
+// Record and instantiate the graphs of both buffer parities at once, so that
+// no later lb_step captures or instantiates one (a caller timing lb_step
+// then times replays only).  Synchronous.
+lb_status prepare_graphs(lb_handle* h)
+{
+    drop_graphs(h);
+    if (h->graph_steps <= 0) return LB_OK;
+    for (int p = 0; p < 2; ++p) {
+        lb_status s = build_graph(h, p);
+        if (s != LB_OK) return s;
+    }
+    HIPCHK(h, hipStreamSynchronize(h->stream));
     return LB_OK;
 }
 
@@ -683,10 +702,11 @@ lb_status lb_observables(lb_handle* h, lb_obs* out)
     double* stat = (double*)(h->scratch + lo.sc_stat);
     double* chain = (double*)(h->scratch + lo.sc_chain);
     const void* A = h->pop(h->cur);
+    double* mid = (double*)(h->scratch + lo.sc_mid);
     if (h->prec == LB_FP64)
-        HIPCHK(h, launch_stats<double>(h->ctx, A, (uint32_t)lo.total_tiles, part, stat));
+        HIPCHK(h, launch_stats<double>(h->ctx, A, (uint32_t)lo.total_tiles, part, mid, stat));
     else
-        HIPCHK(h, launch_stats<float>(h->ctx, A, (uint32_t)lo.total_tiles, part, stat));
+        HIPCHK(h, launch_stats<float>(h->ctx, A, (uint32_t)lo.total_tiles, part, mid, stat));
     HIPCHK(h, launch_chain_obs(h->ctx, chain));
     std::vector<double> st(h->n_boxes * NSTAT_REC), ch(h->n_boxes * NCHAIN_REC);
     std::vector<uint32_t> reb(h->n_boxes);
@@ -889,7 +909,7 @@ lb_status lb_set_launch(lb_handle* h, int32_t batched, int32_t graph_steps)
     h->batched = batched ? 1 : 0;
     h->overlap = batched == 2 ? 0 : 1;
     h->graph_steps = graph_steps + (graph_steps & 1);
-    return LB_OK;
+    return prepare_graphs(h);
 }
 
 
@@ -1227,9 +1247,8 @@ lb_status lb_set_collide_variant(lb_handle* h, int32_t variant)
     if (!h) return fail(nullptr, LB_EINVAL, "null handle");
     if (variant < 0 || variant >= N_COLLIDE_VARIANTS) return fail(h, LB_EINVAL, "variant out of range");
     HIPCHK(h, hipStreamSynchronize(h->stream));
-    drop_graphs(h);
     h->ctx.collide_variant = h->ctx2.collide_variant = variant;
-    return LB_OK;
+    return prepare_graphs(h);
 }
 
 lb_status lb_autotune(lb_handle* h, int32_t reps, float* times_us, int32_t* chosen)
@@ -1280,7 +1299,7 @@ lb_status lb_autotune(lb_handle* h, int32_t reps, float* times_us, int32_t* chos
     }
     h->ctx.collide_variant = h->ctx2.collide_variant = best_v;
     if (chosen) *chosen = best_v;
-    return LB_OK;
+    return prepare_graphs(h);
 }
 
 void* lb_stream(const lb_handle* h) { return h ? (void*)h->stream : nullptr; }
