@@ -262,7 +262,7 @@ lb_status lb_window_backward(lb_handle* h, void* d_ws, size_t bytes, const doubl
 lb_status lb_window_rewind(lb_handle* h, void* d_ws, size_t bytes);
 /* Change a box's shear and bulk relaxation rates (the stress-mode rates of
  * the collision, Sec. II.B) and bead friction zeta_bare (Sec. II.B, coupling
- * paragraph); the ranges are those of lb_box_desc (LB_EINVAL otherwise).
+ * paragraph); the ranges are those of lb_box_desc, else LB_EINVAL.
  * Synchronises the stream; takes effect at the next step. */
 lb_status lb_set_rates(lb_handle* h, int32_t box, double omega_shear, double omega_bulk, double zeta);
 
