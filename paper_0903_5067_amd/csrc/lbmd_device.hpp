@@ -30,7 +30,7 @@ struct BoxDev {
     int32_t chain_len;   // beads per chain (> 0; N for a single chain)
     int32_t dense;       // 1: beads cover much of the box; its collide follows the coupling and
                          // takes the node impulses itself (no fix-up pass)
-    int32_t pad_;
+    uint32_t stat_off;   // first record of the box's observable partials (one per STAT_TPB tiles)
     double rho0, gam_b, gam_s, gam_g, mu;
     double tau_lb, dt, mass, zeta, k_fene, r0sq, eps, sigsq, rc2, bead_noise;
     double inv_L, inv_r0sq;

@@ -157,6 +157,7 @@ struct ChainArgs {
     uint32_t* dclaim;          // per collide tile: stamp of the last step that listed it
     uint32_t* defer_list; uint32_t defer_cap;
     uint32_t* ovf; uint32_t ovf_cap;   // (bead, local node) pairs outside the deferred tiles
+    uint32_t* ovm;             // per global node: stamp of the last step that listed it in ovf
 };
 
 // node velocities (MD units) of the 8 stencil nodes from the frozen populations;
@@ -593,14 +594,46 @@ __global__ __launch_bounds__(256) void k_node_field(const BoxDev* __restrict__ b
     o[0] = u[0]; o[1] = u[1]; o[2] = u[2];
 }
 
+// fix-up of one node after the plain collide: defined with the fix-up kernels
+template <typename R>
+__device__ __forceinline__ void fixup_node(const BoxDev& bx, const CollideConst<R>* __restrict__ ccs, int bi,
+                                           uint32_t r, unsigned long long* __restrict__ imp,
+                                           uint32_t* __restrict__ claim, const R* __restrict__ A, R* __restrict__ B,
+                                           Ctrl* __restrict__ ctrl, uint32_t t, int keep_imp);
+
+// The node table of the step.  With Aprev (batched steps that defer tiles,
+// from the second step of a run of steps on) it also finishes the previous
+// step: the impulses that landed outside that step's deferred tiles are
+// collided again (Aprev -> A, the previous step's number), their impulses
+// left in the field for the chain kernel to clear.  A table node whose
+// population comes from such a node takes the fixed value computed here
+// instead of reading it, so no thread reads what another writes.
 template <typename R>
 __global__ __launch_bounds__(256) void k_near_nodes(const BoxDev* __restrict__ boxes,
-                                                    const int32_t* __restrict__ list, const R* __restrict__ A,
+                                                    const int32_t* __restrict__ list, R* A,
                                                     ChainArgs ca, R* __restrict__ near_u, int4* __restrict__ near_c,
                                                     const R* __restrict__ field, Ctrl* __restrict__ ctrl,
-                                                    uint32_t s_off)
+                                                    uint32_t s_off, const CollideConst<R>* __restrict__ ccs,
+                                                    const int32_t* __restrict__ bead_box,
+                                                    uint32_t* __restrict__ claim, const R* __restrict__ Aprev,
+                                                    int one_box, BoxDev one)
 {
-    const BoxDev& bx = boxes[list[blockIdx.y]];
+    // one_box >= 0: the launch covers that box alone, its descriptor passed by
+    // value (no dependent loads of the box list and table before the beads')
+    const uint32_t t = ctrl->step + s_off;
+    uint32_t n_pend = 0;
+    if (Aprev) {
+        n_pend = min(ctrl->ovf_cnt, ca.ovf_cap);
+        const uint32_t nth = gridDim.x * gridDim.y * blockDim.x;
+        for (uint32_t e = (blockIdx.y * gridDim.x + blockIdx.x) * blockDim.x + threadIdx.x; e < n_pend; e += nth) {
+            const uint64_t g = ca.ovf[2 * (uint64_t)e];
+            const uint32_t r = ca.ovf[2 * (uint64_t)e + 1];
+            const int bi = bead_box[g];
+            fixup_node<R>(boxes[bi], ccs, bi, r, ca.imp, claim, Aprev, A, ctrl, t - 1u, 1);
+        }
+    }
+    const int bi = one_box >= 0 ? one_box : list[blockIdx.y];
+    const BoxDev& bx = one_box >= 0 ? one : boxes[bi];
     const int N = bx.N, L = bx.L;
     const int tid = (int)(blockIdx.x * blockDim.x + threadIdx.x);
     if (tid >= N * NEAR) return;
@@ -623,10 +656,25 @@ __global__ __launch_bounds__(256) void k_near_nodes(const BoxDev* __restrict__ b
     const Upwind up(nx, ny, nz, (uint32_t)L);
     R d[19];
     gather_pre<R, false>(A + bx.pop_off, up, d);
+    if (n_pend) {
+        const uint32_t pst = defer_stamp(t - 1u);
+        for (int i = 0; i < 19; ++i) {
+            const uint32_t src = up.src(i);
+            if (ca.ovm[bx.node_off + src] != pst) continue;
+            R dd[19], oo[19];
+            gather_pre<R, false>(Aprev + bx.pop_off, upwind_of(src, L, bx.inv_L), dd);
+            const unsigned long long* qi = ca.imp + 3 * (bx.node_off + src);
+            const R fx = (R)((double)(long long)qi[0] * IMP_INV_SCALE),
+                    fy = (R)((double)(long long)qi[1] * IMP_INV_SCALE),
+                    fz = (R)((double)(long long)qi[2] * IMP_INV_SCALE);
+            (void)collide<R>(dd, oo, fx, fy, fz, ccs[bi], src, t - 1u, bx.seed, bx.box_id);
+            d[i] = oo[i];
+        }
+    }
     if (ca.defer)   // the bead's stencil stays on its table's nodes while it moves less
                     // than half a cell from its nearest node: their tiles wait for the
                     // impulses (a plain store: every writer stores the same stamp)
-        ca.defer[bx.tile_begin + node / 256u] = defer_stamp(ctrl->step + s_off);
+        ca.defer[bx.tile_begin + node / 256u] = defer_stamp(t);
     R u[3];
     node_velocity<R>(d, bx.rho0, 1.0 / bx.tau_lb, u);
     o[0] = u[0]; o[1] = u[1]; o[2] = u[2];
@@ -642,7 +690,8 @@ __global__ __launch_bounds__(WG_MAXB) void k_chain_wg(const BoxDev* __restrict__
                                                       const R* __restrict__ near_u,
                                                       const int4* __restrict__ near_c,
                                                       double* __restrict__ rec, Ctrl* __restrict__ ctrl,
-                                                      uint32_t s_off)
+                                                      uint32_t s_off, const int32_t* __restrict__ ca_bead_box,
+                                                      int clear_ovf)
 {
     __shared__ double xs[3 * WG_MAXB];           // current positions
     __shared__ double x0s[3 * WG_MAXB];          // positions at the last list build
@@ -668,6 +717,21 @@ __global__ __launch_bounds__(WG_MAXB) void k_chain_wg(const BoxDev* __restrict__
     const double rl = sqrt(bx.rc2) + NL_SKIN;
     const double rl2 = rl * rl;
     const int nl_cap = ca.nl_cap < NL_SLOTS ? ca.nl_cap : NL_SLOTS;
+
+    if (clear_ovf) {
+        // the previous step's impulses outside its deferred tiles were fixed
+        // up by the node-table kernel, which left them in the field: clear
+        // them before this step's spread, then reset both list counts
+        const uint32_t n_ovf = min(ctrl->ovf_cnt, ca.ovf_cap);
+        for (uint32_t e = (uint32_t)b; e < n_ovf; e += WG_MAXB) {
+            const uint64_t gg = ca.ovf[2 * (uint64_t)e];
+            const uint32_t r = ca.ovf[2 * (uint64_t)e + 1];
+            unsigned long long* q = ca.imp + 3 * (boxes[ca_bead_box[gg]].node_off + r);
+            q[0] = 0ull; q[1] = 0ull; q[2] = 0ull;
+        }
+        __syncthreads();   // every thread has read the count
+        if (b == 0) { ctrl->ovf_cnt = 0u; ctrl->defer_cnt = 0u; }
+    }
 
     double x[3] = {0, 0, 0}, v[3] = {0, 0, 0}, f[3] = {0, 0, 0};
     int nl_n = -2;
@@ -927,6 +991,7 @@ __device__ __forceinline__ uint32_t list_overflow(const ChainArgs& ca, const Box
                                                   Ctrl* __restrict__ ctrl, uint32_t stamp)
 {
     if (!ca.defer || ca.defer[bx.tile_begin + node / 256u] == stamp) return 0u;
+    ca.ovm[bx.node_off + node] = stamp;   // read by the next step's node-table kernel
     const uint32_t k = atomicAdd(&ctrl->ovf_cnt, 1u);
     if (k >= ca.ovf_cap) return H_TABLE;
     ca.ovf[2 * (uint64_t)k] = (uint32_t)g;
@@ -1351,25 +1416,56 @@ __global__ void k_advance(Ctrl* ctrl, uint32_t n)
 // order), so a state gives the same bits on every call and in any batch.
 constexpr int NSTAT = NSTAT_REC;
 
-// sum over the 64 lanes of a wavefront by xor butterfly: every lane ends with
-// the same bits (each stage adds the same two values in either order)
-__device__ __forceinline__ double wave_sum(double v)
+// value of v in another lane of the same 16-lane row, by a DPP lane move of
+// both 32-bit halves (CTRL: a gfx9 DPP control; every source lane is active)
+template <int CTRL>
+__device__ __forceinline__ double dpp_from(double v)
 {
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
-    return v;
+    const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(v), CTRL, 0xF, 0xF, false);
+    const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(v), CTRL, 0xF, 0xF, false);
+    return __hiloint2double(hi, lo);
 }
 
-// sum of acc[0..NV-1] over a 256-thread block: per wavefront, then wavefronts
-// 0..3 in order; the result is valid in threads 0..NV-1 (thread k holds sum k)
+__device__ __forceinline__ double lane_value(double v, int lane)
+{
+    return __hiloint2double(__builtin_amdgcn_readlane(__double2hiint(v), lane),
+                            __builtin_amdgcn_readlane(__double2loint(v), lane));
+}
+
+// Sum of v[k] over the 64 lanes of a wavefront for k < NV, with every lane of
+// the wavefront active: within each 16-lane row by DPP moves (neighbour in the
+// pair, the other pair of the quad, the mirrored quad, the mirrored half-row;
+// each stage adds the same two values in either order, so all 16 lanes hold
+// the same row sum), then the four row sums in row order.  The NV sums are
+// advanced stage by stage so that their moves issue back to back.  Every lane
+// returns the same bits.
+template <int NV>
+__device__ __forceinline__ void wave_sums(double v[NV])
+{
+#pragma unroll
+    for (int k = 0; k < NV; ++k) v[k] += dpp_from<0xB1>(v[k]);    // quad_perm [1,0,3,2]
+#pragma unroll
+    for (int k = 0; k < NV; ++k) v[k] += dpp_from<0x4E>(v[k]);    // quad_perm [2,3,0,1]
+#pragma unroll
+    for (int k = 0; k < NV; ++k) v[k] += dpp_from<0x141>(v[k]);   // row_half_mirror
+#pragma unroll
+    for (int k = 0; k < NV; ++k) v[k] += dpp_from<0x140>(v[k]);   // row_mirror
+#pragma unroll
+    for (int k = 0; k < NV; ++k)
+        v[k] = ((lane_value(v[k], 0) + lane_value(v[k], 16)) + lane_value(v[k], 32)) + lane_value(v[k], 48);
+}
+
+// sum of acc[0..NV-1] over a 256-thread block (all threads active): per
+// wavefront, then wavefronts 0..3 in order; the result is valid in threads
+// 0..NV-1 (thread k holds sum k).  acc is consumed.
 template <int NV>
 __device__ __forceinline__ double block_sum256(double acc[NV], double (*lds)[NV])
 {
     const int wv_ = threadIdx.x >> 6, ln = threadIdx.x & 63;
+    wave_sums<NV>(acc);
+    if (ln == 0) {
 #pragma unroll
-    for (int k = 0; k < NV; ++k) {
-        const double s = wave_sum(acc[k]);
-        if (ln == 0) lds[wv_][k] = s;
+        for (int k = 0; k < NV; ++k) lds[wv_][k] = acc[k];
     }
     __syncthreads();
     double r = 0.0;
@@ -1377,24 +1473,28 @@ __device__ __forceinline__ double block_sum256(double acc[NV], double (*lds)[NV]
     return r;
 }
 
+// grid (records of the largest box, boxes): block (c, box) sums tiles
+// c*STAT_TPB .. c*STAT_TPB + STAT_TPB - 1 of the box, one node per thread and
+// tile, into record stat_off + c
 template <typename R>
-__global__ __launch_bounds__(256) void k_stats(const BoxDev* __restrict__ boxes,
-                                               const uint32_t* __restrict__ tile_box,
-                                               const R* __restrict__ A, double* __restrict__ part)
+__global__ __launch_bounds__(256) void k_stats(const BoxDev* __restrict__ boxes, const R* __restrict__ A,
+                                               double* __restrict__ part)
 {
     __shared__ double red[4][NSTAT];
-    const uint32_t tile = blockIdx.x;
-    const int bi = (int)tile_box[tile];
-    const BoxDev& bx = boxes[bi];
+    const BoxDev& bx = boxes[blockIdx.y];
+    const uint32_t c = blockIdx.x;
+    if (c >= stat_recs_of(bx.n_tiles)) return;
     const uint32_t V = (uint32_t)bx.L * bx.L * bx.L;
-    const uint32_t r = (tile - bx.tile_begin) * 256u + threadIdx.x;
+    const R* a = A + bx.pop_off;
     double acc[NSTAT];
 #pragma unroll
     for (int k = 0; k < NSTAT; ++k) acc[k] = 0.0;
-    if (r < V) {
+    for (int k = 0; k < STAT_TPB; ++k) {
+        const uint32_t r = (c * STAT_TPB + k) * 256u + threadIdx.x;
+        if (r >= V) break;
         const Upwind up = upwind_of(r, bx.L, bx.inv_L);
         R dr[19];
-        gather_pre<R, false>(A + bx.pop_off, up, dr);
+        gather_pre<R, false>(a, up, dr);
         double d[19], m[19];
 #pragma unroll
         for (int i = 0; i < 19; ++i) {
@@ -1402,28 +1502,29 @@ __global__ __launch_bounds__(256) void k_stats(const BoxDev* __restrict__ boxes,
             if (wv(i) * bx.rho0 + d[i] < 0.0) acc[4] += 1.0;
         }
         to_modes<double>(d, m);
-        acc[0] = m[0]; acc[1] = m[1]; acc[2] = m[2]; acc[3] = m[3];
+        acc[0] += m[0]; acc[1] += m[1]; acc[2] += m[2]; acc[3] += m[3];
 #pragma unroll
-        for (int k = 0; k < 19; ++k) acc[5 + k] = m[k] * m[k];
+        for (int q = 0; q < 19; ++q) acc[5 + q] += m[q] * m[q];
     }
     const double s = block_sum256<NSTAT>(acc, red);
-    if (threadIdx.x < NSTAT) part[(uint64_t)tile * NSTAT + threadIdx.x] = s;
+    if (threadIdx.x < NSTAT) part[(uint64_t)(bx.stat_off + c) * NSTAT + threadIdx.x] = s;
 }
 
-// grid (STAT_CHUNKS, boxes): block (c, box) sums the tile records of chunk c
-// of the box (a fixed split of its tiles into STAT_CHUNKS ranges)
+// grid (STAT_CHUNKS, boxes): block (c, box) sums the block records of chunk
+// c of the box (a fixed split of its records into STAT_CHUNKS ranges)
 __global__ __launch_bounds__(256) void k_stats_mid(const BoxDev* __restrict__ boxes,
                                                    const double* __restrict__ part, double* __restrict__ mid)
 {
     __shared__ double red[4][NSTAT];
     const BoxDev& bx = boxes[blockIdx.y];
-    const uint32_t per = (bx.n_tiles + STAT_CHUNKS - 1) / STAT_CHUNKS;
-    const uint32_t t0 = blockIdx.x * per, t1 = min(bx.n_tiles, t0 + per);
+    const uint32_t nrec = stat_recs_of(bx.n_tiles);
+    const uint32_t per = (nrec + STAT_CHUNKS - 1) / STAT_CHUNKS;
+    const uint32_t t0 = blockIdx.x * per, t1 = min(nrec, t0 + per);
     double acc[NSTAT];
 #pragma unroll
     for (int k = 0; k < NSTAT; ++k) acc[k] = 0.0;
     for (uint32_t tt = t0 + threadIdx.x; tt < t1; tt += 256) {
-        const double* rec = part + (uint64_t)(bx.tile_begin + tt) * NSTAT;
+        const double* rec = part + (uint64_t)(bx.stat_off + tt) * NSTAT;
 #pragma unroll
         for (int k = 0; k < NSTAT; ++k) acc[k] += rec[k];
     }
@@ -1512,7 +1613,7 @@ static ChainArgs chain_args(const LaunchCtx& c)
     return ChainArgs{c.x, c.v, c.f, c.fc, c.nl_cnt, c.nl_idx, c.nl_x0, c.nl_cap, c.imp, c.touched,
                      c.touched_cnt, c.touch_cap, c.nl_rebuilds, c.vhist, c.hist_len, c.total_beads, c.tape,
                      c.tape_x0, c.tape_vo, c.tape_fo,
-                     c.defer_on ? c.defer : nullptr, c.dclaim, c.defer_list, c.defer_cap, c.ovf, c.ovf_cap};
+                     c.defer_on ? c.defer : nullptr, c.dclaim, c.defer_list, c.defer_cap, c.ovf, c.ovf_cap, c.ovm};
 }
 
 template <typename R, int W, bool PERSIST>
@@ -1604,22 +1705,27 @@ hipError_t launch_couple(const LaunchCtx& c, const void* A, const int32_t* list,
 
 template <typename R>
 hipError_t launch_couple_big(const LaunchCtx& c, const void* A, const int32_t* list, int n_list, int max_n,
-                             uint32_t s_off, hipEvent_t after_table)
+                             uint32_t s_off, hipEvent_t after_table, const void* Aprev, int single_box)
 {
     if (n_list == 0) return hipSuccess;
     if (c.nl_cap > NL_SLOTS || max_n > WG_MAXB || max_n <= 0) return hipErrorInvalidValue;
+    if (Aprev && (c.dense_max_tiles || !c.defer_on)) return hipErrorInvalidValue;
     const ChainArgs ca = chain_args(c);
     if (c.dense_max_tiles)
         hipLaunchKernelGGL(k_node_field<R>, dim3(c.dense_max_tiles, n_list), dim3(256), 0, c.stream, c.boxes, list,
                            (const R*)A, (R*)c.field);
     hipLaunchKernelGGL(k_near_nodes<R>, dim3((max_n * NEAR + 255) / 256, n_list), dim3(256), 0, c.stream, c.boxes,
-                       list, (const R*)A, ca, (R*)c.near_u, c.near_c, (const R*)c.field, c.ctrl, s_off);
+                       list, (R*)A, ca, (R*)c.near_u, c.near_c, (const R*)c.field, c.ctrl, s_off,
+                       (const CollideConst<R>*)c.ccs, c.bead_box, c.claim, (const R*)Aprev,
+                       n_list == 1 && single_box >= 0 ? single_box : -1,
+                       n_list == 1 && single_box >= 0 ? c.boxes_host[single_box] : BoxDev{});
     if (after_table) {
         const hipError_t e = hipEventRecord(after_table, c.stream);
         if (e != hipSuccess) return e;
     }
     hipLaunchKernelGGL(k_chain_wg<R>, dim3(n_list), dim3(WG_MAXB), 0, c.stream, c.boxes, list, (const R*)A, ca,
-                       (const R*)c.near_u, (const int4*)c.near_c, c.sub_rec, c.ctrl, s_off);
+                       (const R*)c.near_u, (const int4*)c.near_c, c.sub_rec, c.ctrl, s_off, c.bead_box,
+                       Aprev ? 1 : 0);
     if (c.big_sparse)
         hipLaunchKernelGGL(k_spread, dim3((max_n * 8 + 255) / 256, n_list), dim3(256), 0, c.stream, c.boxes, list,
                            ca, (const double*)c.sub_rec, c.ctrl, s_off);
@@ -1651,11 +1757,10 @@ hipError_t launch_advance(const LaunchCtx& c, uint32_t n)
 }
 
 template <typename R>
-hipError_t launch_stats(const LaunchCtx& c, const void* A, uint32_t total_tiles, double* part, double* mid,
+hipError_t launch_stats(const LaunchCtx& c, const void* A, uint32_t max_recs, double* part, double* mid,
                         double* out)
 {
-    hipLaunchKernelGGL(k_stats<R>, dim3(total_tiles), dim3(256), 0, c.stream, c.boxes, c.tile_box, (const R*)A,
-                       part);
+    hipLaunchKernelGGL(k_stats<R>, dim3(max_recs, c.n_boxes), dim3(256), 0, c.stream, c.boxes, (const R*)A, part);
     hipLaunchKernelGGL(k_stats_mid, dim3(STAT_CHUNKS, c.n_boxes), dim3(256), 0, c.stream, c.boxes, part, mid);
     hipLaunchKernelGGL(k_stats_final, dim3(c.n_boxes), dim3(64), 0, c.stream, mid, out);
     return hipGetLastError();
@@ -2113,9 +2218,9 @@ template hipError_t launch_collide_forced<double>(const LaunchCtx&, const void*,
 template hipError_t launch_couple<float>(const LaunchCtx&, const void*, const int32_t*, int, int, uint32_t);
 template hipError_t launch_couple<double>(const LaunchCtx&, const void*, const int32_t*, int, int, uint32_t);
 template hipError_t launch_couple_big<float>(const LaunchCtx&, const void*, const int32_t*, int, int, uint32_t,
-                                            hipEvent_t);
+                                            hipEvent_t, const void*, int);
 template hipError_t launch_couple_big<double>(const LaunchCtx&, const void*, const int32_t*, int, int, uint32_t,
-                                             hipEvent_t);
+                                             hipEvent_t, const void*, int);
 template hipError_t launch_stats<float>(const LaunchCtx&, const void*, uint32_t, double*, double*, double*);
 template hipError_t launch_stats<double>(const LaunchCtx&, const void*, uint32_t, double*, double*, double*);
 

@@ -15,6 +15,7 @@ struct LaunchCtx {
     int n_cu;                      // compute units of the device
     int collide_variant;           // launch shape of the collide kernel (0..N_COLLIDE_VARIANTS-1)
     const BoxDev* boxes;
+    const BoxDev* boxes_host;      // host copy of the box table
     int n_boxes;
     const void* ccs;               // CollideConst<R>[n_boxes]
     const uint32_t* tile_box;      // box index of every collide tile
@@ -54,6 +55,7 @@ struct LaunchCtx {
     uint32_t defer_cap;
     uint32_t* ovf;                 // (bead, local node) pairs, Ctrl::ovf_cnt of them
     uint32_t ovf_cap;
+    uint32_t* ovm;                 // per global node: stamp of the last step that listed it in ovf
 };
 
 template <typename R>
@@ -78,18 +80,25 @@ hipError_t launch_couple(const LaunchCtx& c, const void* A, const int32_t* list,
 // chains of BIG_CHAIN+1..1024 beads (at most max_n): one 1024-thread workgroup
 // per box in `list`, with its node-table and impulse-spreading launches.
 // after_table (may be null) is recorded on c.stream between the node-table
-// kernel and the chain kernel.
+// kernel and the chain kernel.  Aprev (batched steps that defer tiles, sparse
+// boxes only): the previous step's input buffer; the node-table kernel then
+// fixes up the previous step's impulses outside its deferred tiles and the
+// chain kernel clears them and resets the list counts (instead of the
+// end-of-step kernel of launch_overflow).
+// single_box: the box `list` holds when n_list == 1 (its descriptor is then
+// passed to the node-table kernel by value), or -1.
 template <typename R>
 hipError_t launch_couple_big(const LaunchCtx& c, const void* A, const int32_t* list, int n_list, int max_n,
-                             uint32_t s_off, hipEvent_t after_table);
+                             uint32_t s_off, hipEvent_t after_table, const void* Aprev = nullptr,
+                             int single_box = -1);
 constexpr int BIG_CHAIN = 256;   // chains above this many beads take the one-workgroup-per-chain kernel
 hipError_t launch_advance(const LaunchCtx& c, uint32_t n);
 hipError_t launch_init_forces(const LaunchCtx& c, const int32_t* list, int n_list, int block);
-// observables of the state A: per-tile records in part [total_tiles][NSTAT_REC],
-// per-chunk sums in mid [n_boxes][STAT_CHUNKS][NSTAT_REC], per-box sums in out
-// [n_boxes][NSTAT_REC]
+// observables of the state A: per-block records in part [sum of stat_recs_of(n_tiles)][NSTAT_REC]
+// (box b's from BoxDev::stat_off), per-chunk sums in mid [n_boxes][STAT_CHUNKS][NSTAT_REC], per-box
+// sums in out [n_boxes][NSTAT_REC]; max_recs: the most records of any box
 template <typename R>
-hipError_t launch_stats(const LaunchCtx& c, const void* A, uint32_t total_tiles, double* part, double* mid,
+hipError_t launch_stats(const LaunchCtx& c, const void* A, uint32_t max_recs, double* part, double* mid,
                         double* out);
 hipError_t launch_chain_obs(const LaunchCtx& c, double* out);
 
@@ -112,7 +121,9 @@ hipError_t launch_adj_couple(const LaunchCtx& c, const int32_t* list, int n_list
 constexpr int N_COLLIDE_VARIANTS = 10;
 constexpr int DEFAULT_COLLIDE_VARIANT = 3;   // one block per tile, at most 7 waves per SIMD
 constexpr int NSTAT_REC = 24;
-constexpr int STAT_CHUNKS = 64;   // per box, the tile records are summed in this many fixed ranges first
+constexpr int STAT_TPB = 8;       // collide tiles per block of the observables pass (8 nodes per thread)
+constexpr int STAT_CHUNKS = 64;   // per box, the block records are summed in this many fixed ranges first
+__host__ __device__ inline uint32_t stat_recs_of(uint32_t n_tiles) { return (n_tiles + STAT_TPB - 1) / STAT_TPB; }
 constexpr int NCHAIN_REC = 11;
 constexpr int NL_SLOTS = 32;
 constexpr int TAPE_REC = 40;     // doubles per bead and substep in the adjoint tape

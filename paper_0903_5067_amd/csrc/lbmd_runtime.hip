@@ -43,12 +43,14 @@ struct Layout {
     uint32_t dense_max_tiles = 0;                     // collide tiles of the largest dense box
     uint64_t tiles_sparse = 0, beads_sparse = 0;      // collide tiles (first in tile order) and beads of the other boxes
     uint64_t pop_elems = 0, total_tiles = 0, total_beads = 0, total_nodes = 0;
+    std::vector<uint32_t> stat_off;                   // per box: first observable partial record
+    uint32_t stat_recs = 0, stat_max_recs = 0;        // records of all boxes, of the largest box
     size_t st_popA = 0, st_popB = 0, st_x = 0, st_v = 0, st_f = 0, st_fc = 0, state_bytes = 0;
     size_t sc_ctrl = 0, sc_boxes = 0, sc_ccs = 0, sc_tilebox = 0, sc_couple = 0, sc_imp = 0, sc_claim = 0,
            sc_touched = 0, sc_tcnt = 0, sc_beadbox = 0, sc_nlcnt = 0, sc_nlidx = 0, sc_nlx0 = 0,
            sc_part = 0, sc_mid = 0, sc_stat = 0, sc_chain = 0, sc_vhist = 0, sc_nlreb = 0, sc_biglist = 0, sc_alllist = 0,
            sc_nearu = 0, sc_nearc = 0, sc_subrec = 0, sc_field = 0, sc_binstart = 0, sc_items = 0, sc_slotof = 0,
-           sc_defer = 0, sc_dclaim = 0, sc_dlist = 0, sc_ovf = 0, scratch_bytes = 0;
+           sc_defer = 0, sc_dclaim = 0, sc_dlist = 0, sc_ovf = 0, sc_ovm = 0, scratch_bytes = 0;
     uint64_t beads_big_sparse = 0;                    // beads of the chains above BIG_CHAIN in the other boxes
     uint32_t defer_cap = 0, ovf_cap = 0;              // deferred-tile list and overflow list entries
     int max_N = 0;         // largest chain taking the one-workgroup path
@@ -103,6 +105,9 @@ Layout make_layout(const lb_box_desc* b, int32_t n, int32_t prec, int32_t hist)
         pop += pop_elems_of(V);   // whole tiles of PTILE nodes (4 or 8 KB per plane)
         Lo.n_tiles.push_back((uint32_t)((V + 255) / 256));
         tiles += (V + 255) / 256;
+        Lo.stat_off.push_back(Lo.stat_recs);
+        Lo.stat_recs += stat_recs_of(Lo.n_tiles.back());
+        Lo.stat_max_recs = std::max(Lo.stat_max_recs, stat_recs_of(Lo.n_tiles.back()));
         // a chain on the workgroup path whose stencils (8 nodes per bead)
         // cover a quarter of the box or more: re-colliding its nodes in a
         // fix-up would cost more than colliding the box after the coupling
@@ -187,7 +192,7 @@ Layout make_layout(const lb_box_desc* b, int32_t n, int32_t prec, int32_t hist)
     Lo.sc_nlcnt = o; o = align256(o + nbx * sizeof(int32_t));
     Lo.sc_nlidx = o; o = align256(o + nbx * NL_CAP * sizeof(uint16_t));
     Lo.sc_nlx0 = o; o = align256(o + std::max<uint64_t>(beads, 1) * 3 * sizeof(double));
-    Lo.sc_part = o; o = align256(o + tiles * NSTAT_REC * sizeof(double));
+    Lo.sc_part = o; o = align256(o + (size_t)Lo.stat_recs * NSTAT_REC * sizeof(double));
     Lo.sc_mid = o; o = align256(o + (size_t)n * STAT_CHUNKS * NSTAT_REC * sizeof(double));
     Lo.sc_stat = o; o = align256(o + n * NSTAT_REC * sizeof(double));
     Lo.sc_chain = o; o = align256(o + n * NCHAIN_REC * sizeof(double));
@@ -213,6 +218,7 @@ Layout make_layout(const lb_box_desc* b, int32_t n, int32_t prec, int32_t hist)
         Lo.sc_dclaim = o; o = align256(o + (Lo.beads_big_sparse ? tiles : 1) * sizeof(uint32_t));
         Lo.sc_dlist = o; o = align256(o + std::max<uint32_t>(Lo.defer_cap, 1) * sizeof(uint32_t));
         Lo.sc_ovf = o; o = align256(o + std::max<uint32_t>(Lo.ovf_cap, 1) * 2 * sizeof(uint32_t));
+        Lo.sc_ovm = o; o = align256(o + (Lo.beads_big_sparse ? nodes : 1) * sizeof(uint32_t));
     }
     Lo.scratch_bytes = o;
     return Lo;
@@ -251,12 +257,13 @@ struct lb_handle {
     // the chain coupling runs on a second stream, concurrently with the
     // collide kernel of the same step (both only read the current state)
     hipStream_t stream2 = nullptr;
-    hipEvent_t ev_fork = nullptr, ev_join = nullptr, ev_table = nullptr;
+    hipEvent_t ev_fork = nullptr, ev_join = nullptr, ev_table = nullptr, ev_head = nullptr, ev_def = nullptr;
     LaunchCtx ctx{};
     LaunchCtx ctx2{};
     int32_t* couple_list = nullptr;   // device: boxes on the one-workgroup path (chains <= 256 beads)
     int32_t* big_list = nullptr;      // device: boxes with chains of 257..1024 beads
     std::vector<int32_t> couple_host; // box indices with beads
+    std::vector<BoxDev> boxes_host;   // host copy of the device box table
     int cur = 0;                      // 0: buffer A holds the current state
     uint64_t step = 0;                // host mirror of the device step counter
     bool pending = false;             // lb_couple done, impulses not yet consumed
@@ -300,6 +307,7 @@ hipError_t clear_step_stamps(lb_handle* h)
     if (e == hipSuccess && lo.beads_big_sparse) {
         e = hipMemset(h->scratch + lo.sc_defer, 0, lo.total_tiles * sizeof(uint32_t));
         if (e == hipSuccess) e = hipMemset(h->scratch + lo.sc_dclaim, 0, lo.total_tiles * sizeof(uint32_t));
+        if (e == hipSuccess) e = hipMemset(h->scratch + lo.sc_ovm, 0, lo.total_nodes * sizeof(uint32_t));
     }
     return e;
 }
@@ -382,6 +390,103 @@ lb_status enqueue_step(lb_handle* h, int from, uint32_t s_off, bool couple)
     return LB_OK;
 }
 
+// Batched coupled steps run as a pipeline with a step head when some large
+// chain sits in a sparse box, no box is dense and the tiles are deferred.
+bool headed_steps(const lb_handle* h)
+{
+    const Layout& lo = h->lo;
+    return h->batched && h->overlap && lo.beads_big_sparse > 0 && lo.field_nodes == 0 && !h->ctx.keep_imp &&
+           !h->ctx.tape;
+}
+
+// A run of n batched steps from buffer `from` (step offsets 0..n-1), on the
+// two streams in turn.  Step k's plain collide runs on queue P[k & 1]; the
+// other queue, right behind step k-1's collide, holds step k's chain work:
+// the fix-up of the small chains' nodes of step k-1, the node-table kernel
+// (which also re-collides step k-1's large-chain impulses outside its
+// deferred tiles, and stamps step k's deferred tiles), then the chain kernel,
+// the spread, the deferred tiles' list and collide, and the small chains'
+// coupling.  Step k's collide waits for the node table only.  So the node
+// table follows the previous collide on its own queue, and one short kernel
+// separates two plain collides; the chain kernel, queued right behind the
+// node table, starts before the collide it runs beside (it needs a whole CU,
+// and its first reads are done before the collide loads the memory system).
+// The run ends with the last step's leftovers and a join into the handle's
+// stream.  Each node gets the same collide call with the same impulse as in
+// enqueue_step, so the bits are the same.
+lb_status enqueue_headed_run(lb_handle* h, int from, uint32_t n)
+{
+    const Layout& lo = h->lo;
+    const bool f64 = h->prec == LB_FP64;
+    LaunchCtx cq[2] = {h->ctx, h->ctx2};
+    cq[0].defer_on = cq[1].defer_on = 1;
+    hipStream_t P[2] = {h->stream, h->stream2};
+    const int nc = (int)h->couple_host.size(), nbig = (int)lo.big_list.size();
+    const bool small_fix = lo.beads_sparse > lo.beads_big_sparse;
+    const uint32_t ts = (uint32_t)lo.tiles_sparse;
+    const int one = nbig == 1 ? lo.big_list[0] : -1;
+    HIPCHK(h, hipEventRecord(h->ev_fork, P[0]));
+    HIPCHK(h, hipStreamWaitEvent(P[1], h->ev_fork, 0));
+    for (uint32_t k = 0; k < n; ++k) {
+        const int cqi = (int)(k & 1), wq = cqi ^ 1;   // collide queue, chain-work queue
+        const LaunchCtx& cw = cq[wq];
+        const int p = from ^ (int)(k & 1);
+        const void* A = h->pop(p);
+        void* B = h->pop(1 - p);
+        // the previous step read pop(1 - p) and wrote pop(p)
+        const void* prevA = h->pop(1 - p);
+        void* prevB = h->pop(p);
+        if (k > 0) {
+            // step k-1's chain work (on this step's collide queue) is done
+            HIPCHK(h, hipStreamWaitEvent(P[wq], h->ev_def, 0));
+            if (small_fix)
+                HIPCHK(h, f64 ? launch_fixup<double>(cw, prevA, prevB, 0, lo.total_beads, k - 1)
+                              : launch_fixup<float>(cw, prevA, prevB, 0, lo.total_beads, k - 1));
+        }
+        const void* pend = k > 0 ? prevA : nullptr;
+        HIPCHK(h, f64 ? launch_couple_big<double>(cw, A, h->big_list, nbig, lo.big_max_n, k, h->ev_head, pend, one)
+                      : launch_couple_big<float>(cw, A, h->big_list, nbig, lo.big_max_n, k, h->ev_head, pend, one));
+        if (nc)
+            HIPCHK(h, f64 ? launch_couple<double>(cw, A, h->couple_list, nc, lo.couple_block, k)
+                          : launch_couple<float>(cw, A, h->couple_list, nc, lo.couple_block, k));
+        HIPCHK(h, f64 ? launch_collide_deferred<double>(cw, A, B, k) : launch_collide_deferred<float>(cw, A, B, k));
+        HIPCHK(h, hipEventRecord(h->ev_def, P[wq]));
+        HIPCHK(h, hipStreamWaitEvent(P[cqi], h->ev_head, 0));
+        HIPCHK(h, f64 ? launch_collide<double>(cq[cqi], A, B, -1, 0, ts, k)
+                      : launch_collide<float>(cq[cqi], A, B, -1, 0, ts, k));
+    }
+    // the last step's leftovers behind its collide, then everything joins
+    // the handle's stream
+    const int cl = (int)((n - 1) & 1);
+    const int pl = from ^ (int)((n - 1) & 1);
+    const void* lastA = h->pop(pl);
+    void* lastB = h->pop(1 - pl);
+    HIPCHK(h, hipStreamWaitEvent(P[cl], h->ev_def, 0));
+    if (small_fix)
+        HIPCHK(h, f64 ? launch_fixup<double>(cq[cl], lastA, lastB, 0, lo.total_beads, n - 1)
+                      : launch_fixup<float>(cq[cl], lastA, lastB, 0, lo.total_beads, n - 1));
+    HIPCHK(h, f64 ? launch_overflow<double>(cq[cl], lastA, lastB, n - 1)
+                  : launch_overflow<float>(cq[cl], lastA, lastB, n - 1));
+    if (cl == 1) {
+        HIPCHK(h, hipEventRecord(h->ev_join, P[1]));
+        HIPCHK(h, hipStreamWaitEvent(P[0], h->ev_join, 0));
+    }
+    return LB_OK;
+}
+
+// n coupled steps from buffer `from`, step offsets 0..n-1 (the device step
+// counter is advanced by the caller)
+lb_status enqueue_steps(lb_handle* h, int from, uint32_t n)
+{
+    if (n == 0) return LB_OK;
+    if (headed_steps(h)) return enqueue_headed_run(h, from, n);
+    for (uint32_t k = 0; k < n; ++k) {
+        const lb_status s = enqueue_step(h, from ^ (int)(k & 1), k, true);
+        if (s != LB_OK) return s;
+    }
+    return LB_OK;
+}
+
 void drop_graphs(lb_handle* h)
 {
     for (int p = 0; p < 2; ++p) {
@@ -396,7 +501,7 @@ lb_status build_graph(lb_handle* h, int parity)
 {
     HIPCHK(h, hipStreamBeginCapture(h->stream, hipStreamCaptureModeThreadLocal));
     lb_status st = LB_OK;
-    for (int k = 0; k < h->graph_steps && st == LB_OK; ++k) st = enqueue_step(h, parity ^ (k & 1), (uint32_t)k, true);
+    st = enqueue_steps(h, parity, (uint32_t)h->graph_steps);
     if (st == LB_OK && launch_advance(h->ctx, (uint32_t)h->graph_steps) != hipSuccess) st = LB_EDEVICE;
     hipGraph_t g = nullptr;
     hipError_t e = hipStreamEndCapture(h->stream, &g);
@@ -495,7 +600,7 @@ lb_status lb_init(const lb_box_desc* boxes, int32_t n_boxes, int32_t precision, 
         b.couple_T = lo.couple_T[i];
         b.chain_len = d.chain_len > 0 ? d.chain_len : std::max(d.n_beads, 1);
         b.dense = lo.dense[i];
-        b.pad_ = 0;
+        b.stat_off = lo.stat_off[i];
         b.field_off = lo.field_off[i];
         b.bin_off = lo.bin_off[i];
         b.item_off = lo.item_off[i];
@@ -562,6 +667,8 @@ lb_status lb_init(const lb_box_desc* boxes, int32_t n_boxes, int32_t precision, 
         c.collide_variant = DEFAULT_COLLIDE_VARIANT;
     }
     c.boxes = (const BoxDev*)sc(lo.sc_boxes);
+    h->boxes_host = bd;
+    c.boxes_host = h->boxes_host.data();
     c.n_boxes = n_boxes;
     c.ccs = sc(lo.sc_ccs);
     c.tile_box = (const uint32_t*)sc(lo.sc_tilebox);
@@ -593,6 +700,7 @@ lb_status lb_init(const lb_box_desc* boxes, int32_t n_boxes, int32_t precision, 
     c.defer_cap = lo.defer_cap;
     c.ovf = (uint32_t*)sc(lo.sc_ovf);
     c.ovf_cap = lo.ovf_cap;
+    c.ovm = (uint32_t*)sc(lo.sc_ovm);
     c.vhist = hist_steps > 0 ? (double*)sc(lo.sc_vhist) : nullptr;
     c.hist_len = hist_steps > 0 ? hist_steps : 1;
     c.total_beads = nb;
@@ -602,6 +710,8 @@ lb_status lb_init(const lb_box_desc* boxes, int32_t n_boxes, int32_t precision, 
     if (e == hipSuccess) e = hipEventCreateWithFlags(&h->ev_fork, hipEventDisableTiming);
     if (e == hipSuccess) e = hipEventCreateWithFlags(&h->ev_join, hipEventDisableTiming);
     if (e == hipSuccess) e = hipEventCreateWithFlags(&h->ev_table, hipEventDisableTiming);
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&h->ev_head, hipEventDisableTiming);
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&h->ev_def, hipEventDisableTiming);
     if (e != hipSuccess) {
         std::string msg = std::string("second stream: ") + hipGetErrorString(e);
         lb_free(h);
@@ -683,10 +793,8 @@ lb_status lb_step(lb_handle* h, int64_t n_steps)
         }
     }
     if (left > 0) {
-        for (int64_t k = 0; k < left; ++k) {
-            lb_status s = enqueue_step(h, h->cur ^ (int)(k & 1), (uint32_t)k, true);
-            if (s != LB_OK) return s;
-        }
+        lb_status s = enqueue_steps(h, h->cur, (uint32_t)left);
+        if (s != LB_OK) return s;
         HIPCHK(h, launch_advance(h->ctx, (uint32_t)left));
         if (left & 1) h->cur ^= 1;
         h->step += left;
@@ -704,9 +812,9 @@ lb_status lb_observables(lb_handle* h, lb_obs* out)
     const void* A = h->pop(h->cur);
     double* mid = (double*)(h->scratch + lo.sc_mid);
     if (h->prec == LB_FP64)
-        HIPCHK(h, launch_stats<double>(h->ctx, A, (uint32_t)lo.total_tiles, part, mid, stat));
+        HIPCHK(h, launch_stats<double>(h->ctx, A, lo.stat_max_recs, part, mid, stat));
     else
-        HIPCHK(h, launch_stats<float>(h->ctx, A, (uint32_t)lo.total_tiles, part, mid, stat));
+        HIPCHK(h, launch_stats<float>(h->ctx, A, lo.stat_max_recs, part, mid, stat));
     HIPCHK(h, launch_chain_obs(h->ctx, chain));
     std::vector<double> st(h->n_boxes * NSTAT_REC), ch(h->n_boxes * NCHAIN_REC);
     std::vector<uint32_t> reb(h->n_boxes);
@@ -1047,6 +1155,7 @@ lb_status lb_set_rates(lb_handle* h, int32_t box, double omega_shear, double ome
     b.zeta = zeta;
     b.bead_noise = std::sqrt(2.0 * d.kT * zeta / d.md_dt);
     HIPCHK(h, hipMemcpy(h->scratch + h->lo.sc_boxes + box * sizeof(BoxDev), &b, sizeof b, hipMemcpyHostToDevice));
+    h->boxes_host[box] = b;   // launches that pass a descriptor by value are recorded again below
     if (h->prec == LB_FP64) {
         CollideConst<double> cc = collide_const<double>(d);
         HIPCHK(h, hipMemcpy(h->scratch + h->lo.sc_ccs + box * sizeof(cc), &cc, sizeof cc, hipMemcpyHostToDevice));
@@ -1054,7 +1163,7 @@ lb_status lb_set_rates(lb_handle* h, int32_t box, double omega_shear, double ome
         CollideConst<float> cc = collide_const<float>(d);
         HIPCHK(h, hipMemcpy(h->scratch + h->lo.sc_ccs + box * sizeof(cc), &cc, sizeof cc, hipMemcpyHostToDevice));
     }
-    return LB_OK;
+    return prepare_graphs(h);
 }
 
 lb_status lb_window_forward(lb_handle* h, void* d_ws, size_t bytes, int32_t T, int32_t k, double* vhist_host)
@@ -1314,6 +1423,8 @@ void lb_free(lb_handle* h)
     if (h->ev_fork) (void)hipEventDestroy(h->ev_fork);
     if (h->ev_join) (void)hipEventDestroy(h->ev_join);
     if (h->ev_table) (void)hipEventDestroy(h->ev_table);
+    if (h->ev_head) (void)hipEventDestroy(h->ev_head);
+    if (h->ev_def) (void)hipEventDestroy(h->ev_def);
     if (h->stream2) (void)hipStreamDestroy(h->stream2);
     if (h->own_stream && h->stream) (void)hipStreamDestroy(h->stream);
     delete h;

@@ -52,8 +52,9 @@ def test_query_sizes_layout(lbm):
     # two FP32 deviation buffers of 19 planes plus FP64 bead arrays
     assert 2 * 19 * V * 4 <= s32 < 2 * 19 * V * 4 * 1.01
     assert 2 * 19 * V * 8 <= s64 < 2 * 19 * V * 8 * 1.01
-    # scratch: dense fixed-point node impulses (24 B) and fix-up stamps (4 B) per node
-    assert 28 * V <= c32 < 28 * V + 64 * 2 ** 20
+    # scratch: dense fixed-point node impulses (24 B), fix-up stamps (4 B) and,
+    # with a chain above 256 beads, overflow marks (4 B) per node
+    assert 32 * V <= c32 < 32 * V + 64 * 2 ** 20
     b = [lbinputs.box_params("plain16", L=L, N=N) for L, N in lbinputs.batched_table(256, 1)]
     sb, cb = _sizes(lbm, b, 1)
     nodes = sum(L ** 3 for L, _ in lbinputs.batched_table(256, 1))

@@ -619,7 +619,7 @@ def test_negative_population_count_matches_oracle(orc, prec, kT, N):
     for t in range(40):
         s.step(1)
         o.run(1)
-        g = s.observables()[0]["neg_count"]
+        g = s.observables()[0]["neg"]
         ref = o.observables()[orc.OBS["neg"]]
         near = int(np.count_nonzero(np.abs(o.n) < tol))
         assert abs(g - ref) <= near, (t, g, ref, near)
