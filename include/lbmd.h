@@ -180,6 +180,23 @@ lb_status lb_step(lb_handle* h, int64_t n_steps);
  * NULL arguments, LB_EDEVICE on a HIP failure. */
 lb_status lb_observables(lb_handle* h, lb_obs* out);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the
+ * observables of lb_observables, with the partial sums of the reduction in a
+ * device array the library holds statically (LB_STATIC_SCRATCH_BYTES per
+ * device, from the first lb_init on that device until the process ends)
+ * instead of the handle's scratch buffer.  Allocates nothing.  Same kernels
+ * and summation order as lb_observables, so the same bits.  The partials
+ * take 192 bytes per 2048 nodes of each box (rounded up per box) plus 12.5
+ * KB per box; LB_ENOMEM if they exceed the array (the message gives both
+ * sizes), LB_EDEVICE if the array's device address could not be found at
+ * init.  Every call on one device shares that device's array: calls that
+ * overlap on one GPU (other threads, other handles) race.  Every partial is
+ * written before it is read, so nothing carries over between calls.
+ * Synchronises the handle's stream. */
+#define LB_STATIC_SCRATCH_BYTES ((size_t)8 << 20)
+lb_status lb_observables_static(lb_handle* h, lb_obs* out);
+
 /* Canonical state as FP64 host data, per box in order: 19 planes of L^3 full
  * populations n_i(r, t) of the LB equation (Sec. II.B; pre-collision, plane-
  * major, node r = x + L (y + L z)), then N x 3 each of bead x, v, last total

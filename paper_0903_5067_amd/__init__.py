@@ -72,6 +72,7 @@ def lib() -> ctypes.CDLL:
         L.lb_couple.argtypes = [vp]
         L.lb_step.argtypes = [vp, i64]
         L.lb_observables.argtypes = [vp, ctypes.POINTER(Obs)]
+        L.lb_observables_static.argtypes = [vp, ctypes.POINTER(Obs)]
         L.lb_state_host_bytes.argtypes = [vp]
         L.lb_state_host_bytes.restype = sz
         L.lb_export_state.argtypes = [vp, vp, sz]
@@ -95,7 +96,7 @@ def lib() -> ctypes.CDLL:
         L.lb_free.restype = None
         L.lb_last_error.argtypes = [vp]
         L.lb_last_error.restype = ctypes.c_char_p
-        for name in ("lb_query_sizes", "lb_init", "lb_couple", "lb_step", "lb_observables",
+        for name in ("lb_query_sizes", "lb_init", "lb_couple", "lb_step", "lb_observables", "lb_observables_static",
                      "lb_export_state", "lb_import_state", "lb_pending_impulse",
                      "lb_velocity_history", "lb_bead_positions", "lb_set_launch", "lb_collide_only", "lb_window_forward",
                      "lb_window_backward", "lb_window_rewind", "lb_set_rates", "lb_autotune",
@@ -195,9 +196,11 @@ class LBSystem:
         self.stream.synchronize()
 
     # -- observation ------------------------------------------------------
-    def observables(self, allow_unhealthy: bool = False) -> list[dict]:
+    def observables(self, allow_unhealthy: bool = False, static: bool = False) -> list[dict]:
+        """Observables of every box (lb_observables); static=True takes the
+        entry point that allocates nothing (lb_observables_static)."""
         out = (Obs * len(self.boxes))()
-        st = lib().lb_observables(self.h, out)
+        st = (lib().lb_observables_static if static else lib().lb_observables)(self.h, out)
         if st != LB_OK and not (allow_unhealthy and st == LB_ENUMERIC):
             _check(st, self.h)
         res = []

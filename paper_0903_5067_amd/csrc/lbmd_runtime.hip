@@ -12,6 +12,7 @@
 #include <cmath>
 #include <cstdlib>
 #include <cstring>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -20,7 +21,34 @@
 
 using namespace lbd;
 
+// Device memory of lb_observables_static: the partial sums of its reduction
+// live in this file-scope array instead of the caller's scratch buffer, for
+// callers that cannot allocate.  Each device the library runs on holds its
+// own copy, at its own address, until the process ends.  In host code the
+// name stands for a host-side symbol, not a device address: kernels receive
+// the address hipGetSymbolAddress gives for the current device (static_scratch).
+constexpr size_t STATIC_SCRATCH_BYTES = LB_STATIC_SCRATCH_BYTES;
+static __device__ __align__(256) unsigned char scratch[STATIC_SCRATCH_BYTES];
+
 namespace {
+
+constexpr int MAX_DEVICES = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_dev[MAX_DEVICES] = {};
+
+// the device address of `scratch` on device dev (the current device), looked
+// up once per device; null if the runtime could not give it
+void* static_scratch(int dev)
+{
+    if (dev < 0 || dev >= MAX_DEVICES) return nullptr;
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_dev[dev]) {
+        void* p = nullptr;
+        if (hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)) == hipSuccess) g_scratch_dev[dev] = p;
+        else (void)hipGetLastError();
+    }
+    return g_scratch_dev[dev];
+}
 
 thread_local std::string g_err;
 
@@ -246,6 +274,8 @@ CollideConst<R> collide_const(const lb_box_desc& d)
 
 struct lb_handle {
     int n_boxes = 0;
+    int dev = 0;                      // the device the handle was set up on
+    void* static_scr = nullptr;       // that device's address of the static array (lb_observables_static)
     int prec = LB_FP32_DEV;
     int hist = 0;
     std::vector<lb_box_desc> desc;
@@ -665,6 +695,8 @@ lb_status lb_init(const lb_box_desc* boxes, int32_t n_boxes, int32_t precision, 
         }
         c.n_cu = ncu;
         c.collide_variant = DEFAULT_COLLIDE_VARIANT;
+        h->dev = dev;
+        h->static_scr = static_scratch(dev);   // once per device, this device current
     }
     c.boxes = (const BoxDev*)sc(lo.sc_boxes);
     h->boxes_host = bd;
@@ -802,6 +834,41 @@ lb_status lb_step(lb_handle* h, int64_t n_steps)
     return LB_OK;
 }
 
+}  // extern "C"
+
+namespace {
+
+// one box's lb_obs from its stats record s [NSTAT_REC] and chain record c
+// [NCHAIN_REC]
+void fill_obs(const lb_handle* h, int i, const double* s, const double* c, uint32_t rebuilds, const Ctrl& ctrl,
+              lb_obs& o)
+{
+    const lb_box_desc& d = h->desc[i];
+    std::memset(&o, 0, sizeof o);
+    o.mass = (double)h->lo.V[i] * d.rho0 + s[0];
+    for (int a = 0; a < 3; ++a) {
+        o.j_lat[a] = s[1 + a];
+        o.p_fluid[a] = s[1 + a] / d.tau_lb;
+        o.p_beads[a] = c[3 + a];
+        o.p_total[a] = o.p_fluid[a] + o.p_beads[a] + 0.5 * d.md_dt * c[6 + a];
+        o.com[a] = d.n_beads > 0 ? c[a] / d.n_beads : 0.0;
+    }
+    // record: [9] sum over chains of R_e^2, [10] sum over beads of the
+    // square distance to their chain's centre of mass
+    const int chains = d.n_beads > 0 ? (d.chain_len > 0 ? d.n_beads / d.chain_len : 1) : 1;
+    o.rg2 = d.n_beads > 0 ? c[10] / d.n_beads : 0.0;
+    o.re2 = c[9] / chains;
+    o.neg_count = s[4];
+    for (int k = 0; k < 19; ++k) o.mode_sq[k] = s[5 + k];
+    o.health = ctrl.health;
+    o.nlist_builds = rebuilds;
+    o.step = ctrl.step;
+}
+
+}  // namespace
+
+extern "C" {
+
 lb_status lb_observables(lb_handle* h, lb_obs* out)
 {
     if (!h || !out) return fail(h, LB_EINVAL, "null argument");
@@ -824,30 +891,56 @@ lb_status lb_observables(lb_handle* h, lb_obs* out)
     HIPCHK(h, hipMemcpyAsync(ch.data(), chain, ch.size() * sizeof(double), hipMemcpyDeviceToHost, h->stream));
     HIPCHK(h, hipMemcpyAsync(&ctrl, h->scratch + lo.sc_ctrl, sizeof ctrl, hipMemcpyDeviceToHost, h->stream));
     HIPCHK(h, hipStreamSynchronize(h->stream));
-    for (int i = 0; i < h->n_boxes; ++i) {
-        const lb_box_desc& d = h->desc[i];
-        const double* s = &st[i * NSTAT_REC];
-        const double* c = &ch[i * NCHAIN_REC];
-        lb_obs& o = out[i];
-        std::memset(&o, 0, sizeof o);
-        o.mass = (double)lo.V[i] * d.rho0 + s[0];
-        for (int a = 0; a < 3; ++a) {
-            o.j_lat[a] = s[1 + a];
-            o.p_fluid[a] = s[1 + a] / d.tau_lb;
-            o.p_beads[a] = c[3 + a];
-            o.p_total[a] = o.p_fluid[a] + o.p_beads[a] + 0.5 * d.md_dt * c[6 + a];
-            o.com[a] = d.n_beads > 0 ? c[a] / d.n_beads : 0.0;
-        }
-        // record: [9] sum over chains of R_e^2, [10] sum over beads of the
-        // square distance to their chain's centre of mass
-        const int chains = d.n_beads > 0 ? (d.chain_len > 0 ? d.n_beads / d.chain_len : 1) : 1;
-        o.rg2 = d.n_beads > 0 ? c[10] / d.n_beads : 0.0;
-        o.re2 = c[9] / chains;
-        o.neg_count = s[4];
-        for (int k = 0; k < 19; ++k) o.mode_sq[k] = s[5 + k];
-        o.health = ctrl.health;
-        o.nlist_builds = reb[i];
-        o.step = ctrl.step;
+    for (int i = 0; i < h->n_boxes; ++i)
+        fill_obs(h, i, &st[i * NSTAT_REC], &ch[i * NCHAIN_REC], reb[i], ctrl, out[i]);
+    if (ctrl.health) return fail(h, LB_ENUMERIC, "device health flags set: " + std::to_string(ctrl.health));
+    return LB_OK;
+}
+
+lb_status lb_observables_static(lb_handle* h, lb_obs* out)
+{
+    if (!h || !out) return fail(h, LB_EINVAL, "null argument");
+    if (!h->static_scr) return fail(h, LB_EDEVICE, "no device address for the static partial-sum array");
+    const Layout& lo = h->lo;
+    // partials in the static array: block records, chunk sums, box sums, chain records
+    const size_t part_b = align256((size_t)lo.stat_recs * NSTAT_REC * sizeof(double));
+    const size_t mid_b = align256((size_t)h->n_boxes * STAT_CHUNKS * NSTAT_REC * sizeof(double));
+    const size_t stat_b = align256((size_t)h->n_boxes * NSTAT_REC * sizeof(double));
+    const size_t chain_b = align256((size_t)h->n_boxes * NCHAIN_REC * sizeof(double));
+    if (part_b + mid_b + stat_b + chain_b > STATIC_SCRATCH_BYTES)
+        return fail(h, LB_ENOMEM, "boxes need " + std::to_string(part_b + mid_b + stat_b + chain_b) +
+                                      " bytes of partial sums; the static array holds " +
+                                      std::to_string(STATIC_SCRATCH_BYTES));
+    char* base = (char*)h->static_scr;
+    double* part = (double*)base;
+    double* mid = (double*)(base + part_b);
+    double* stat = (double*)(base + part_b + mid_b);
+    double* chain = (double*)(base + part_b + mid_b + stat_b);
+    const void* A = h->pop(h->cur);
+    // every partial the kernels read is written earlier in the same call, so
+    // no value carries over from a previous call
+    if (h->prec == LB_FP64)
+        HIPCHK(h, launch_stats<double>(h->ctx, A, lo.stat_max_recs, part, mid, stat));
+    else
+        HIPCHK(h, launch_stats<float>(h->ctx, A, lo.stat_max_recs, part, mid, stat));
+    HIPCHK(h, launch_chain_obs(h->ctx, chain));
+    Ctrl ctrl;
+    HIPCHK(h, hipMemcpyAsync(&ctrl, h->scratch + lo.sc_ctrl, sizeof ctrl, hipMemcpyDeviceToHost, h->stream));
+    // results to the host in chunks of boxes, through fixed buffers
+    constexpr int CH = 32;
+    double st[CH * NSTAT_REC], ch[CH * NCHAIN_REC];
+    uint32_t reb[CH];
+    for (int b0 = 0; b0 < h->n_boxes; b0 += CH) {
+        const int nb = std::min(CH, h->n_boxes - b0);
+        HIPCHK(h, hipMemcpyAsync(st, stat + (size_t)b0 * NSTAT_REC, (size_t)nb * NSTAT_REC * sizeof(double),
+                                 hipMemcpyDeviceToHost, h->stream));
+        HIPCHK(h, hipMemcpyAsync(ch, chain + (size_t)b0 * NCHAIN_REC, (size_t)nb * NCHAIN_REC * sizeof(double),
+                                 hipMemcpyDeviceToHost, h->stream));
+        HIPCHK(h, hipMemcpyAsync(reb, h->scratch + lo.sc_nlreb + (size_t)b0 * sizeof(uint32_t),
+                                 (size_t)nb * sizeof(uint32_t), hipMemcpyDeviceToHost, h->stream));
+        HIPCHK(h, hipStreamSynchronize(h->stream));
+        for (int i = 0; i < nb; ++i)
+            fill_obs(h, b0 + i, &st[i * NSTAT_REC], &ch[i * NCHAIN_REC], reb[i], ctrl, out[b0 + i]);
     }
     if (ctrl.health) return fail(h, LB_ENUMERIC, "device health flags set: " + std::to_string(ctrl.health));
     return LB_OK;
