@@ -445,12 +445,14 @@ def main():
     elif args.fixup_after_collide:
         s.set_launch(batched=True, graph_steps=0, overlap=False)
     tune = None
+    import paper_0903_5067_amd as lbm
     if args.variant >= 0:
         s.set_collide_variant(args.variant)
-        tune = {"chosen": args.variant, "forced": True}
+        tune = {"chosen": args.variant, "shape": lbm.COLLIDE_VARIANT_SHAPES[args.variant], "forced": True}
     elif not args.no_autotune:
         chosen, times = s.autotune(reps=20)
-        tune = {"chosen": chosen, "us_per_variant": [round(t, 2) for t in times]}
+        tune = {"chosen": chosen, "shape": lbm.COLLIDE_VARIANT_SHAPES[chosen],
+                "us_per_variant": [round(t, 2) for t in times]}
         log("autotune", json.dumps(tune))
     obs0 = s.observables()[0]
     t_ev, t_wall = time_steps(s, args.steps, args.warmup)

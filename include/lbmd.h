@@ -294,8 +294,11 @@ lb_status lb_collide_only(lb_handle* h, int32_t n);
 /* ---- launch-shape autotuning of the collide+stream kernel ---------------
  * LB_N_COLLIDE_VARIANTS launch shapes compute identical values (same per-node
  * arithmetic, bit for bit); they differ in the cap on resident waves per SIMD
- * (4..8) and in the grid: one workgroup per 256-node tile (variants 0..4) or
- * a grid of n_CU x waves workgroups that strides over the tiles (5..9).
+ * (4..8), in the nodes per workgroup and in the grid: one workgroup per
+ * 256-node tile (variants 0..4, at most 4..8 waves per SIMD), a grid of
+ * n_CU x waves workgroups that strides over the tiles (5..9), one workgroup
+ * per 512 nodes (10: at most 4 waves per SIMD; 11: at most 6) or per 1024
+ * nodes (12).
  * lb_autotune times every variant on the handle's own state (two sweeps; in
  * each, reps launches per variant after two untimed ones, HIP events on the
  * handle's stream, no state change), selects the fastest, drops recorded
@@ -304,7 +307,7 @@ lb_status lb_collide_only(lb_handle* h, int32_t n);
  * times_us[LB_N_COLLIDE_VARIANTS] (may be NULL) and the choice to *chosen (may
  * be NULL).  lb_set_collide_variant forces one (LB_EINVAL out of range).
  * The arithmetic is the LB equation of Sec. II.B in every shape. */
-#define LB_N_COLLIDE_VARIANTS 10
+#define LB_N_COLLIDE_VARIANTS 13
 lb_status lb_autotune(lb_handle* h, int32_t reps, float* times_us, int32_t* chosen);
 lb_status lb_set_collide_variant(lb_handle* h, int32_t variant);
 

@@ -17,7 +17,15 @@ LIB_PATH = os.path.join(_HERE, "liblbmd.so")
 
 LB_OK, LB_EINVAL, LB_ENOMEM, LB_EDEVICE, LB_ENUMERIC, LB_ESTATE = 0, -1, -2, -3, -4, -5
 FP64, FP32_DEV = 0, 1
-N_COLLIDE_VARIANTS = 10
+N_COLLIDE_VARIANTS = 13
+# launch shape of each collide variant (include/lbmd.h): nodes per workgroup,
+# cap on waves per SIMD, grid form
+COLLIDE_VARIANT_SHAPES = (
+    [{"nodes_per_workgroup": 256, "max_waves_per_simd": w, "grid": "one workgroup per tile"} for w in range(4, 9)]
+    + [{"nodes_per_workgroup": 256, "max_waves_per_simd": w, "grid": "n_CU x waves, strided"} for w in range(4, 9)]
+    + [{"nodes_per_workgroup": 512, "max_waves_per_simd": 4, "grid": "one workgroup per tile"},
+       {"nodes_per_workgroup": 512, "max_waves_per_simd": 6, "grid": "one workgroup per tile"},
+       {"nodes_per_workgroup": 1024, "max_waves_per_simd": 4, "grid": "one workgroup per tile"}])
 HEALTH = {"density": 0x1, "mach": 0x2, "fene": 0x4, "table": 0x8, "fixed": 0x10}
 
 

@@ -91,7 +91,7 @@ template <typename R>
 __device__ __forceinline__ void collide_tile(const BoxDev* __restrict__ boxes, const CollideConst<R>* __restrict__ ccs,
                                              const uint32_t* __restrict__ tile_box, int fixed_box, uint32_t tile,
                                              const R* __restrict__ A, R* __restrict__ B, Ctrl* __restrict__ ctrl,
-                                             uint32_t t, const uint32_t* __restrict__ defer)
+                                             uint32_t t, const uint32_t* __restrict__ defer, uint32_t lane)
 {
     int bi;
     if (defer) {   // batched steps (every tile's box from tile_box)
@@ -106,7 +106,7 @@ __device__ __forceinline__ void collide_tile(const BoxDev* __restrict__ boxes, c
     const BoxDev& bx = boxes[bi];
     const int L = bx.L;
     const uint32_t V = (uint32_t)L * L * L;
-    const uint32_t r = (tile - bx.tile_begin) * 256u + threadIdx.x;
+    const uint32_t r = (tile - bx.tile_begin) * 256u + lane;
     if (r >= V) return;
     const CollideConst<R> cc = ccs[bi];
     const Upwind up = upwind_of(r, L, bx.inv_L);
@@ -120,21 +120,35 @@ __device__ __forceinline__ void collide_tile(const BoxDev* __restrict__ boxes, c
     if (h) atomicOr(&ctrl->health, h);
 }
 
-// Launch shapes the autotuner chooses from: W caps the waves per SIMD (4..8),
-// PERSIST selects a grid of a few blocks per CU that strides over the tiles
-// instead of one block per tile.  All shapes compute the same values.
-template <typename R, int W, bool PERSIST>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, W))) void k_collide(
+// Launch shapes the autotuner chooses from: W caps the waves per SIMD (4..8);
+// BT threads per block collide BT / 256 consecutive 256-node tiles (256, 512
+// or 1024 nodes per block); PERSIST selects a grid of a few blocks per CU
+// that strides over the tiles instead of one block per tile group.  Every
+// node gets the same per-node arithmetic, so all shapes compute the same bits.
+template <typename R, int W, bool PERSIST, int BT = 256>
+__global__ __launch_bounds__(BT) __attribute__((amdgpu_waves_per_eu(1, W))) void k_collide(
     const BoxDev* __restrict__ boxes, const CollideConst<R>* __restrict__ ccs, const uint32_t* __restrict__ tile_box,
     int fixed_box, uint32_t tile0, uint32_t n_tiles, const R* __restrict__ A, R* __restrict__ B,
     Ctrl* __restrict__ ctrl, uint32_t s_off, const uint32_t* __restrict__ defer)
 {
+    constexpr uint32_t M = BT / 256;   // 256-node tiles per block
     const uint32_t t = ctrl->step + s_off;
-    if (PERSIST) {
-        for (uint32_t k = blockIdx.x; k < n_tiles; k += gridDim.x)
-            collide_tile<R>(boxes, ccs, tile_box, fixed_box, tile0 + k, A, B, ctrl, t, defer);
+    if constexpr (M == 1) {
+        if (PERSIST) {
+            for (uint32_t k = blockIdx.x; k < n_tiles; k += gridDim.x)
+                collide_tile<R>(boxes, ccs, tile_box, fixed_box, tile0 + k, A, B, ctrl, t, defer, threadIdx.x);
+        } else {
+            collide_tile<R>(boxes, ccs, tile_box, fixed_box, tile0 + blockIdx.x, A, B, ctrl, t, defer, threadIdx.x);
+        }
     } else {
-        collide_tile<R>(boxes, ccs, tile_box, fixed_box, tile0 + blockIdx.x, A, B, ctrl, t, defer);
+        const uint32_t sub = threadIdx.x / 256u, lane = threadIdx.x % 256u;
+        if (PERSIST) {
+            for (uint32_t k = blockIdx.x * M + sub; k < n_tiles; k += gridDim.x * M)
+                collide_tile<R>(boxes, ccs, tile_box, fixed_box, tile0 + k, A, B, ctrl, t, defer, lane);
+        } else {
+            const uint32_t k = blockIdx.x * M + sub;
+            if (k < n_tiles) collide_tile<R>(boxes, ccs, tile_box, fixed_box, tile0 + k, A, B, ctrl, t, defer, lane);
+        }
     }
 }
 
@@ -633,7 +647,7 @@ __global__ __launch_bounds__(256) void k_near_nodes(const BoxDev* __restrict__ b
         }
     }
     const int bi = one_box >= 0 ? one_box : list[blockIdx.y];
-    const BoxDev& bx = one_box >= 0 ? one : boxes[bi];
+    const BoxDev bx = one_box >= 0 ? one : boxes[bi];   // a copy: its fields stay in registers
     const int N = bx.N, L = bx.L;
     const int tid = (int)(blockIdx.x * blockDim.x + threadIdx.x);
     if (tid >= N * NEAR) return;
@@ -657,10 +671,20 @@ __global__ __launch_bounds__(256) void k_near_nodes(const BoxDev* __restrict__ b
     R d[19];
     gather_pre<R, false>(A + bx.pop_off, up, d);
     if (n_pend) {
+        // directions whose source node the previous step listed; every array
+        // index below is a compile-time constant, so d and oo stay in registers
         const uint32_t pst = defer_stamp(t - 1u);
-        for (int i = 0; i < 19; ++i) {
-            const uint32_t src = up.src(i);
-            if (ca.ovm[bx.node_off + src] != pst) continue;
+        uint32_t need = 0;
+#pragma unroll
+        for (int i = 0; i < 19; ++i)
+            if (ca.ovm[bx.node_off + up.src(i)] == pst) need |= 1u << i;
+        while (need) {
+            const int ik = __builtin_ctz(need);
+            need &= need - 1u;
+            uint32_t src = 0;
+#pragma unroll
+            for (int j = 0; j < 19; ++j)
+                if (j == ik) src = up.src(j);
             R dd[19], oo[19];
             gather_pre<R, false>(Aprev + bx.pop_off, upwind_of(src, L, bx.inv_L), dd);
             const unsigned long long* qi = ca.imp + 3 * (bx.node_off + src);
@@ -668,7 +692,9 @@ __global__ __launch_bounds__(256) void k_near_nodes(const BoxDev* __restrict__ b
                     fy = (R)((double)(long long)qi[1] * IMP_INV_SCALE),
                     fz = (R)((double)(long long)qi[2] * IMP_INV_SCALE);
             (void)collide<R>(dd, oo, fx, fy, fz, ccs[bi], src, t - 1u, bx.seed, bx.box_id);
-            d[i] = oo[i];
+#pragma unroll
+            for (int j = 0; j < 19; ++j)
+                if (j == ik) d[j] = oo[j];
         }
     }
     if (ca.defer)   // the bead's stencil stays on its table's nodes while it moves less
@@ -1616,12 +1642,14 @@ static ChainArgs chain_args(const LaunchCtx& c)
                      c.defer_on ? c.defer : nullptr, c.dclaim, c.defer_list, c.defer_cap, c.ovf, c.ovf_cap, c.ovm};
 }
 
-template <typename R, int W, bool PERSIST>
+template <typename R, int W, bool PERSIST, int BT = 256>
 static void launch_collide_v(const LaunchCtx& c, const void* A, void* B, int fixed_box, uint32_t tile0,
                              uint32_t n_tiles, uint32_t s_off)
 {
-    const uint32_t grid = PERSIST ? std::min<uint32_t>(n_tiles, (uint32_t)(c.n_cu * W)) : n_tiles;
-    hipLaunchKernelGGL((k_collide<R, W, PERSIST>), dim3(grid), dim3(256), 0, c.stream, c.boxes,
+    constexpr uint32_t M = BT / 256;
+    const uint32_t groups = (n_tiles + M - 1) / M;
+    const uint32_t grid = PERSIST ? std::min<uint32_t>(groups, (uint32_t)(c.n_cu * W)) : groups;
+    hipLaunchKernelGGL((k_collide<R, W, PERSIST, BT>), dim3(grid), dim3(BT), 0, c.stream, c.boxes,
                        (const CollideConst<R>*)c.ccs, c.tile_box, fixed_box, tile0, n_tiles, (const R*)A, (R*)B,
                        c.ctrl, s_off, c.defer_on ? (const uint32_t*)c.defer : nullptr);
 }
@@ -1641,7 +1669,10 @@ hipError_t launch_collide(const LaunchCtx& c, const void* A, void* B, int fixed_
     case 6: launch_collide_v<R, 5, true>(c, A, B, fixed_box, tile0, n_tiles, s_off); break;
     case 7: launch_collide_v<R, 6, true>(c, A, B, fixed_box, tile0, n_tiles, s_off); break;
     case 8: launch_collide_v<R, 7, true>(c, A, B, fixed_box, tile0, n_tiles, s_off); break;
-    default: launch_collide_v<R, 8, true>(c, A, B, fixed_box, tile0, n_tiles, s_off); break;
+    case 9: launch_collide_v<R, 8, true>(c, A, B, fixed_box, tile0, n_tiles, s_off); break;
+    case 10: launch_collide_v<R, 4, false, 512>(c, A, B, fixed_box, tile0, n_tiles, s_off); break;
+    case 11: launch_collide_v<R, 6, false, 512>(c, A, B, fixed_box, tile0, n_tiles, s_off); break;
+    default: launch_collide_v<R, 4, false, 1024>(c, A, B, fixed_box, tile0, n_tiles, s_off); break;
     }
     return hipGetLastError();
 }

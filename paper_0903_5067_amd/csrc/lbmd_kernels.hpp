@@ -118,7 +118,7 @@ template <typename R>
 hipError_t launch_adj_couple(const LaunchCtx& c, const int32_t* list, int n_list, int block, const void* P,
                              const AdjArgsHost& a, uint32_t step);
 
-constexpr int N_COLLIDE_VARIANTS = 10;
+constexpr int N_COLLIDE_VARIANTS = 13;
 constexpr int DEFAULT_COLLIDE_VARIANT = 3;   // one block per tile, at most 7 waves per SIMD
 constexpr int NSTAT_REC = 24;
 constexpr int STAT_TPB = 8;       // collide tiles per block of the observables pass (8 nodes per thread)

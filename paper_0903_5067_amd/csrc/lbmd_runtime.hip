@@ -539,9 +539,6 @@ lb_status build_graph(lb_handle* h, int parity)
     if (e != hipSuccess) return fail(h, LB_EDEVICE, std::string("graph capture: ") + hipGetErrorString(e));
     h->graph[parity] = g;
     HIPCHK(h, hipGraphInstantiate(&h->gexec[parity], g, nullptr, nullptr, 0));
-    // move the executable graph to the device now rather than at its first
-    // launch; a runtime without the call keeps the lazy upload
-    if (hipGraphUpload(h->gexec[parity], h->stream) != hipSuccess) (void)hipGetLastError();
     return LB_OK;
 }
 

@@ -13,7 +13,8 @@ dynamic ones from the sampled centre of mass and the two innermost beads:
   g1 exponent over t in [20, 80], D_CM from g3 = 6 D t over the same window
   and over [100, 1000], tau_tr = <R_g^2> / (6 D_CM), the first Rouse mode's
   autocorrelation at t = 700,
-and the beads' kinetic temperature <m v^2> / 3 against kT.
+the beads' kinetic temperature <m v^2> / 3 against kT, and the fraction of
+populations n_i < 0 at the samples (Sec. II.E).
 
     python -m paper_0903_5067_amd.table1 --L 10 15 --boxes 128 --out result.json
     python -m paper_0903_5067_amd.table1 --therm 1 ...   (stress modes only)
@@ -80,12 +81,16 @@ def run_box_size(L: int, n_boxes: int, equil_tau: float, prod_tau: float, sample
     snaps = []
     mid = [N // 2 - 1, N // 2]
     health = 0
+    neg = 0.0          # populations n_i < 0 summed over samples and boxes (Sec. II.E)
+    neg_max = 0.0      # the most in one box at one sample
     for k in range(n_s):
         s.step(every)
         obs = s.observables()
         for b, o in enumerate(obs):
             com[k, b], rg2[k, b], re2[k, b] = o["com"], o["rg2"], o["re2"]
             health |= o["health"]
+            neg += o["neg"]
+            neg_max = max(neg_max, o["neg"])
         x = s.bead_positions().reshape(n_boxes, N, 3)
         mids[k] = x[:, mid]
         modes[k] = an.rouse_modes(x, 5)
@@ -106,7 +111,10 @@ def run_box_size(L: int, n_boxes: int, equil_tau: float, prod_tau: float, sample
     res = {"L": L, "boxes": n_boxes, "precision": "fp32_dev" if prec == lbm.FP32_DEV else "fp64",
            "thermalize": "all modes" if therm == 2 else ("stress modes" if therm == 1 else "none"),
            "equil_tau": n_eq * every * tau, "prod_tau": n_s * every * tau, "sample_tau": every * tau,
-           "lb_steps": (n_eq + n_s) * every, "wall_s": round(wall, 1), "health": int(health)}
+           "lb_steps": (n_eq + n_s) * every, "wall_s": round(wall, 1), "health": int(health),
+           # Sec. II.E chooses the LB step so that populations rarely go negative
+           "negative_population_fraction": neg / (n_s * n_boxes * 19 * L ** 3),
+           "negative_populations_max_per_box": int(neg_max)}
     res["re2"] = box_mean(re2)
     res["rg2"] = box_mean(rg2)
     ks = np.geomspace(0.3, 3.0, 24)

@@ -71,6 +71,39 @@ def test_adjoint_linear_functional_matches_oracle_tangent(orc, prec, tol):
     np.testing.assert_allclose(grad, ref, rtol=tol, atol=tol * np.max(np.abs(ref)))
 
 
+@pytest.mark.parametrize("prec,tol", [(FP64, 1e-8), (FP32, 2e-3)])
+@pytest.mark.parametrize("T", [1, 2])
+def test_adjoint_of_one_operator_is_the_transpose_of_the_tangent(orc, prec, tol, T):
+    """Dot-product test of single operators: for J = <w, v> with several random
+    w, the reverse sweep gives <J^T w, e_theta> and the oracle's forward
+    tangent gives <w, J e_theta> for each rate direction e_theta; they agree
+    for every w.  A one-step window holds the coupling alone (the velocities
+    after the first step depend on the fluid's rates only through later steps,
+    so both sides give exactly zero there); a two-step window adds exactly one
+    collide and one stream between the two couplings."""
+    say("adjoint transpose", prec, T)
+    p = _case(omega_s=1.3, omega_b=0.7)
+    x0 = chain(p)
+    n0 = initial_pops(orc, p, amp=0.02, seed=21)
+    s = gpu_system([p], prec, xs=[x0], pops=[n0])
+    vh = s.window_forward(T, 1)
+    o = oracle_state(orc, p, n0, x0)
+    ho, dh = o.window_tangent(T)
+    assert np.max(np.abs(vh - ho)) < (1e-10 if prec == FP64 else 1e-5)
+    rng = np.random.default_rng(30 + T)
+    for _ in range(3):
+        w = rng.normal(size=vh.shape)
+        grad = s.window_backward(w)[0]
+        ref = np.einsum("tna,tnak->k", w, dh)
+        if T == 1:
+            assert ref[0] == 0.0 and ref[1] == 0.0
+            assert grad[0] == 0.0 and grad[1] == 0.0
+        else:
+            assert abs(ref[0]) > 0 and abs(ref[1]) > 0
+        np.testing.assert_allclose(grad, ref, rtol=tol, atol=tol * np.max(np.abs(ref)))
+    s.close()
+
+
 @pytest.mark.parametrize("prec,tol", [(FP64, 1e-7), (FP32, 2e-3)])
 def test_adjoint_several_chains_matches_oracle_tangent(orc, prec, tol):
     """Four chains of six beads in one box (bonds along each chain only): the
