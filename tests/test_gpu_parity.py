@@ -399,6 +399,42 @@ def test_deferred_tiles_equal_fixup_after_collide_bitwise(prec, graph_steps):
             assert np.array_equal(out[0][i][k], out[1][i][k]), (i, k)
 
 
+@pytest.mark.parametrize("prec,graph_steps", [(FP64, 0), (FP32, 0), (FP64, 4), (FP32, 6)])
+def test_two_queue_runs_equal_fixup_after_collide_bitwise(prec, graph_steps):
+    """With no dense box, a run of batched steps alternates its two queues:
+    each step's node-table kernel also re-collides the previous step's
+    impulses outside its deferred tiles.  Twelve steps in one call (one run,
+    or graph replays of several steps) give the bits of twelve steps with
+    the chain's nodes re-collided after each collide; the hot box's beads
+    leave their node tables within the twelve steps."""
+    say("two-queue runs vs fix-up", prec, graph_steps)
+    hot = dict(kT=1.0, therm=0, md_dt=0.01, md_substeps=25, tau_lb=0.25, zeta=1.0, k_fene=7.0, r0_fene=2.0)
+    boxes = [params(L=40, N=300, kT=1e-2, seed=7, box_id=0),
+             params(L=40, N=300, seed=7, box_id=1, **hot),
+             params(L=12, N=16, kT=1e-2, seed=7, box_id=2)]
+    xs = [chain(b) for b in boxes]
+    ref = gpu_system(boxes, prec, xs=xs)
+    ref.set_launch(batched=True, graph_steps=0, overlap=False)
+    left = 0
+    for _ in range(12):
+        x_a = ref.bead_positions()[300:600]
+        ref.step(1)
+        left += int(_left_table(x_a, ref.bead_positions()[300:600], 40).sum())
+    assert left > 0
+    assert all(o["health"] == 0 for o in ref.observables())
+    want = ref.export_state()["boxes"]
+    ref.close()
+    s = gpu_system(boxes, prec, xs=xs)
+    s.set_launch(batched=True, graph_steps=graph_steps, overlap=True)
+    s.step(12)
+    assert all(o["health"] == 0 for o in s.observables())
+    got = s.export_state()["boxes"]
+    s.close()
+    for i in range(len(boxes)):
+        for k in ("n", "x", "v", "f", "fc"):
+            assert np.array_equal(got[i][k], want[i][k]), (i, k)
+
+
 @pytest.mark.parametrize("prec", [FP64, FP32])
 def test_deferred_tiles_after_restoring_an_earlier_step(prec):
     """The deferral stamps of later steps must not survive an import that
