@@ -68,6 +68,7 @@ typedef enum { LB_THERM_OFF = 0, LB_THERM_STRESS = 1, LB_THERM_ALL = 2 } lb_ther
 #define LB_HEALTH_FENE 0x4u     /* a bond reached R0 */
 #define LB_HEALTH_TABLE 0x8u    /* a node-impulse list overflowed (touched nodes, impulses outside deferred tiles) */
 #define LB_HEALTH_FIXED 0x10u   /* node impulse outside the fixed-point range */
+#define LB_HEALTH_SYNC 0x40u    /* a bounded wait of one kernel for a concurrent one gave up (results of the step invalid) */
 
 /* One box.  An array of these is a batch of independent boxes. */
 typedef struct {

@@ -57,8 +57,11 @@ __host__ __device__ __forceinline__ uint64_t pop_elems_of(uint64_t V)
 struct Ctrl {
     uint32_t step;
     uint32_t health;
-    uint32_t defer_cnt;   // collide tiles deferred this step (reset at the step's end)
-    uint32_t ovf_cnt;     // impulses of this step outside the deferred tiles
+    uint32_t defer_cnt;     // collide tiles deferred this step (reset at the step's end)
+    uint32_t ovf_cnt;       // impulses of this step outside the deferred tiles
+    uint32_t ovf_flag[2];   // [t & 1]: the deferral stamp of step t if it listed any such impulse
+    uint32_t head_done[2];  // [t & 1]: node-table workgroups of step t's collide that are done
+    uint32_t head_fix[2];   // [t & 1]: those that have done their part of step t-1's overflow fix-up
 };
 
 // Tag of step t in the per-tile deferral stamps: never 0 (the cleared value),
@@ -73,6 +76,7 @@ enum : uint32_t {
     H_TABLE = 1u << 3,     // impulse table full
     H_FIXED = 1u << 4,     // impulse outside the fixed-point range
     H_NLIST = 1u << 5,     // neighbour list overflow
+    H_SYNC = 1u << 6,      // a bounded wait for a concurrent kernel gave up
 };
 
 // fixed-point scale of the node impulse accumulator (lattice momentum units):

@@ -97,7 +97,7 @@ __device__ __forceinline__ void collide_tile(const BoxDev* __restrict__ boxes, c
     if (defer) {   // batched steps (every tile's box from tile_box)
         // a deferred tile is collided after the coupling, with its impulses
         // (k_collide_deferred); the stamp load goes out beside the box load
-        const uint32_t st = defer[tile];
+        const uint32_t st = defer[2u * tile + (t & 1u)];
         bi = (int)tile_box[tile];
         if (st == defer_stamp(t)) return;
     } else {
@@ -615,43 +615,66 @@ __device__ __forceinline__ void fixup_node(const BoxDev& bx, const CollideConst<
                                            uint32_t* __restrict__ claim, const R* __restrict__ A, R* __restrict__ B,
                                            Ctrl* __restrict__ ctrl, uint32_t t, int keep_imp);
 
-// The node table of the step.  With Aprev (batched steps that defer tiles,
-// from the second step of a run of steps on) it also finishes the previous
-// step: the impulses that landed outside that step's deferred tiles are
-// collided again (Aprev -> A, the previous step's number), their impulses
-// left in the field for the chain kernel to clear.  A table node whose
-// population comes from such a node takes the fixed value computed here
-// instead of reading it, so no thread reads what another writes.
+// the same fix-up (impulses left in the field), the node claimed before its
+// populations are read: fewer live registers, for a rare path inside a
+// bandwidth-bound kernel
 template <typename R>
-__global__ __launch_bounds__(256) void k_near_nodes(const BoxDev* __restrict__ boxes,
-                                                    const int32_t* __restrict__ list, R* A,
-                                                    ChainArgs ca, R* __restrict__ near_u, int4* __restrict__ near_c,
-                                                    const R* __restrict__ field, Ctrl* __restrict__ ctrl,
-                                                    uint32_t s_off, const CollideConst<R>* __restrict__ ccs,
-                                                    const int32_t* __restrict__ bead_box,
-                                                    uint32_t* __restrict__ claim, const R* __restrict__ Aprev,
-                                                    int one_box, BoxDev one)
+__device__ __forceinline__ void fixup_node_claim_first(const BoxDev& bx, const CollideConst<R>* __restrict__ ccs,
+                                                       int bi, uint32_t r, const unsigned long long* __restrict__ imp,
+                                                       uint32_t* __restrict__ claim, const R* __restrict__ A,
+                                                       R* __restrict__ B, Ctrl* __restrict__ ctrl, uint32_t t)
 {
-    // one_box >= 0: the launch covers that box alone, its descriptor passed by
-    // value (no dependent loads of the box list and table before the beads')
-    const uint32_t t = ctrl->step + s_off;
+    const uint64_t node = bx.node_off + r;
+    if (atomicExch(&claim[node], t + 1u) == t + 1u) return;   // another caller took this node
+    R d[19];
+    gather_pre<R, false>(A + bx.pop_off, upwind_of(r, bx.L, bx.inv_L), d);
+    const unsigned long long* q = imp + 3 * node;
+    const R fx = (R)((double)(long long)q[0] * IMP_INV_SCALE), fy = (R)((double)(long long)q[1] * IMP_INV_SCALE),
+            fz = (R)((double)(long long)q[2] * IMP_INV_SCALE);
+    R o[19];
+    const uint32_t h = collide<R>(d, o, fx, fy, fz, ccs[bi], r, t, bx.seed, bx.box_id);
+    R* b = B + bx.pop_off;
+#pragma unroll
+    for (int i = 0; i < 19; ++i) b[pop_at(i, r)] = o[i];
+    if (h) atomicOr(&ctrl->health, h);
+}
+
+// The node table of the step, one (bead, table node) item per thread: item
+// `item` of list entry `li`.  With Aprev (batched steps that defer tiles,
+// from the second step of a run of steps on) it also finishes the previous
+// step first: the impulses that landed outside that step's deferred tiles are
+// collided again (Aprev -> A, the previous step's number), their impulses
+// left in the field for the chain kernel to clear; this thread takes entries
+// fix_e0, fix_e0 + fix_n, ...  A table node whose population comes from such
+// a node takes the fixed value computed here instead of reading it, so no
+// thread reads what another writes.  With `stamp` the item also stamps its
+// node's collide tile as deferred in step t.
+template <typename R>
+__device__ __forceinline__ void near_work(const BoxDev* __restrict__ boxes, const int32_t* __restrict__ list,
+                                          R* A, const ChainArgs& ca, R* __restrict__ near_u,
+                                          int4* __restrict__ near_c, const R* __restrict__ field, Ctrl* ctrl,
+                                          uint32_t t, const CollideConst<R>* __restrict__ ccs,
+                                          const int32_t* __restrict__ bead_box, uint32_t* __restrict__ claim,
+                                          const R* __restrict__ Aprev, int one_box, const BoxDev& one, int li,
+                                          int item, uint32_t fix_e0, uint32_t fix_n, bool stamp)
+{
     uint32_t n_pend = 0;
     if (Aprev) {
         n_pend = min(ctrl->ovf_cnt, ca.ovf_cap);
-        const uint32_t nth = gridDim.x * gridDim.y * blockDim.x;
-        for (uint32_t e = (blockIdx.y * gridDim.x + blockIdx.x) * blockDim.x + threadIdx.x; e < n_pend; e += nth) {
+        for (uint32_t e = fix_e0; e < n_pend; e += fix_n) {
             const uint64_t g = ca.ovf[2 * (uint64_t)e];
             const uint32_t r = ca.ovf[2 * (uint64_t)e + 1];
             const int bi = bead_box[g];
             fixup_node<R>(boxes[bi], ccs, bi, r, ca.imp, claim, Aprev, A, ctrl, t - 1u, 1);
         }
     }
-    const int bi = one_box >= 0 ? one_box : list[blockIdx.y];
+    // one_box >= 0: the launch covers that box alone, its descriptor passed by
+    // value (no dependent loads of the box list and table before the beads')
+    const int bi = one_box >= 0 ? one_box : list[li];
     const BoxDev bx = one_box >= 0 ? one : boxes[bi];   // a copy: its fields stay in registers
     const int N = bx.N, L = bx.L;
-    const int tid = (int)(blockIdx.x * blockDim.x + threadIdx.x);
-    if (tid >= N * NEAR) return;
-    const int b = tid / NEAR, q = tid - b * NEAR;
+    if (item >= N * NEAR) return;
+    const int b = item / NEAR, q = item - b * NEAR;
     const uint64_t g = bx.bead_off + (uint64_t)b;
     const double Ld = (double)L, iL = bx.inv_L;
     const int n0 = nearest_of(ca.x[3 * g], L, Ld, iL), n1 = nearest_of(ca.x[3 * g + 1], L, Ld, iL),
@@ -697,13 +720,144 @@ __global__ __launch_bounds__(256) void k_near_nodes(const BoxDev* __restrict__ b
                 if (j == ik) d[j] = oo[j];
         }
     }
-    if (ca.defer)   // the bead's stencil stays on its table's nodes while it moves less
-                    // than half a cell from its nearest node: their tiles wait for the
-                    // impulses (a plain store: every writer stores the same stamp)
-        ca.defer[bx.tile_begin + node / 256u] = defer_stamp(t);
+    if (stamp && ca.defer)   // the bead's stencil stays on its table's nodes while it moves
+                             // less than half a cell from its nearest node: their tiles wait
+                             // for the impulses (a plain store: every writer stores the same stamp)
+        ca.defer[2u * (bx.tile_begin + node / 256u) + (t & 1u)] = defer_stamp(t);
     R u[3];
     node_velocity<R>(d, bx.rho0, 1.0 / bx.tau_lb, u);
     o[0] = u[0]; o[1] = u[1]; o[2] = u[2];
+}
+
+// The node-table kernel: grid (items of the largest chain / 256, list
+// entries).  zero_head: a run of steps starts here; its later collides count
+// their node-table workgroups from zero.
+template <typename R>
+__global__ __launch_bounds__(256) void k_near_nodes(const BoxDev* __restrict__ boxes,
+                                                    const int32_t* __restrict__ list, R* A,
+                                                    ChainArgs ca, R* __restrict__ near_u, int4* __restrict__ near_c,
+                                                    const R* __restrict__ field, Ctrl* __restrict__ ctrl,
+                                                    uint32_t s_off, const CollideConst<R>* __restrict__ ccs,
+                                                    const int32_t* __restrict__ bead_box,
+                                                    uint32_t* __restrict__ claim, const R* __restrict__ Aprev,
+                                                    int one_box, BoxDev one, int zero_head)
+{
+    const uint32_t t = ctrl->step + s_off;
+    if (zero_head && blockIdx.x == 0 && blockIdx.y == 0 && threadIdx.x < 2) {
+        ctrl->head_done[threadIdx.x] = 0u;
+        ctrl->head_fix[threadIdx.x] = 0u;
+    }
+    const uint32_t nth = gridDim.x * gridDim.y * blockDim.x;
+    const uint32_t e0 = (blockIdx.y * gridDim.x + blockIdx.x) * blockDim.x + threadIdx.x;
+    near_work<R>(boxes, list, A, ca, near_u, near_c, field, ctrl, t, ccs, bead_box, claim, Aprev, one_box, one,
+                 (int)blockIdx.y, (int)(blockIdx.x * blockDim.x + threadIdx.x), e0, nth, true);
+}
+
+// Step t's collide in a run of batched steps that carries its own node
+// tables: workgroups 0..n_head-1 do the node-table kernel's work (step t's
+// tables; the tiles were stamped by the previous step's chain kernel) and
+// count themselves done in head_done[t & 1]; the chain kernel, already
+// resident on another queue, waits for that count.  The other workgroups
+// collide one tile each, like k_collide.  When the previous step listed
+// impulses outside its deferred tiles, the node-table workgroups first fix
+// those nodes up and wait for each other (head_fix), so that the tables read
+// the fixed values; and every tile waits for the node-table workgroups, whose
+// fix-up rewrites populations that the tiles read, from inputs the tiles
+// overwrite.  The node-table workgroups come first in the grid, are
+// dispatched first and fit on the GPU at once (n_head <= CUs), so no
+// workgroup waits for one that is not running.  The table code here has no
+// in-register re-collision, so the kernel keeps the plain collide's
+// register count and occupancy.
+constexpr uint32_t SPIN_LIMIT = 1u << 19;   // polls of a bounded wait (~0.1 s)
+
+// thread 0 polls *cnt (relaxed, so a poll invalidates no cache) until it
+// reaches target, then acquires; the workgroup waits at the barrier
+__device__ __forceinline__ void wait_count(Ctrl* __restrict__ ctrl, uint32_t* cnt, uint32_t target)
+{
+    if (threadIdx.x == 0) {
+        uint32_t it = 0;
+        while (__hip_atomic_load(cnt, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < target) {
+            if (++it > SPIN_LIMIT) { atomicOr(&ctrl->health, H_SYNC); break; }
+            __builtin_amdgcn_s_sleep(8);
+        }
+        __atomic_thread_fence(__ATOMIC_ACQUIRE);
+    }
+    __syncthreads();
+}
+
+// every thread of the workgroup has written what it should: count the
+// workgroup in *cnt, visibly for the other agents' acquire
+__device__ __forceinline__ void count_done(uint32_t* cnt)
+{
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        __threadfence();
+        atomicAdd(cnt, 1u);
+    }
+}
+
+// one (bead, table node) item of a sparse box: the node's fluid velocity from
+// the current populations
+template <typename R>
+__device__ __forceinline__ void table_item(const BoxDev* __restrict__ boxes, const int32_t* __restrict__ list,
+                                           const R* A, const ChainArgs& ca, R* __restrict__ near_u,
+                                           int4* __restrict__ near_c, int one_box, const BoxDev& one, int li,
+                                           int item)
+{
+    const int bi = one_box >= 0 ? one_box : list[li];
+    const BoxDev bx = one_box >= 0 ? one : boxes[bi];
+    const int N = bx.N, L = bx.L;
+    if (item >= N * NEAR) return;
+    const int b = item / NEAR, q = item - b * NEAR;
+    const uint64_t g = bx.bead_off + (uint64_t)b;
+    const double Ld = (double)L, iL = bx.inv_L;
+    const int n0 = nearest_of(ca.x[3 * g], L, Ld, iL), n1 = nearest_of(ca.x[3 * g + 1], L, Ld, iL),
+              n2 = nearest_of(ca.x[3 * g + 2], L, Ld, iL);
+    if (q == 0) near_c[g] = make_int4(n0, n1, n2, 0);
+    const uint32_t node = node_of(n0 - 1 + q % 3, n1 - 1 + (q / 3) % 3, n2 - 1 + q / 9, L);
+    const uint32_t nz = node / ((uint32_t)L * (uint32_t)L), rem = node - nz * (uint32_t)L * (uint32_t)L;
+    const uint32_t ny = rem / (uint32_t)L, nx = rem - ny * (uint32_t)L;
+    R d[19];
+    gather_pre<R, false>(A + bx.pop_off, Upwind(nx, ny, nz, (uint32_t)L), d);
+    R u[3];
+    node_velocity<R>(d, bx.rho0, 1.0 / bx.tau_lb, u);
+    R* o = near_u + (g * NEAR + (uint64_t)q) * 3;
+    o[0] = u[0]; o[1] = u[1]; o[2] = u[2];
+}
+
+template <typename R, int W>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, W))) void k_collide_headed(
+    const BoxDev* __restrict__ boxes, const CollideConst<R>* __restrict__ ccs, const uint32_t* __restrict__ tile_box,
+    R* A, R* B, Ctrl* __restrict__ ctrl, uint32_t s_off, const uint32_t* __restrict__ defer, uint32_t n_head,
+    uint32_t head_x, const int32_t* __restrict__ list, ChainArgs ca, R* __restrict__ near_u,
+    int4* __restrict__ near_c, const int32_t* __restrict__ bead_box, uint32_t* __restrict__ claim,
+    const R* Aprev, int one_box, BoxDev one)   // Aprev and B are one buffer: the fix-up reads it, the tiles write it
+{
+    const uint32_t t = ctrl->step + s_off;
+    const bool pend = ctrl->ovf_flag[(t - 1u) & 1u] == defer_stamp(t - 1u);
+    if (blockIdx.x < n_head) {
+        const uint32_t li = blockIdx.x / head_x, bx_ = blockIdx.x - li * head_x;
+        if (pend) {
+            // the workgroups of list entry li fix the listed nodes of its box:
+            // the box and its constants stay uniform (scalar registers)
+            const int bi = __builtin_amdgcn_readfirstlane(one_box >= 0 ? one_box : list[li]);
+            const BoxDev& bx = boxes[bi];
+            const uint32_t n_pend = min(ctrl->ovf_cnt, ca.ovf_cap);
+            for (uint32_t e = bx_ * 256u + threadIdx.x; e < n_pend; e += head_x * 256u) {
+                const uint64_t g = ca.ovf[2 * (uint64_t)e];
+                const uint32_t r = ca.ovf[2 * (uint64_t)e + 1];
+                if (bead_box[g] == bi)
+                    fixup_node_claim_first<R>(bx, ccs, bi, r, ca.imp, claim, Aprev, A, ctrl, t - 1u);
+            }
+            count_done(&ctrl->head_fix[t & 1u]);
+            wait_count(ctrl, &ctrl->head_fix[t & 1u], n_head);
+        }
+        table_item<R>(boxes, list, A, ca, near_u, near_c, one_box, one, (int)li, (int)(bx_ * 256u + threadIdx.x));
+        count_done(&ctrl->head_done[t & 1u]);
+        return;
+    }
+    if (pend) wait_count(ctrl, &ctrl->head_done[t & 1u], n_head);
+    collide_tile<R>(boxes, ccs, tile_box, -1, blockIdx.x - n_head, A, B, ctrl, t, defer, threadIdx.x);
 }
 
 // one substep of one bead, as k_spread reads it
@@ -717,7 +871,7 @@ __global__ __launch_bounds__(WG_MAXB) void k_chain_wg(const BoxDev* __restrict__
                                                       const int4* __restrict__ near_c,
                                                       double* __restrict__ rec, Ctrl* __restrict__ ctrl,
                                                       uint32_t s_off, const int32_t* __restrict__ ca_bead_box,
-                                                      int clear_ovf)
+                                                      int clear_ovf, uint32_t wait_head, int stamp_next)
 {
     __shared__ double xs[3 * WG_MAXB];           // current positions
     __shared__ double x0s[3 * WG_MAXB];          // positions at the last list build
@@ -744,9 +898,18 @@ __global__ __launch_bounds__(WG_MAXB) void k_chain_wg(const BoxDev* __restrict__
     const double rl2 = rl * rl;
     const int nl_cap = ca.nl_cap < NL_SLOTS ? ca.nl_cap : NL_SLOTS;
 
+    if (wait_head) {
+        // the node tables come from the first workgroups of this step's
+        // collide, which starts once the previous collide is done
+        wait_count(ctrl, &ctrl->head_done[t & 1u], wait_head);
+        if (b == 0) {   // the previous step's readers of its counts are done
+            ctrl->head_done[(t + 1u) & 1u] = 0u;
+            ctrl->head_fix[(t + 1u) & 1u] = 0u;
+        }
+    }
     if (clear_ovf) {
         // the previous step's impulses outside its deferred tiles were fixed
-        // up by the node-table kernel, which left them in the field: clear
+        // up by the node-table work, which left them in the field: clear
         // them before this step's spread, then reset both list counts
         const uint32_t n_ovf = min(ctrl->ovf_cnt, ca.ovf_cap);
         for (uint32_t e = (uint32_t)b; e < n_ovf; e += WG_MAXB) {
@@ -1002,6 +1165,17 @@ __global__ __launch_bounds__(WG_MAXB) void k_chain_wg(const BoxDev* __restrict__
         for (int c = 0; c < 3; ++c) {
             ca.x[3 * g + c] = x[c]; ca.v[3 * g + c] = v[c]; ca.f[3 * g + c] = f[c];
         }
+        if (stamp_next && ca.defer) {
+            // the next step's deferred tiles: those of the table around the
+            // nearest node of the end position (what its node-table work uses)
+            const int m0 = nearest_of(x[0], L, Ld, iL), m1 = nearest_of(x[1], L, Ld, iL),
+                      m2 = nearest_of(x[2], L, Ld, iL);
+            const uint32_t sn = defer_stamp(t + 1u);
+            for (int q = 0; q < NEAR; ++q) {
+                const uint32_t node = node_of(m0 - 1 + q % 3, m1 - 1 + (q / 3) % 3, m2 - 1 + q / 9, L);
+                ca.defer[2u * (bx.tile_begin + node / 256u) + (sn & 1u)] = sn;
+            }
+        }
         if (ca.vhist) {
             double* hv = ca.vhist + ((uint64_t)(t % (uint32_t)ca.hist_len) * ca.total_beads + g) * 3;
             hv[0] = v[0]; hv[1] = v[1]; hv[2] = v[2];
@@ -1016,8 +1190,9 @@ __global__ __launch_bounds__(WG_MAXB) void k_chain_wg(const BoxDev* __restrict__
 __device__ __forceinline__ uint32_t list_overflow(const ChainArgs& ca, const BoxDev& bx, uint64_t g, uint32_t node,
                                                   Ctrl* __restrict__ ctrl, uint32_t stamp)
 {
-    if (!ca.defer || ca.defer[bx.tile_begin + node / 256u] == stamp) return 0u;
-    ca.ovm[bx.node_off + node] = stamp;   // read by the next step's node-table kernel
+    if (!ca.defer || ca.defer[2u * (bx.tile_begin + node / 256u) + (stamp & 1u)] == stamp) return 0u;
+    ca.ovm[bx.node_off + node] = stamp;   // read by the next step's node-table work
+    ctrl->ovf_flag[stamp & 1u] = stamp;   // the next step's collide waits for that work
     const uint32_t k = atomicAdd(&ctrl->ovf_cnt, 1u);
     if (k >= ca.ovf_cap) return H_TABLE;
     ca.ovf[2 * (uint64_t)k] = (uint32_t)g;
@@ -1313,7 +1488,8 @@ __global__ __launch_bounds__(256) void k_overflow(const BoxDev* __restrict__ box
                                                    const CollideConst<R>* __restrict__ ccs,
                                                    const int32_t* __restrict__ bead_box, ChainArgs ca,
                                                    uint32_t* __restrict__ claim, const R* __restrict__ A,
-                                                   R* __restrict__ B, Ctrl* __restrict__ ctrl, uint32_t s_off)
+                                                   R* __restrict__ B, Ctrl* __restrict__ ctrl, uint32_t s_off,
+                                                   uint32_t advance)
 {
     const uint32_t t = ctrl->step + s_off;
     const uint32_t n_ovf = min(ctrl->ovf_cnt, ca.ovf_cap);
@@ -1323,8 +1499,12 @@ __global__ __launch_bounds__(256) void k_overflow(const BoxDev* __restrict__ box
         const int bi = bead_box[g];
         fixup_node<R>(boxes[bi], ccs, bi, r, ca.imp, claim, A, B, ctrl, t, 0);
     }
-    __syncthreads();   // every thread has read the count
-    if (threadIdx.x == 0) { ctrl->defer_cnt = 0u; ctrl->ovf_cnt = 0u; }
+    __syncthreads();   // every thread has read the count and the step
+    if (threadIdx.x == 0) {
+        ctrl->defer_cnt = 0u;
+        ctrl->ovf_cnt = 0u;
+        ctrl->step += advance;   // the run's steps, when this kernel ends it (else 0)
+    }
 }
 
 // Collide and stream one 256-node tile after the coupling stage: each node's
@@ -1704,11 +1884,11 @@ hipError_t launch_collide_deferred(const LaunchCtx& c, const void* A, void* B, u
 }
 
 template <typename R>
-hipError_t launch_overflow(const LaunchCtx& c, const void* A, void* B, uint32_t s_off)
+hipError_t launch_overflow(const LaunchCtx& c, const void* A, void* B, uint32_t s_off, uint32_t advance)
 {
     if (!c.defer_on) return hipErrorInvalidValue;
     hipLaunchKernelGGL(k_overflow<R>, dim3(1), dim3(256), 0, c.stream, c.boxes, (const CollideConst<R>*)c.ccs,
-                       c.bead_box, chain_args(c), c.claim, (const R*)A, (R*)B, c.ctrl, s_off);
+                       c.bead_box, chain_args(c), c.claim, (const R*)A, (R*)B, c.ctrl, s_off, advance);
     return hipGetLastError();
 }
 
@@ -1736,27 +1916,30 @@ hipError_t launch_couple(const LaunchCtx& c, const void* A, const int32_t* list,
 
 template <typename R>
 hipError_t launch_couple_big(const LaunchCtx& c, const void* A, const int32_t* list, int n_list, int max_n,
-                             uint32_t s_off, hipEvent_t after_table, const void* Aprev, int single_box)
+                             uint32_t s_off, hipEvent_t after_table, const void* Aprev, int single_box,
+                             uint32_t wait_head, int zero_head, int stamp_next)
 {
     if (n_list == 0) return hipSuccess;
     if (c.nl_cap > NL_SLOTS || max_n > WG_MAXB || max_n <= 0) return hipErrorInvalidValue;
-    if (Aprev && (c.dense_max_tiles || !c.defer_on)) return hipErrorInvalidValue;
+    if ((Aprev || wait_head || stamp_next) && (c.dense_max_tiles || !c.defer_on)) return hipErrorInvalidValue;
+    if (wait_head && (Aprev || after_table)) return hipErrorInvalidValue;
     const ChainArgs ca = chain_args(c);
     if (c.dense_max_tiles)
         hipLaunchKernelGGL(k_node_field<R>, dim3(c.dense_max_tiles, n_list), dim3(256), 0, c.stream, c.boxes, list,
                            (const R*)A, (R*)c.field);
-    hipLaunchKernelGGL(k_near_nodes<R>, dim3((max_n * NEAR + 255) / 256, n_list), dim3(256), 0, c.stream, c.boxes,
-                       list, (R*)A, ca, (R*)c.near_u, c.near_c, (const R*)c.field, c.ctrl, s_off,
-                       (const CollideConst<R>*)c.ccs, c.bead_box, c.claim, (const R*)Aprev,
-                       n_list == 1 && single_box >= 0 ? single_box : -1,
-                       n_list == 1 && single_box >= 0 ? c.boxes_host[single_box] : BoxDev{});
+    if (!wait_head)
+        hipLaunchKernelGGL(k_near_nodes<R>, dim3((max_n * NEAR + 255) / 256, n_list), dim3(256), 0, c.stream,
+                           c.boxes, list, (R*)A, ca, (R*)c.near_u, c.near_c, (const R*)c.field, c.ctrl, s_off,
+                           (const CollideConst<R>*)c.ccs, c.bead_box, c.claim, (const R*)Aprev,
+                           n_list == 1 && single_box >= 0 ? single_box : -1,
+                           n_list == 1 && single_box >= 0 ? c.boxes_host[single_box] : BoxDev{}, zero_head);
     if (after_table) {
         const hipError_t e = hipEventRecord(after_table, c.stream);
         if (e != hipSuccess) return e;
     }
     hipLaunchKernelGGL(k_chain_wg<R>, dim3(n_list), dim3(WG_MAXB), 0, c.stream, c.boxes, list, (const R*)A, ca,
                        (const R*)c.near_u, (const int4*)c.near_c, c.sub_rec, c.ctrl, s_off, c.bead_box,
-                       Aprev ? 1 : 0);
+                       (Aprev || wait_head) ? 1 : 0, wait_head, stamp_next);
     if (c.big_sparse)
         hipLaunchKernelGGL(k_spread, dim3((max_n * 8 + 255) / 256, n_list), dim3(256), 0, c.stream, c.boxes, list,
                            ca, (const double*)c.sub_rec, c.ctrl, s_off);
@@ -1771,6 +1954,35 @@ hipError_t launch_couple_big(const LaunchCtx& c, const void* A, const int32_t* l
         hipLaunchKernelGGL(k_gather_imp, dim3(c.dense_max_tiles, n_list), dim3(256), 0, c.stream, c.boxes, list, ca,
                            (const uint32_t*)c.bin_start, (const unsigned long long*)c.runimp);
     }
+    return hipGetLastError();
+}
+
+template <typename R, int W>
+static void launch_collide_headed_w(const LaunchCtx& c, const void* A, void* B, uint32_t n_tiles, uint32_t s_off,
+                                    const int32_t* list, int n_list, int max_n, const void* Aprev, int single_box)
+{
+    const uint32_t head_x = (uint32_t)((max_n * NEAR + 255) / 256);
+    const uint32_t n_head = head_blocks(n_list, max_n);
+    hipLaunchKernelGGL((k_collide_headed<R, W>), dim3(n_head + n_tiles), dim3(256), 0, c.stream, c.boxes,
+                       (const CollideConst<R>*)c.ccs, c.tile_box, (R*)A, (R*)B, c.ctrl, s_off,
+                       (const uint32_t*)c.defer, n_head, head_x, list, chain_args(c), (R*)c.near_u, c.near_c,
+                       c.bead_box, c.claim, (const R*)Aprev, n_list == 1 && single_box >= 0 ? single_box : -1,
+                       n_list == 1 && single_box >= 0 ? c.boxes_host[single_box] : BoxDev{});
+}
+
+template <typename R>
+hipError_t launch_collide_headed(const LaunchCtx& c, const void* A, void* B, uint32_t n_tiles, uint32_t s_off,
+                                 const int32_t* list, int n_list, int max_n, const void* Aprev, int single_box)
+{
+    static_assert(NEAR == NEAR_ITEMS, "one table size");
+    if (n_list == 0 || n_tiles == 0 || !Aprev || !c.defer_on || c.dense_max_tiles) return hipErrorInvalidValue;
+    if (max_n > WG_MAXB || max_n <= 0) return hipErrorInvalidValue;
+    // the node-table code caps the occupancy at 5 waves per SIMD, so the
+    // launch shape keeps only the autotuned cap of 4
+    if (c.collide_variant == 0)
+        launch_collide_headed_w<R, 4>(c, A, B, n_tiles, s_off, list, n_list, max_n, Aprev, single_box);
+    else
+        launch_collide_headed_w<R, 5>(c, A, B, n_tiles, s_off, list, n_list, max_n, Aprev, single_box);
     return hipGetLastError();
 }
 
@@ -2240,8 +2452,8 @@ template hipError_t launch_fixup<float>(const LaunchCtx&, const void*, void*, ui
 template hipError_t launch_fixup<double>(const LaunchCtx&, const void*, void*, uint64_t, uint64_t, uint32_t);
 template hipError_t launch_collide_deferred<float>(const LaunchCtx&, const void*, void*, uint32_t);
 template hipError_t launch_collide_deferred<double>(const LaunchCtx&, const void*, void*, uint32_t);
-template hipError_t launch_overflow<float>(const LaunchCtx&, const void*, void*, uint32_t);
-template hipError_t launch_overflow<double>(const LaunchCtx&, const void*, void*, uint32_t);
+template hipError_t launch_overflow<float>(const LaunchCtx&, const void*, void*, uint32_t, uint32_t);
+template hipError_t launch_overflow<double>(const LaunchCtx&, const void*, void*, uint32_t, uint32_t);
 template hipError_t launch_collide_forced<float>(const LaunchCtx&, const void*, void*, int, uint32_t, uint32_t,
                                                  uint32_t);
 template hipError_t launch_collide_forced<double>(const LaunchCtx&, const void*, void*, int, uint32_t, uint32_t,
@@ -2249,9 +2461,13 @@ template hipError_t launch_collide_forced<double>(const LaunchCtx&, const void*,
 template hipError_t launch_couple<float>(const LaunchCtx&, const void*, const int32_t*, int, int, uint32_t);
 template hipError_t launch_couple<double>(const LaunchCtx&, const void*, const int32_t*, int, int, uint32_t);
 template hipError_t launch_couple_big<float>(const LaunchCtx&, const void*, const int32_t*, int, int, uint32_t,
-                                            hipEvent_t, const void*, int);
+                                            hipEvent_t, const void*, int, uint32_t, int, int);
 template hipError_t launch_couple_big<double>(const LaunchCtx&, const void*, const int32_t*, int, int, uint32_t,
-                                             hipEvent_t, const void*, int);
+                                             hipEvent_t, const void*, int, uint32_t, int, int);
+template hipError_t launch_collide_headed<float>(const LaunchCtx&, const void*, void*, uint32_t, uint32_t,
+                                                 const int32_t*, int, int, const void*, int);
+template hipError_t launch_collide_headed<double>(const LaunchCtx&, const void*, void*, uint32_t, uint32_t,
+                                                  const int32_t*, int, int, const void*, int);
 template hipError_t launch_stats<float>(const LaunchCtx&, const void*, uint32_t, double*, double*, double*);
 template hipError_t launch_stats<double>(const LaunchCtx&, const void*, uint32_t, double*, double*, double*);
 

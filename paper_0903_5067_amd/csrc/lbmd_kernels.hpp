@@ -69,8 +69,9 @@ hipError_t launch_fixup(const LaunchCtx& c, const void* A, void* B, uint64_t bea
 // them, then the deferral cleared
 template <typename R>
 hipError_t launch_collide_deferred(const LaunchCtx& c, const void* A, void* B, uint32_t s_off);
+// advance: added to the device step counter once the fix-up is done (0: none)
 template <typename R>
-hipError_t launch_overflow(const LaunchCtx& c, const void* A, void* B, uint32_t s_off);
+hipError_t launch_overflow(const LaunchCtx& c, const void* A, void* B, uint32_t s_off, uint32_t advance = 0);
 template <typename R>
 hipError_t launch_collide_forced(const LaunchCtx& c, const void* A, void* B, int fixed_box, uint32_t tile0,
                                  uint32_t n_tiles, uint32_t s_off);
@@ -87,11 +88,28 @@ hipError_t launch_couple(const LaunchCtx& c, const void* A, const int32_t* list,
 // end-of-step kernel of launch_overflow).
 // single_box: the box `list` holds when n_list == 1 (its descriptor is then
 // passed to the node-table kernel by value), or -1.
+// wait_head > 0: no node-table kernel; the step's collide carries the node
+// tables (launch_collide_headed) and the chain kernel waits for its wait_head
+// node-table workgroups, then clears the previous step's impulses outside its
+// deferred tiles.  zero_head: the node-table kernel starts a run of such
+// steps (zeroes the workgroup counts).  stamp_next: the chain kernel stamps
+// the next step's deferred tiles from its end positions.
 template <typename R>
 hipError_t launch_couple_big(const LaunchCtx& c, const void* A, const int32_t* list, int n_list, int max_n,
                              uint32_t s_off, hipEvent_t after_table, const void* Aprev = nullptr,
-                             int single_box = -1);
+                             int single_box = -1, uint32_t wait_head = 0, int zero_head = 0, int stamp_next = 0);
+// step s_off's plain collide over tiles 0..n_tiles-1 with the node-table work
+// of the big chains in `list` in its first workgroups (their count is
+// head_blocks(n_list, max_n)); Aprev: the previous step's input buffer
+template <typename R>
+hipError_t launch_collide_headed(const LaunchCtx& c, const void* A, void* B, uint32_t n_tiles, uint32_t s_off,
+                                 const int32_t* list, int n_list, int max_n, const void* Aprev, int single_box);
 constexpr int BIG_CHAIN = 256;   // chains above this many beads take the one-workgroup-per-chain kernel
+constexpr int NEAR_ITEMS = 27;   // table nodes per bead
+inline uint32_t head_blocks(int n_list, int max_n)
+{
+    return (uint32_t)n_list * (uint32_t)((max_n * NEAR_ITEMS + 255) / 256);
+}
 hipError_t launch_advance(const LaunchCtx& c, uint32_t n);
 hipError_t launch_init_forces(const LaunchCtx& c, const int32_t* list, int n_list, int block);
 // observables of the state A: per-block records in part [sum of stat_recs_of(n_tiles)][NSTAT_REC]

@@ -9,6 +9,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <cstddef>
 #include <cmath>
 #include <cstdlib>
 #include <cstring>
@@ -237,12 +238,13 @@ Layout make_layout(const lb_box_desc* b, int32_t n, int32_t prec, int32_t hist)
         Lo.sc_binstart = o; o = align256(o + std::max<uint64_t>(Lo.bin_entries, 1) * sizeof(uint32_t));
         Lo.sc_items = o; o = align256(o + std::max<uint64_t>(Lo.item_entries, 1) * 24 * sizeof(unsigned long long));
         Lo.sc_slotof = o; o = align256(o + std::max<uint64_t>(Lo.item_entries, 1) * sizeof(uint32_t));
-        // deferred tiles: two step stamps per collide tile; a tile is listed
+        // deferred tiles: three step stamps per collide tile (deferred in the
+        // steps of either parity, listed in); a tile is listed
         // once, and a bead's table spans at most 27 tiles.  A bead hands
         // impulses to at most 8 new nodes per substep.
         Lo.defer_cap = (uint32_t)(27 * Lo.beads_big_sparse);
         Lo.ovf_cap = (uint32_t)(8 * (uint64_t)std::max(Lo.big_max_sub, 1) * Lo.beads_big_sparse);
-        Lo.sc_defer = o; o = align256(o + (Lo.beads_big_sparse ? tiles : 1) * sizeof(uint32_t));
+        Lo.sc_defer = o; o = align256(o + (Lo.beads_big_sparse ? 2 * tiles : 1) * sizeof(uint32_t));
         Lo.sc_dclaim = o; o = align256(o + (Lo.beads_big_sparse ? tiles : 1) * sizeof(uint32_t));
         Lo.sc_dlist = o; o = align256(o + std::max<uint32_t>(Lo.defer_cap, 1) * sizeof(uint32_t));
         Lo.sc_ovf = o; o = align256(o + std::max<uint32_t>(Lo.ovf_cap, 1) * 2 * sizeof(uint32_t));
@@ -327,18 +329,25 @@ lb_status fail(lb_handle* h, lb_status s, const std::string& msg)
             return fail(h, LB_EDEVICE, std::string(#call) + ": " + hipGetErrorString(e_));     \
     } while (0)
 
-// zero every per-node and per-tile step stamp (after the step count is set
-// back); synchronous, outside any graph
+// zero every per-node and per-tile step stamp and the step-tagged control
+// words (after the step count is set back), on the handle's stream, then
+// wait for it; outside any graph
 hipError_t clear_step_stamps(lb_handle* h)
 {
     const Layout& lo = h->lo;
     if (!lo.total_beads) return hipSuccess;
-    hipError_t e = hipMemset(h->scratch + lo.sc_claim, 0, lo.total_nodes * sizeof(uint32_t));
+    char* ctrl = h->scratch + lo.sc_ctrl;
+    hipError_t e = hipMemsetAsync(h->scratch + lo.sc_claim, 0, lo.total_nodes * sizeof(uint32_t), h->stream);
+    if (e == hipSuccess)
+        e = hipMemsetAsync(ctrl + offsetof(Ctrl, ovf_flag), 0, sizeof(Ctrl) - offsetof(Ctrl, ovf_flag), h->stream);
     if (e == hipSuccess && lo.beads_big_sparse) {
-        e = hipMemset(h->scratch + lo.sc_defer, 0, lo.total_tiles * sizeof(uint32_t));
-        if (e == hipSuccess) e = hipMemset(h->scratch + lo.sc_dclaim, 0, lo.total_tiles * sizeof(uint32_t));
-        if (e == hipSuccess) e = hipMemset(h->scratch + lo.sc_ovm, 0, lo.total_nodes * sizeof(uint32_t));
+        e = hipMemsetAsync(h->scratch + lo.sc_defer, 0, 2 * lo.total_tiles * sizeof(uint32_t), h->stream);
+        if (e == hipSuccess)
+            e = hipMemsetAsync(h->scratch + lo.sc_dclaim, 0, lo.total_tiles * sizeof(uint32_t), h->stream);
+        if (e == hipSuccess)
+            e = hipMemsetAsync(h->scratch + lo.sc_ovm, 0, lo.total_nodes * sizeof(uint32_t), h->stream);
     }
+    if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
     return e;
 }
 
@@ -504,16 +513,106 @@ lb_status enqueue_headed_run(lb_handle* h, int from, uint32_t n)
     return LB_OK;
 }
 
-// n coupled steps from buffer `from`, step offsets 0..n-1 (the device step
-// counter is advanced by the caller)
+// FP32 runs whose chains are all large (every box with beads holds a chain
+// above BIG_CHAIN beads, none of them dense) take the collide that carries
+// its own node tables from the second step on.  (In FP64 the node-table code
+// would hold the collide to two waves per SIMD.)  Such runs rely on the two
+// streams running on two hardware queues, so that the chain kernel of a step
+// is resident before that step's collide: they are launched directly, never
+// from a HIP graph, whose replay does not keep that order (the chain kernel's
+// bounded wait then gives up).  A stream under capture takes the layout of
+// enqueue_headed_run instead.
+bool fused_steps(const lb_handle* h)
+{
+    // the collide's node-table workgroups wait for each other, so they must
+    // fit on the GPU at once: at most one per CU
+    return headed_steps(h) && h->couple_host.empty() && h->prec == LB_FP32_DEV &&
+           head_blocks((int)h->lo.big_list.size(), h->lo.big_max_n) <= (uint32_t)h->ctx.n_cu;
+}
+
+bool capturing(hipStream_t s)
+{
+    hipStreamCaptureStatus st = hipStreamCaptureStatusNone;
+    return hipStreamIsCapturing(s, &st) == hipSuccess && st != hipStreamCaptureStatusNone;
+}
+
+// A run of n batched steps from buffer `from` in which every collide after
+// the first carries the step's node tables.  The handle's stream holds the
+// plain collides, the second stream the chain work, one step after another.
+// Step 0 is laid out as in enqueue_step (node-table kernel, then the chain
+// kernel and, once the table is there, the collide).  From step 1 on, step
+// k's collide follows step k-1's collide and deferred tiles; its first
+// workgroups fix up step k-1's impulses outside its deferred tiles and build
+// step k's node tables.  Step k's chain kernel is queued behind step k-1's
+// chain work, long before the previous collide ends: it gets a CU as that
+// collide drains, before step k's collide starts, and waits there for the
+// node-table workgroups.  Each chain kernel stamps the next step's deferred
+// tiles from its end positions.  So a step is one collide and one kernel
+// boundary.  Every node gets the same collide call with the same impulse as
+// in enqueue_step, so the bits are the same.
+lb_status enqueue_fused_run(lb_handle* h, int from, uint32_t n, uint32_t advance)
+{
+    const Layout& lo = h->lo;
+    const bool f64 = h->prec == LB_FP64;
+    LaunchCtx ca = h->ctx, cb = h->ctx2;
+    ca.defer_on = cb.defer_on = 1;
+    const int nbig = (int)lo.big_list.size();
+    const uint32_t ts = (uint32_t)lo.tiles_sparse;
+    const int one = nbig == 1 ? lo.big_list[0] : -1;
+    const uint32_t n_head = head_blocks(nbig, lo.big_max_n);
+    HIPCHK(h, hipEventRecord(h->ev_fork, h->stream));
+    HIPCHK(h, hipStreamWaitEvent(h->stream2, h->ev_fork, 0));
+    for (uint32_t k = 0; k < n; ++k) {
+        const int p = from ^ (int)(k & 1);
+        const void* A = h->pop(p);
+        void* B = h->pop(1 - p);
+        if (k == 0) {
+            HIPCHK(h, f64 ? launch_couple_big<double>(cb, A, h->big_list, nbig, lo.big_max_n, 0, h->ev_head, nullptr,
+                                                      one, 0, 1, 1)
+                          : launch_couple_big<float>(cb, A, h->big_list, nbig, lo.big_max_n, 0, h->ev_head, nullptr,
+                                                     one, 0, 1, 1));
+            HIPCHK(h, hipStreamWaitEvent(h->stream, h->ev_head, 0));
+            HIPCHK(h, f64 ? launch_collide<double>(ca, A, B, -1, 0, ts, 0) : launch_collide<float>(ca, A, B, -1, 0, ts, 0));
+        } else {
+            // step k-1 read pop(1 - p); its deferred tiles are collided
+            HIPCHK(h, hipStreamWaitEvent(h->stream, h->ev_def, 0));
+            const void* prevA = h->pop(1 - p);
+            HIPCHK(h, f64 ? launch_collide_headed<double>(ca, A, B, ts, k, h->big_list, nbig, lo.big_max_n, prevA, one)
+                          : launch_collide_headed<float>(ca, A, B, ts, k, h->big_list, nbig, lo.big_max_n, prevA, one));
+            HIPCHK(h, f64 ? launch_couple_big<double>(cb, A, h->big_list, nbig, lo.big_max_n, k, nullptr, nullptr, one,
+                                                      n_head, 0, 1)
+                          : launch_couple_big<float>(cb, A, h->big_list, nbig, lo.big_max_n, k, nullptr, nullptr, one,
+                                                     n_head, 0, 1));
+        }
+        HIPCHK(h, f64 ? launch_collide_deferred<double>(cb, A, B, k) : launch_collide_deferred<float>(cb, A, B, k));
+        HIPCHK(h, hipEventRecord(h->ev_def, h->stream2));
+    }
+    // the last step's impulses outside its deferred tiles, then the counts
+    // reset and the step counter advanced; the second stream has joined
+    // through ev_def
+    const int pl = from ^ (int)((n - 1) & 1);
+    HIPCHK(h, hipStreamWaitEvent(h->stream, h->ev_def, 0));
+    HIPCHK(h, f64 ? launch_overflow<double>(ca, h->pop(pl), h->pop(1 - pl), n - 1, advance)
+                  : launch_overflow<float>(ca, h->pop(pl), h->pop(1 - pl), n - 1, advance));
+    return LB_OK;
+}
+
+// n coupled steps from buffer `from`, step offsets 0..n-1, then the device
+// step counter advanced by n
 lb_status enqueue_steps(lb_handle* h, int from, uint32_t n)
 {
     if (n == 0) return LB_OK;
-    if (headed_steps(h)) return enqueue_headed_run(h, from, n);
-    for (uint32_t k = 0; k < n; ++k) {
-        const lb_status s = enqueue_step(h, from ^ (int)(k & 1), k, true);
+    if (fused_steps(h) && !capturing(h->stream)) return enqueue_fused_run(h, from, n, n);
+    if (headed_steps(h)) {
+        const lb_status s = enqueue_headed_run(h, from, n);
         if (s != LB_OK) return s;
+    } else {
+        for (uint32_t k = 0; k < n; ++k) {
+            const lb_status s = enqueue_step(h, from ^ (int)(k & 1), k, true);
+            if (s != LB_OK) return s;
+        }
     }
+    HIPCHK(h, launch_advance(h->ctx, n));
     return LB_OK;
 }
 
@@ -532,7 +631,6 @@ lb_status build_graph(lb_handle* h, int parity)
     HIPCHK(h, hipStreamBeginCapture(h->stream, hipStreamCaptureModeThreadLocal));
     lb_status st = LB_OK;
     st = enqueue_steps(h, parity, (uint32_t)h->graph_steps);
-    if (st == LB_OK && launch_advance(h->ctx, (uint32_t)h->graph_steps) != hipSuccess) st = LB_EDEVICE;
     hipGraph_t g = nullptr;
     hipError_t e = hipStreamEndCapture(h->stream, &g);
     if (st != LB_OK) { if (g) (void)hipGraphDestroy(g); return st; }
@@ -548,7 +646,7 @@ lb_status build_graph(lb_handle* h, int parity)
 lb_status prepare_graphs(lb_handle* h)
 {
     drop_graphs(h);
-    if (h->graph_steps <= 0) return LB_OK;
+    if (h->graph_steps <= 0 || fused_steps(h)) return LB_OK;
     for (int p = 0; p < 2; ++p) {
         lb_status s = build_graph(h, p);
         if (s != LB_OK) return s;
@@ -810,7 +908,7 @@ lb_status lb_step(lb_handle* h, int64_t n_steps)
         h->pending = false;
         left -= 1;
     }
-    if (h->graph_steps > 0) {
+    if (h->graph_steps > 0 && !fused_steps(h)) {
         while (left >= h->graph_steps) {
             if (!h->gexec[h->cur]) {
                 lb_status s = build_graph(h, h->cur);
@@ -824,7 +922,6 @@ lb_status lb_step(lb_handle* h, int64_t n_steps)
     if (left > 0) {
         lb_status s = enqueue_steps(h, h->cur, (uint32_t)left);
         if (s != LB_OK) return s;
-        HIPCHK(h, launch_advance(h->ctx, (uint32_t)left));
         if (left & 1) h->cur ^= 1;
         h->step += left;
     }

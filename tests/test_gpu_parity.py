@@ -400,18 +400,24 @@ def test_deferred_tiles_equal_fixup_after_collide_bitwise(prec, graph_steps):
 
 
 @pytest.mark.parametrize("prec,graph_steps", [(FP64, 0), (FP32, 0), (FP64, 4), (FP32, 6)])
-def test_two_queue_runs_equal_fixup_after_collide_bitwise(prec, graph_steps):
-    """With no dense box, a run of batched steps alternates its two queues:
-    each step's node-table kernel also re-collides the previous step's
-    impulses outside its deferred tiles.  Twelve steps in one call (one run,
-    or graph replays of several steps) give the bits of twelve steps with
-    the chain's nodes re-collided after each collide; the hot box's beads
-    leave their node tables within the twelve steps."""
-    say("two-queue runs vs fix-up", prec, graph_steps)
+@pytest.mark.parametrize("small", [True, False])
+def test_two_queue_runs_equal_fixup_after_collide_bitwise(prec, graph_steps, small):
+    """With no dense box, a run of batched steps puts the chain work of step k
+    right behind the collide of step k-1, where the previous step's impulses
+    outside its deferred tiles are re-collided too.  With a small chain in
+    the batch the two queues alternate and a node-table kernel heads each
+    step; with large chains only (FP32) every collide after the first carries
+    the node tables in its first workgroups, and the chain kernel waits for
+    them.  Twelve steps in one call (one run, or graph replays of several
+    steps) give the bits of twelve steps with the chains' nodes re-collided
+    after each collide; the hot box's beads leave their node tables within
+    the twelve steps."""
+    say("two-queue runs vs fix-up", prec, graph_steps, "small chain" if small else "large chains only")
     hot = dict(kT=1.0, therm=0, md_dt=0.01, md_substeps=25, tau_lb=0.25, zeta=1.0, k_fene=7.0, r0_fene=2.0)
     boxes = [params(L=40, N=300, kT=1e-2, seed=7, box_id=0),
-             params(L=40, N=300, seed=7, box_id=1, **hot),
-             params(L=12, N=16, kT=1e-2, seed=7, box_id=2)]
+             params(L=40, N=300, seed=7, box_id=1, **hot)]
+    if small:
+        boxes.append(params(L=12, N=16, kT=1e-2, seed=7, box_id=2))
     xs = [chain(b) for b in boxes]
     ref = gpu_system(boxes, prec, xs=xs)
     ref.set_launch(batched=True, graph_steps=0, overlap=False)
