@@ -64,7 +64,13 @@ struct Ctrl {
     uint32_t head_fix[2];   // [t & 1]: those that have done their part of step t-1's overflow fix-up
 };
 
-// Tag of step t in the per-tile deferral stamps: never 0 (the cleared value),
+// Deferral is decided per segment of DSEG consecutive nodes of a box (one
+// wavefront of a 256-node collide tile): each segment has one stamp per step
+// parity, at defer[2 * segment + (t & 1)].
+constexpr uint32_t DSEG = 64;
+constexpr uint32_t DSEG_PER_TILE = 256 / DSEG;
+
+// Tag of step t in the per-segment deferral stamps: never 0 (the cleared value),
 // so a tile is deferred in step t exactly when its stamp equals this.  Stamps
 // repeat every 2^31 steps; restoring an earlier step count clears them.
 __device__ __forceinline__ uint32_t defer_stamp(uint32_t t) { return t | 0x80000000u; }

@@ -84,6 +84,13 @@ __device__ __forceinline__ Upwind upwind_of(uint32_t r, int L, double inv_L)
     return Upwind(x, y, z, (uint32_t)L);
 }
 
+// deferral segment of node `node` of box bx (its stamps sit at 2 * segment
+// and 2 * segment + 1)
+__device__ __forceinline__ uint32_t dseg_of(const BoxDev& bx, uint32_t node)
+{
+    return DSEG_PER_TILE * bx.tile_begin + node / DSEG;
+}
+
 // -------------------------------------------------------------- collide
 // One tile of 256 nodes: gather the pre-collision populations (pull), collide
 // with no impulse, write post-collision values aligned and non-temporal.
@@ -95,9 +102,11 @@ __device__ __forceinline__ void collide_tile(const BoxDev* __restrict__ boxes, c
 {
     int bi;
     if (defer) {   // batched steps (every tile's box from tile_box)
-        // a deferred tile is collided after the coupling, with its impulses
-        // (k_collide_deferred); the stamp load goes out beside the box load
-        const uint32_t st = defer[2u * tile + (t & 1u)];
+        // a deferred segment (this wavefront's nodes) is collided after the
+        // coupling, with its impulses (k_collide_deferred); the stamp load
+        // goes out beside the box load
+        const uint32_t w = __builtin_amdgcn_readfirstlane(lane / DSEG);   // wavefront-uniform: a scalar load
+        const uint32_t st = defer[2u * (DSEG_PER_TILE * tile + w) + (t & 1u)];
         bi = (int)tile_box[tile];
         if (st == defer_stamp(t)) return;
     } else {
@@ -723,7 +732,7 @@ __device__ __forceinline__ void near_work(const BoxDev* __restrict__ boxes, cons
     if (stamp && ca.defer)   // the bead's stencil stays on its table's nodes while it moves
                              // less than half a cell from its nearest node: their tiles wait
                              // for the impulses (a plain store: every writer stores the same stamp)
-        ca.defer[2u * (bx.tile_begin + node / 256u) + (t & 1u)] = defer_stamp(t);
+        ca.defer[2u * dseg_of(bx, node) + (t & 1u)] = defer_stamp(t);
     R u[3];
     node_velocity<R>(d, bx.rho0, 1.0 / bx.tau_lb, u);
     o[0] = u[0]; o[1] = u[1]; o[2] = u[2];
@@ -1173,7 +1182,7 @@ __global__ __launch_bounds__(WG_MAXB) void k_chain_wg(const BoxDev* __restrict__
             const uint32_t sn = defer_stamp(t + 1u);
             for (int q = 0; q < NEAR; ++q) {
                 const uint32_t node = node_of(m0 - 1 + q % 3, m1 - 1 + (q / 3) % 3, m2 - 1 + q / 9, L);
-                ca.defer[2u * (bx.tile_begin + node / 256u) + (sn & 1u)] = sn;
+                ca.defer[2u * dseg_of(bx, node) + (sn & 1u)] = sn;
             }
         }
         if (ca.vhist) {
@@ -1190,7 +1199,7 @@ __global__ __launch_bounds__(WG_MAXB) void k_chain_wg(const BoxDev* __restrict__
 __device__ __forceinline__ uint32_t list_overflow(const ChainArgs& ca, const BoxDev& bx, uint64_t g, uint32_t node,
                                                   Ctrl* __restrict__ ctrl, uint32_t stamp)
 {
-    if (!ca.defer || ca.defer[2u * (bx.tile_begin + node / 256u) + (stamp & 1u)] == stamp) return 0u;
+    if (!ca.defer || ca.defer[2u * dseg_of(bx, node) + (stamp & 1u)] == stamp) return 0u;
     ca.ovm[bx.node_off + node] = stamp;   // read by the next step's node-table work
     ctrl->ovf_flag[stamp & 1u] = stamp;   // the next step's collide waits for that work
     const uint32_t k = atomicAdd(&ctrl->ovf_cnt, 1u);
@@ -1516,13 +1525,13 @@ __device__ __forceinline__ void collide_forced_tile(const BoxDev* __restrict__ b
                                                     const uint32_t* __restrict__ tile_box, int fixed_box,
                                                     uint32_t tile, unsigned long long* __restrict__ imp,
                                                     const R* __restrict__ A, R* __restrict__ B,
-                                                    Ctrl* __restrict__ ctrl, uint32_t t)
+                                                    Ctrl* __restrict__ ctrl, uint32_t t, uint32_t lane)
 {
     const int bi = fixed_box >= 0 ? fixed_box : (int)tile_box[tile];
     const BoxDev& bx = boxes[bi];
     const int L = bx.L;
     const uint32_t V = (uint32_t)L * L * L;
-    const uint32_t r = (tile - bx.tile_begin) * 256u + threadIdx.x;
+    const uint32_t r = (tile - bx.tile_begin) * 256u + lane;
     if (r >= V) return;
     const CollideConst<R> cc = ccs[bi];
     const Upwind up = upwind_of(r, L, bx.inv_L);
@@ -1551,7 +1560,7 @@ __global__ __launch_bounds__(256) void k_collide_forced(const BoxDev* __restrict
                                                         Ctrl* __restrict__ ctrl, uint32_t s_off)
 {
     collide_forced_tile<R>(boxes, ccs, tile_box, fixed_box, tile0 + blockIdx.x, imp, A, B, ctrl,
-                           ctrl->step + s_off);
+                           ctrl->step + s_off, threadIdx.x);
 }
 
 // The deferred tiles of a step as a list, built after the coupling on the
@@ -1567,13 +1576,13 @@ __global__ __launch_bounds__(256) void k_defer_list(const BoxDev* __restrict__ b
     const int tid = (int)(blockIdx.x * blockDim.x + threadIdx.x);
     const uint32_t stamp = defer_stamp(ctrl->step + s_off);
     bool win = false;
-    uint32_t tile = 0;
+    uint32_t seg = 0;
     if (tid < bx.N * NEAR) {
         const int b = tid / NEAR, q = tid - b * NEAR;
         const int4 nc = near_c[bx.bead_off + (uint64_t)b];
         const uint32_t node = node_of(nc.x - 1 + q % 3, nc.y - 1 + (q / 3) % 3, nc.z - 1 + q / 9, bx.L);
-        tile = bx.tile_begin + node / 256u;
-        win = ca.dclaim[tile] != stamp && atomicExch(&ca.dclaim[tile], stamp) != stamp;
+        seg = dseg_of(bx, node);
+        win = ca.dclaim[seg] != stamp && atomicExch(&ca.dclaim[seg], stamp) != stamp;
     }
     const unsigned long long m = __ballot(win);
     if (m == 0ull) return;
@@ -1584,7 +1593,7 @@ __global__ __launch_bounds__(256) void k_defer_list(const BoxDev* __restrict__ b
     base = __shfl(base, lead);
     if (win) {
         const uint32_t k = base + (uint32_t)__popcll(m & ((1ull << lane) - 1ull));
-        if (k < ca.defer_cap) ca.defer_list[k] = tile;
+        if (k < ca.defer_cap) ca.defer_list[k] = seg;
         else atomicOr(&ctrl->health, H_TABLE);
     }
 }
@@ -1601,10 +1610,15 @@ __global__ __launch_bounds__(256) void k_collide_deferred(const BoxDev* __restri
                                                           const R* __restrict__ A, R* __restrict__ B,
                                                           Ctrl* __restrict__ ctrl, uint32_t s_off)
 {
+    // one wavefront per listed segment
     const uint32_t t = ctrl->step + s_off;
     const uint32_t n = min(ctrl->defer_cnt, cap);
-    for (uint32_t k = blockIdx.x; k < n; k += gridDim.x)
-        collide_forced_tile<R>(boxes, ccs, tile_box, -1, defer_list[k], imp, A, B, ctrl, t);
+    const uint32_t w = threadIdx.x / DSEG, lane = threadIdx.x % DSEG;
+    for (uint32_t k = blockIdx.x * DSEG_PER_TILE + w; k < n; k += gridDim.x * DSEG_PER_TILE) {
+        const uint32_t seg = defer_list[k];
+        collide_forced_tile<R>(boxes, ccs, tile_box, -1, seg / DSEG_PER_TILE, imp, A, B, ctrl, t,
+                               (seg % DSEG_PER_TILE) * DSEG + lane);
+    }
 }
 
 // --------------------------------------------------------------- advance
@@ -1682,7 +1696,32 @@ __device__ __forceinline__ double block_sum256(double acc[NV], double (*lds)[NV]
 // grid (records of the largest box, boxes): block (c, box) sums tiles
 // c*STAT_TPB .. c*STAT_TPB + STAT_TPB - 1 of the box, one node per thread and
 // tile, into record stat_off + c
+__device__ __forceinline__ float uniform_value(float v)
+{
+    return __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(v)));
+}
+__device__ __forceinline__ double uniform_value(double v)
+{
+    return __hiloint2double(__builtin_amdgcn_readfirstlane(__double2hiint(v)),
+                            __builtin_amdgcn_readfirstlane(__double2loint(v)));
+}
+
+// the pre-collision populations of node `up` with 32-bit offsets from the
+// box's array (valid while that array is under 4 GiB): a uniform base and one
+// 32-bit offset per load instead of 64-bit address arithmetic
 template <typename R>
+__device__ __forceinline__ void gather_pre32(const R* __restrict__ a, const Upwind& up, R d[19])
+{
+    const char* base = (const char*)a;
+#pragma unroll
+    for (int i = 0; i < 19; ++i) {
+        const uint32_t s = up.src(i);
+        const uint32_t e = ((s >> PTILE_LOG) * 19u + (uint32_t)i) * PTILE + (s & (PTILE - 1u));
+        d[i] = *(const R*)(base + (uint64_t)(e * (uint32_t)sizeof(R)));
+    }
+}
+
+template <typename R, bool O32>
 __global__ __launch_bounds__(256) void k_stats(const BoxDev* __restrict__ boxes, const R* __restrict__ A,
                                                double* __restrict__ part)
 {
@@ -1692,26 +1731,42 @@ __global__ __launch_bounds__(256) void k_stats(const BoxDev* __restrict__ boxes,
     if (c >= stat_recs_of(bx.n_tiles)) return;
     const uint32_t V = (uint32_t)bx.L * bx.L * bx.L;
     const R* a = A + bx.pop_off;
+    // n_i = fl(w_i rho0) + delta_i (FP64) is negative exactly when delta_i
+    // lies below -fl(w_i rho0): the rounded sum of two doubles keeps the sign
+    // of the exact one.  For FP32 storage the test compares delta_i with the
+    // smallest float not below that double, which decides the same; the
+    // count is an integer.
+    R thr[19];
+#pragma unroll
+    for (int i = 0; i < 19; ++i) {
+        const double cth = -(wv(i) * bx.rho0);
+        R f = (R)cth;
+        if ((double)f < cth) f = nextafter(f, (R)INFINITY);
+        thr[i] = uniform_value(f);   // the same in every lane: kept in scalar registers
+    }
     double acc[NSTAT];
 #pragma unroll
     for (int k = 0; k < NSTAT; ++k) acc[k] = 0.0;
+    uint32_t neg = 0;
     for (int k = 0; k < STAT_TPB; ++k) {
         const uint32_t r = (c * STAT_TPB + k) * 256u + threadIdx.x;
         if (r >= V) break;
         const Upwind up = upwind_of(r, bx.L, bx.inv_L);
         R dr[19];
-        gather_pre<R, false>(a, up, dr);
+        if (O32) gather_pre32<R>(a, up, dr);
+        else gather_pre<R, false>(a, up, dr);
         double d[19], m[19];
 #pragma unroll
         for (int i = 0; i < 19; ++i) {
             d[i] = (double)dr[i];
-            if (wv(i) * bx.rho0 + d[i] < 0.0) acc[4] += 1.0;
+            neg += dr[i] < thr[i] ? 1u : 0u;
         }
         to_modes<double>(d, m);
         acc[0] += m[0]; acc[1] += m[1]; acc[2] += m[2]; acc[3] += m[3];
 #pragma unroll
         for (int q = 0; q < 19; ++q) acc[5 + q] += m[q] * m[q];
     }
+    acc[4] = (double)neg;   // what adding 1.0 per negative population gives, exactly
     const double s = block_sum256<NSTAT>(acc, red);
     if (threadIdx.x < NSTAT) part[(uint64_t)(bx.stat_off + c) * NSTAT + threadIdx.x] = s;
 }
@@ -1876,7 +1931,7 @@ hipError_t launch_collide_deferred(const LaunchCtx& c, const void* A, void* B, u
     if (!c.defer_on || c.defer_cap == 0) return hipErrorInvalidValue;
     // a grid of a few blocks per CU strides over the list (its length is
     // known on the device only)
-    const uint32_t grid = std::min<uint32_t>(c.defer_cap, (uint32_t)(4 * c.n_cu));
+    const uint32_t grid = std::min<uint32_t>((c.defer_cap + DSEG_PER_TILE - 1) / DSEG_PER_TILE, (uint32_t)(4 * c.n_cu));
     hipLaunchKernelGGL(k_collide_deferred<R>, dim3(grid), dim3(256), 0, c.stream, c.boxes,
                        (const CollideConst<R>*)c.ccs, c.tile_box, (const uint32_t*)c.defer_list, c.defer_cap, c.imp,
                        (const R*)A, (R*)B, c.ctrl, s_off);
@@ -2003,7 +2058,17 @@ template <typename R>
 hipError_t launch_stats(const LaunchCtx& c, const void* A, uint32_t max_recs, double* part, double* mid,
                         double* out)
 {
-    hipLaunchKernelGGL(k_stats<R>, dim3(max_recs, c.n_boxes), dim3(256), 0, c.stream, c.boxes, (const R*)A, part);
+    // every box's population array under 4 GiB: 32-bit offsets
+    bool o32 = true;
+    for (int b = 0; b < c.n_boxes; ++b)
+        o32 = o32 && pop_elems_of((uint64_t)c.boxes_host[b].L * c.boxes_host[b].L * c.boxes_host[b].L) * sizeof(R) <
+                         ((uint64_t)1 << 32);
+    if (o32)
+        hipLaunchKernelGGL((k_stats<R, true>), dim3(max_recs, c.n_boxes), dim3(256), 0, c.stream, c.boxes, (const R*)A,
+                           part);
+    else
+        hipLaunchKernelGGL((k_stats<R, false>), dim3(max_recs, c.n_boxes), dim3(256), 0, c.stream, c.boxes,
+                           (const R*)A, part);
     hipLaunchKernelGGL(k_stats_mid, dim3(STAT_CHUNKS, c.n_boxes), dim3(256), 0, c.stream, c.boxes, part, mid);
     hipLaunchKernelGGL(k_stats_final, dim3(c.n_boxes), dim3(64), 0, c.stream, mid, out);
     return hipGetLastError();

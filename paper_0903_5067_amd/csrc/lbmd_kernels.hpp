@@ -44,14 +44,15 @@ struct LaunchCtx {
     uint32_t* bin_start;           // dense boxes: per base node, first binned stencil run [L^3 + 1]
     unsigned long long* runimp;    // dense boxes: per stencil run, the fixed-point impulse to its 8 corners x 3
     uint32_t* slot_of;             // dense boxes: per bead and run, the run's slot [N x substeps]
-    // deferred tiles: in a batched step the collide tiles that hold a node of
-    // any table of a sparse box's large chain are left out of the plain
-    // collide and collided with their impulses beside it, once the coupling
-    // is done; impulses that land outside them are listed for a fix-up
+    // deferred segments: in a batched step the 64-node segments (wavefronts
+    // of the collide tiles) that hold a node of any table of a sparse box's
+    // large chain are left out of the plain collide and collided with their
+    // impulses beside it, once the coupling is done; impulses that land
+    // outside them are listed for a fix-up
     int defer_on;                  // this launch defers (the pointers below are always set)
-    uint32_t* defer;               // per collide tile: stamp of the last step that deferred it
-    uint32_t* dclaim;              // per collide tile: stamp of the last step that listed it
-    uint32_t* defer_list;          // the deferred tiles, Ctrl::defer_cnt of them
+    uint32_t* defer;               // per segment and step parity: stamp of the last step that deferred it
+    uint32_t* dclaim;              // per segment: stamp of the last step that listed it
+    uint32_t* defer_list;          // the deferred segments, Ctrl::defer_cnt of them
     uint32_t defer_cap;
     uint32_t* ovf;                 // (bead, local node) pairs, Ctrl::ovf_cnt of them
     uint32_t ovf_cap;

@@ -238,14 +238,14 @@ Layout make_layout(const lb_box_desc* b, int32_t n, int32_t prec, int32_t hist)
         Lo.sc_binstart = o; o = align256(o + std::max<uint64_t>(Lo.bin_entries, 1) * sizeof(uint32_t));
         Lo.sc_items = o; o = align256(o + std::max<uint64_t>(Lo.item_entries, 1) * 24 * sizeof(unsigned long long));
         Lo.sc_slotof = o; o = align256(o + std::max<uint64_t>(Lo.item_entries, 1) * sizeof(uint32_t));
-        // deferred tiles: three step stamps per collide tile (deferred in the
-        // steps of either parity, listed in); a tile is listed
-        // once, and a bead's table spans at most 27 tiles.  A bead hands
-        // impulses to at most 8 new nodes per substep.
+        // deferred segments (64 nodes, four per collide tile): three step
+        // stamps per segment (deferred in the steps of either parity, listed
+        // in); a segment is listed once, and a bead's table spans at most
+        // 27.  A bead hands impulses to at most 8 new nodes per substep.
         Lo.defer_cap = (uint32_t)(27 * Lo.beads_big_sparse);
         Lo.ovf_cap = (uint32_t)(8 * (uint64_t)std::max(Lo.big_max_sub, 1) * Lo.beads_big_sparse);
-        Lo.sc_defer = o; o = align256(o + (Lo.beads_big_sparse ? 2 * tiles : 1) * sizeof(uint32_t));
-        Lo.sc_dclaim = o; o = align256(o + (Lo.beads_big_sparse ? tiles : 1) * sizeof(uint32_t));
+        Lo.sc_defer = o; o = align256(o + (Lo.beads_big_sparse ? 2 * DSEG_PER_TILE * tiles : 1) * sizeof(uint32_t));
+        Lo.sc_dclaim = o; o = align256(o + (Lo.beads_big_sparse ? DSEG_PER_TILE * tiles : 1) * sizeof(uint32_t));
         Lo.sc_dlist = o; o = align256(o + std::max<uint32_t>(Lo.defer_cap, 1) * sizeof(uint32_t));
         Lo.sc_ovf = o; o = align256(o + std::max<uint32_t>(Lo.ovf_cap, 1) * 2 * sizeof(uint32_t));
         Lo.sc_ovm = o; o = align256(o + (Lo.beads_big_sparse ? nodes : 1) * sizeof(uint32_t));
@@ -341,9 +341,11 @@ hipError_t clear_step_stamps(lb_handle* h)
     if (e == hipSuccess)
         e = hipMemsetAsync(ctrl + offsetof(Ctrl, ovf_flag), 0, sizeof(Ctrl) - offsetof(Ctrl, ovf_flag), h->stream);
     if (e == hipSuccess && lo.beads_big_sparse) {
-        e = hipMemsetAsync(h->scratch + lo.sc_defer, 0, 2 * lo.total_tiles * sizeof(uint32_t), h->stream);
+        e = hipMemsetAsync(h->scratch + lo.sc_defer, 0, 2 * DSEG_PER_TILE * lo.total_tiles * sizeof(uint32_t),
+                           h->stream);
         if (e == hipSuccess)
-            e = hipMemsetAsync(h->scratch + lo.sc_dclaim, 0, lo.total_tiles * sizeof(uint32_t), h->stream);
+            e = hipMemsetAsync(h->scratch + lo.sc_dclaim, 0, DSEG_PER_TILE * lo.total_tiles * sizeof(uint32_t),
+                               h->stream);
         if (e == hipSuccess)
             e = hipMemsetAsync(h->scratch + lo.sc_ovm, 0, lo.total_nodes * sizeof(uint32_t), h->stream);
     }
