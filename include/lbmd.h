@@ -188,7 +188,7 @@ lb_status lb_observables(lb_handle* h, lb_obs* out);
  * device, from the first lb_init on that device until the process ends)
  * instead of the handle's scratch buffer.  Allocates nothing.  Same kernels
  * and summation order as lb_observables, so the same bits.  The partials
- * take 192 bytes per 2048 nodes of each box (rounded up per box) plus 12.5
+ * take 192 bytes per 4096 nodes of each box (rounded up per box) plus 12.5
  * KB per box; LB_ENOMEM if they exceed the array (the message gives both
  * sizes), LB_EDEVICE if the array's device address could not be found at
  * init.  Every call on one device shares that device's array: calls that

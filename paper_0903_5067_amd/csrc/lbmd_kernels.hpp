@@ -140,7 +140,7 @@ hipError_t launch_adj_couple(const LaunchCtx& c, const int32_t* list, int n_list
 constexpr int N_COLLIDE_VARIANTS = 13;
 constexpr int DEFAULT_COLLIDE_VARIANT = 3;   // one block per tile, at most 7 waves per SIMD
 constexpr int NSTAT_REC = 24;
-constexpr int STAT_TPB = 8;       // collide tiles per block of the observables pass (8 nodes per thread)
+constexpr int STAT_TPB = 16;      // collide tiles per block of the observables pass (16 nodes per thread)
 constexpr int STAT_CHUNKS = 64;   // per box, the block records are summed in this many fixed ranges first
 __host__ __device__ inline uint32_t stat_recs_of(uint32_t n_tiles) { return (n_tiles + STAT_TPB - 1) / STAT_TPB; }
 constexpr int NCHAIN_REC = 11;
