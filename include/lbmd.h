@@ -238,16 +238,20 @@ lb_status lb_bead_positions(lb_handle* h, double* host_out, size_t bytes);
 /* Launch structure of lb_step (the arithmetic is that of lb_step, Sec. II.B,
  * in every form): batched = 1 advances every box with one launch per kernel
  * (the default); batched = 0 launches per box (the plain form).  In batched
- * steps the collide tiles around chains above 256 beads in boxes they do not
- * cover densely are collided beside the other tiles once the chain's
+ * steps the 64-node segments around chains above 256 beads in boxes they do
+ * not cover densely are collided beside the other nodes once the chain's
  * impulses are in; batched = 2 re-collides the chain's nodes after the
  * collide instead.  All forms compute the same bits.
  * graph_steps > 0 records that many LB steps (rounded up to even) in a HIP
  * graph and replays it; 0 launches kernels directly.  The graphs of both
  * buffer parities are recorded and instantiated here, before returning
- * (synchronous), so that lb_step only replays them.  LB_EINVAL for batched
- * outside 0..2 or graph_steps < 0, LB_ESTATE with impulses pending,
- * LB_EDEVICE if capture or instantiation fails. */
+ * (synchronous), so that lb_step only replays them.  Exception: batched FP32
+ * steps whose chains all exceed 256 beads (and cover no box densely) are
+ * always launched directly: each collide there carries the step's node
+ * tables and a resident chain kernel waits for them, an order that graph
+ * replay does not keep (a stream under capture takes a graph-safe form).
+ * LB_EINVAL for batched outside 0..2 or graph_steps < 0, LB_ESTATE with
+ * impulses pending, LB_EDEVICE if capture or instantiation fails. */
 lb_status lb_set_launch(lb_handle* h, int32_t batched, int32_t graph_steps);
 
 /* ---- adjoint window (gradient of a loss of the bead velocities) ----------

@@ -1613,7 +1613,9 @@ __global__ __launch_bounds__(256) void k_collide_deferred(const BoxDev* __restri
     // one wavefront per listed segment
     const uint32_t t = ctrl->step + s_off;
     const uint32_t n = min(ctrl->defer_cnt, cap);
-    const uint32_t w = threadIdx.x / DSEG, lane = threadIdx.x % DSEG;
+    // the wavefront index made uniform: the segment, its tile and box, and the
+    // box constants then sit in scalar registers
+    const uint32_t w = __builtin_amdgcn_readfirstlane(threadIdx.x / DSEG), lane = threadIdx.x % DSEG;
     for (uint32_t k = blockIdx.x * DSEG_PER_TILE + w; k < n; k += gridDim.x * DSEG_PER_TILE) {
         const uint32_t seg = defer_list[k];
         collide_forced_tile<R>(boxes, ccs, tile_box, -1, seg / DSEG_PER_TILE, imp, A, B, ctrl, t,
