@@ -1,6 +1,6 @@
 """Throughput of the fluctuating D3Q19 LB step with bead coupling on one MI355X.
 
-One step = one full LB step of every §-path stage: the chain's MD substeps in
+One step = one full LB step through every stage of the path: the chain's MD substeps in
 the frozen fluid with trilinear interpolation and impulse spreading, the
 fused collide+stream of every node, the re-collision of the impulse nodes.
 Inputs are seeded and synthetic (lbinputs.py) and resident in HBM before the
@@ -404,6 +404,9 @@ def main():
     ap.add_argument("--fixup-after-collide", action="store_true",
                     help="re-collide the chain's nodes after the collide instead of colliding their tiles "
                          "beside it (same results; for comparison)")
+    ap.add_argument("--no-resident-wait", action="store_true",
+                    help="no chain kernel waits for a later collide (needed under hardware counter "
+                         "collection, which runs one kernel at a time)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run the plain copy used to scale the HBM byte counters")
     ap.add_argument("--only-semidilute", action="store_true",
@@ -440,10 +443,9 @@ def main():
         return
     log("workload", args.workload)
     s, boxes, nodes, prec = make_system(args.workload)
-    if args.graph_steps:
-        s.set_launch(batched=True, graph_steps=args.graph_steps, overlap=not args.fixup_after_collide)
-    elif args.fixup_after_collide:
-        s.set_launch(batched=True, graph_steps=0, overlap=False)
+    if args.graph_steps or args.fixup_after_collide or args.no_resident_wait:
+        s.set_launch(batched=True, graph_steps=args.graph_steps, overlap=not args.fixup_after_collide,
+                     resident=not args.no_resident_wait)
     tune = None
     import paper_0903_5067_amd as lbm
     if args.variant >= 0:

@@ -250,7 +250,12 @@ lb_status lb_bead_positions(lb_handle* h, double* host_out, size_t bytes);
  * always launched directly: each collide there carries the step's node
  * tables and a resident chain kernel waits for them, an order that graph
  * replay does not keep (a stream under capture takes a graph-safe form).
- * LB_EINVAL for batched outside 0..2 or graph_steps < 0, LB_ESTATE with
+ * Such a run also needs the GPU to run kernels of its two streams at once;
+ * where a tool runs one kernel at a time (hardware counter collection), the
+ * wait gives up and LB_HEALTH_SYNC is set.  batched = 3 is batched = 1
+ * without that layout: the node tables get a kernel of their own, and
+ * graph_steps applies.
+ * LB_EINVAL for batched outside 0..3 or graph_steps < 0, LB_ESTATE with
  * impulses pending, LB_EDEVICE if capture or instantiation fails. */
 lb_status lb_set_launch(lb_handle* h, int32_t batched, int32_t graph_steps);
 

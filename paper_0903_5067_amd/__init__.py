@@ -180,8 +180,14 @@ class LBSystem:
     def step(self, n: int = 1):
         _check(lib().lb_step(self.h, int(n)), self.h)
 
-    def set_launch(self, batched: bool = True, graph_steps: int = 0, overlap: bool = True):
-        mode = (1 if overlap else 2) if batched else 0
+    def set_launch(self, batched: bool = True, graph_steps: int = 0, overlap: bool = True,
+                   resident: bool = True):
+        """Launch structure of step (lb_set_launch): batched or per box,
+        graph_steps per HIP graph (0: direct launches), overlap False to
+        re-collide the chain's nodes after the collide, resident False to keep
+        every chain kernel from waiting for a later collide (for tools that
+        run one kernel at a time)."""
+        mode = ((3 if not resident else 1) if overlap else 2) if batched else 0
         _check(lib().lb_set_launch(self.h, mode, int(graph_steps)), self.h)
 
     def collide_only(self, n: int = 1):

@@ -352,6 +352,15 @@ __device__ __forceinline__ uint32_t flush_stencil(const ChainArgs& ca, uint64_t 
 // 0..T*Npad-1: bead b = tid / T, lane = tid % T.  All T lanes of a bead
 // compute the same bead update (their force partial sums are combined by a
 // butterfly, which gives every lane the same bits); lane 0 writes.
+// Lane l of bead b owns the partners j = l, l + T, l + 2T, ... (j != b).  It
+// keeps the ones within the list radius (cut-off plus NL_SKIN) in its own
+// list, in ascending j, built at the first substep and again whenever some
+// bead of the chain has moved more than half the skin since the last build:
+// every partner within the cut-off is then on the list, and the list holds
+// them in the order of the full scan, so the forces are the same bits.  A
+// lane whose partners within the list radius exceed its slots scans all of
+// them instead.
+constexpr int CPL_SLOTS = 32;   // list slots per lane of the one-workgroup coupling kernel
 template <typename R, int MAXT = 256>
 __global__ __launch_bounds__(MAXT) void k_couple(const BoxDev* __restrict__ boxes,
                                                  const int32_t* __restrict__ couple_list,
@@ -359,6 +368,9 @@ __global__ __launch_bounds__(MAXT) void k_couple(const BoxDev* __restrict__ boxe
                                                  Ctrl* __restrict__ ctrl, uint32_t s_off)
 {
     __shared__ double xs[3 * BIG_CHAIN];   // chains on this path have at most BIG_CHAIN beads
+    static_assert(BIG_CHAIN <= 256, "partner indices are stored in one byte");
+    __shared__ uint8_t nl[MAXT * CPL_SLOTS + 4];   // per lane: its partners within the list radius
+    __shared__ int moved[2];                        // per substep parity: a bead moved past half the skin
     __builtin_amdgcn_s_setprio(3);   // latency-bound chain beside the bandwidth-bound collide
     const int bi = couple_list[blockIdx.x];
     const BoxDev bx = boxes[bi];   // a copy: its fields stay in registers across the substeps
@@ -378,6 +390,12 @@ __global__ __launch_bounds__(MAXT) void k_couple(const BoxDev* __restrict__ boxe
     const double inv_tau = 1.0 / bx.tau_lb;
     const double eps24 = 24.0 * bx.eps;
     const R* a = A + bx.pop_off;
+    // list radius, a hair above cut-off plus skin so that rounding cannot
+    // drop a partner that comes within the cut-off
+    const double rl = sqrt(bx.rc2) + NL_SKIN + 1e-6;
+    const double rl2 = rl * rl;
+    const uint32_t nl_base = threadIdx.x * CPL_SLOTS;
+    if (threadIdx.x == 0) { moved[0] = 0; moved[1] = 0; }
 
     double x[3] = {0, 0, 0}, v[3] = {0, 0, 0}, f[3] = {0, 0, 0}, fcl[3] = {0, 0, 0};
     if (act) {
@@ -400,6 +418,8 @@ __global__ __launch_bounds__(MAXT) void k_couple(const BoxDev* __restrict__ boxe
     bool have_acc = false;
     uint32_t hbits = 0;
     int tcnt = 0;
+    double x0[3] = {0, 0, 0};     // position at the last list build
+    int nl_n = -1;                // entries of this lane's list (-1: the lane scans all its partners)
 
     for (int s = 0; s < bx.substeps; ++s) {
         if (act) {
@@ -408,14 +428,41 @@ __global__ __launch_bounds__(MAXT) void k_couple(const BoxDev* __restrict__ boxe
                 v[c] += f[c] * hdt_m;
                 x[c] += v[c] * dt;
             }
-            if (lane == 0) { xs[3 * b] = x[0]; xs[3 * b + 1] = x[1]; xs[3 * b + 2] = x[2]; }
+            if (lane == 0) {
+                xs[3 * b] = x[0]; xs[3 * b + 1] = x[1]; xs[3 * b + 2] = x[2];
+                const double e0 = x[0] - x0[0], e1 = x[1] - x0[1], e2 = x[2] - x0[2];
+                if (s > 0 && e0 * e0 + e1 * e1 + e2 * e2 > 0.25 * NL_SKIN * NL_SKIN) moved[s & 1] = 1;
+            }
         }
         __syncthreads();
+        // the same for every thread: the flag of this parity was cleared a
+        // substep ago, and the other parity's is cleared now, after every
+        // read of it
+        const bool rebuild = s == 0 || moved[s & 1] != 0;
+        if (threadIdx.x == 0) moved[(s + 1) & 1] = 0;
         if (act) {
-            // repulsive LJ over all partners (at most 256), this lane's share
+            if (rebuild) {
+                x0[0] = x[0]; x0[1] = x[1]; x0[2] = x[2];
+                int cnt = 0;
+                for (int j = lane; j < N; j += T) {
+                    double d0 = x[0] - xs[3 * j], d1 = x[1] - xs[3 * j + 1], d2 = x[2] - xs[3 * j + 2];
+                    d0 -= Ld * rint(d0 * iL); d1 -= Ld * rint(d1 * iL); d2 -= Ld * rint(d2 * iL);
+                    if (j != b && d0 * d0 + d1 * d1 + d2 * d2 < rl2) {
+                        if (cnt < CPL_SLOTS) nl[nl_base + cnt] = (uint8_t)j;
+                        ++cnt;
+                    }
+                }
+                nl_n = cnt <= CPL_SLOTS ? cnt : -1;
+            }
+            // repulsive LJ over this lane's share of the partners
             double W[3] = {0, 0, 0};
-            auto jof = [](int k) { return k; };
-            for (int j = lane; j < N; j += 4 * T) wca_add4(x, xs, jof, j, N, T, b, Ld, iL, bx.rc2, bx.sigsq, eps24, W);
+            if (nl_n >= 0) {
+                auto jl = [&](int k) { return (int)nl[nl_base + k]; };
+                for (int k = 0; k < nl_n; k += 4) wca_add4(x, xs, jl, k, nl_n, 1, b, Ld, iL, bx.rc2, bx.sigsq, eps24, W);
+            } else {
+                auto jof = [](int k) { return k; };
+                for (int j = lane; j < N; j += 4 * T) wca_add4(x, xs, jof, j, N, T, b, Ld, iL, bx.rc2, bx.sigsq, eps24, W);
+            }
             for (int o = 1; o < T; o <<= 1) {
 #pragma unroll
                 for (int c = 0; c < 3; ++c) W[c] += __shfl_xor(W[c], o, T);

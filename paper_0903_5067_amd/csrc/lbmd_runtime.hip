@@ -301,6 +301,7 @@ struct lb_handle {
     bool pending = false;             // lb_couple done, impulses not yet consumed
     int batched = 1;
     int overlap = 1;                  // batched steps defer the tiles around large chains (see enqueue_step)
+    int resident = 1;                 // runs may keep a chain kernel waiting for a later collide (fused_steps)
     int graph_steps = 0;
     hipGraphExec_t gexec[2] = {nullptr, nullptr};
     hipGraph_t graph[2] = {nullptr, nullptr};
@@ -523,12 +524,15 @@ lb_status enqueue_headed_run(lb_handle* h, int from, uint32_t n)
 // is resident before that step's collide: they are launched directly, never
 // from a HIP graph, whose replay does not keep that order (the chain kernel's
 // bounded wait then gives up).  A stream under capture takes the layout of
-// enqueue_headed_run instead.
+// enqueue_headed_run instead, and so does launch mode 3 (lb_set_launch), for
+// tools that run one kernel at a time, such as hardware counter collection:
+// there the waiting chain kernel can hold the GPU while the collide it waits
+// for has not started.
 bool fused_steps(const lb_handle* h)
 {
     // the collide's node-table workgroups wait for each other, so they must
     // fit on the GPU at once: at most one per CU
-    return headed_steps(h) && h->couple_host.empty() && h->prec == LB_FP32_DEV &&
+    return h->resident && headed_steps(h) && h->couple_host.empty() && h->prec == LB_FP32_DEV &&
            head_blocks((int)h->lo.big_list.size(), h->lo.big_max_n) <= (uint32_t)h->ctx.n_cu;
 }
 
@@ -1199,12 +1203,13 @@ lb_status lb_set_launch(lb_handle* h, int32_t batched, int32_t graph_steps)
 {
     if (!h) return fail(nullptr, LB_EINVAL, "null handle");
     if (graph_steps < 0) return fail(h, LB_EINVAL, "graph_steps must be >= 0");
-    if (batched < 0 || batched > 2) return fail(h, LB_EINVAL, "batched must be 0, 1 or 2");
+    if (batched < 0 || batched > 3) return fail(h, LB_EINVAL, "batched must be 0, 1, 2 or 3");
     if (h->pending) return fail(h, LB_ESTATE, "impulses pending from lb_couple");
     HIPCHK(h, hipStreamSynchronize(h->stream));
     drop_graphs(h);
     h->batched = batched ? 1 : 0;
     h->overlap = batched == 2 ? 0 : 1;
+    h->resident = batched == 3 ? 0 : 1;
     h->graph_steps = graph_steps + (graph_steps & 1);
     return prepare_graphs(h);
 }

@@ -399,9 +399,11 @@ def test_deferred_tiles_equal_fixup_after_collide_bitwise(prec, graph_steps):
             assert np.array_equal(out[0][i][k], out[1][i][k]), (i, k)
 
 
-@pytest.mark.parametrize("prec,graph_steps", [(FP64, 0), (FP32, 0), (FP64, 4), (FP32, 6)])
+@pytest.mark.parametrize("prec,graph_steps,resident",
+                         [(FP64, 0, True), (FP32, 0, True), (FP64, 4, True), (FP32, 6, True),
+                          (FP32, 0, False), (FP32, 6, False)])
 @pytest.mark.parametrize("small", [True, False])
-def test_two_queue_runs_equal_fixup_after_collide_bitwise(prec, graph_steps, small):
+def test_two_queue_runs_equal_fixup_after_collide_bitwise(prec, graph_steps, resident, small):
     """With no dense box, a run of batched steps puts the chain work of step k
     right behind the collide of step k-1, where the previous step's impulses
     outside its deferred tiles are re-collided too.  With a small chain in
@@ -411,8 +413,10 @@ def test_two_queue_runs_equal_fixup_after_collide_bitwise(prec, graph_steps, sma
     them.  Twelve steps in one call (one run, or graph replays of several
     steps) give the bits of twelve steps with the chains' nodes re-collided
     after each collide; the hot box's beads leave their node tables within
-    the twelve steps."""
-    say("two-queue runs vs fix-up", prec, graph_steps, "small chain" if small else "large chains only")
+    the twelve steps.  Launch mode 3 (resident=False) keeps the node tables in
+    a kernel of their own, with the same bits."""
+    say("two-queue runs vs fix-up", prec, graph_steps, "small chain" if small else "large chains only",
+        "resident" if resident else "no resident wait")
     hot = dict(kT=1.0, therm=0, md_dt=0.01, md_substeps=25, tau_lb=0.25, zeta=1.0, k_fene=7.0, r0_fene=2.0)
     boxes = [params(L=40, N=300, kT=1e-2, seed=7, box_id=0),
              params(L=40, N=300, seed=7, box_id=1, **hot)]
@@ -431,7 +435,7 @@ def test_two_queue_runs_equal_fixup_after_collide_bitwise(prec, graph_steps, sma
     want = ref.export_state()["boxes"]
     ref.close()
     s = gpu_system(boxes, prec, xs=xs)
-    s.set_launch(batched=True, graph_steps=graph_steps, overlap=True)
+    s.set_launch(batched=True, graph_steps=graph_steps, overlap=True, resident=resident)
     s.step(12)
     assert all(o["health"] == 0 for o in s.observables())
     got = s.export_state()["boxes"]
