@@ -221,6 +221,50 @@ __device__ __forceinline__ void stencil_velocities(const R* __restrict__ a, cons
     }
 }
 
+// stencil_velocities over the T lanes of one bead (T = 8 / NK, or 16 with the
+// upper eight lanes repeating the lower): lane l gathers corners l, l + T8,
+// ... (NK of them, T8 = 8 / NK), and the lanes then exchange them, so that
+// every lane ends with all eight corners, computed as stencil_velocities
+// computes them
+template <typename R, int NK>
+__device__ __forceinline__ void stencil_shared(const R* __restrict__ a, const int i0[3], int L, double rho0,
+                                               double inv_tau, int lane, int T, R u[8][3])
+{
+    constexpr int T8 = 8 / NK;
+    R d[NK][19];
+    const int k0 = lane & (T8 - 1);
+#pragma unroll
+    for (int k = 0; k < NK; ++k) {
+        const int kk = k0 + k * T8;
+        const int ix = i0[0] + (kk & 1), iy = i0[1] + ((kk >> 1) & 1), iz = i0[2] + ((kk >> 2) & 1);
+        const Upwind up((uint32_t)(ix >= L ? ix - L : ix), (uint32_t)(iy >= L ? iy - L : iy),
+                        (uint32_t)(iz >= L ? iz - L : iz), (uint32_t)L);
+        gather_pre<R, false>(a, up, d[k]);
+    }
+    R own[NK][3];
+#pragma unroll
+    for (int k = 0; k < NK; ++k) {
+        double rho = 0.0, jx = 0.0, jy = 0.0, jz = 0.0;
+#pragma unroll
+        for (int i = 0; i < 19; ++i) {
+            const double di = (double)d[k][i];
+            rho += di;
+            if (cxv(i)) jx += cxv(i) * di;
+            if (cyv(i)) jy += cyv(i) * di;
+            if (czv(i)) jz += czv(i) * di;
+        }
+        rho += rho0;
+        own[k][0] = (R)(jx / rho * inv_tau);
+        own[k][1] = (R)(jy / rho * inv_tau);
+        own[k][2] = (R)(jz / rho * inv_tau);
+    }
+    // corner k sits in slot k / T8 of lane k % T8 of the bead's lanes
+#pragma unroll
+    for (int k = 0; k < 8; ++k)
+#pragma unroll
+        for (int c = 0; c < 3; ++c) u[k][c] = __shfl(own[k / T8][c], k % T8, T);
+}
+
 constexpr int MAXB = 1024;
 constexpr double NL_SKIN = 0.5;
 
@@ -492,7 +536,11 @@ __global__ __launch_bounds__(MAXT) void k_couple(const BoxDev* __restrict__ boxe
                                (uint32_t)L * ((uint32_t)(iy >= L ? iy - L : iy) + (uint32_t)L * (uint32_t)(iz >= L ? iz - L : iz));
                     acc[k][0] = acc[k][1] = acc[k][2] = 0.0;
                 }
-                stencil_velocities<R, R, 8>(a, i0, L, bx.rho0, inv_tau, cu);
+                // the bead's lanes share the gathers (T is uniform over the workgroup)
+                if (T >= 8) stencil_shared<R, 1>(a, i0, L, bx.rho0, inv_tau, lane, T, cu);
+                else if (T == 4) stencil_shared<R, 2>(a, i0, L, bx.rho0, inv_tau, lane, T, cu);
+                else if (T == 2) stencil_shared<R, 4>(a, i0, L, bx.rho0, inv_tau, lane, T, cu);
+                else stencil_velocities<R, R, 8>(a, i0, L, bx.rho0, inv_tau, cu);
                 cb[0] = i0[0]; cb[1] = i0[1]; cb[2] = i0[2];
                 have_acc = true;
             }
