@@ -2351,6 +2351,35 @@ __global__ __launch_bounds__(256) void k_adj_collide(const BoxDev* __restrict__ 
     }
 }
 
+// densities of the eight stencil nodes over the T lanes of one bead, as
+// stencil_shared splits the corners: lane l sums corners l, l + T8, ... (NK
+// of them, T8 = 8 / NK), then the lanes exchange the sums
+template <typename R, int NK>
+__device__ __forceinline__ void adj_densities(const R* __restrict__ a, const int i0[3], int L, double rho0,
+                                              int lane, int T, double rho_k[8])
+{
+    constexpr int T8 = 8 / NK;
+    const int k0 = lane & (T8 - 1);
+    R dn[NK][19];
+#pragma unroll
+    for (int k = 0; k < NK; ++k) {
+        const int kk = k0 + k * T8;
+        const int ix = i0[0] + (kk & 1), iy = i0[1] + ((kk >> 1) & 1), iz = i0[2] + ((kk >> 2) & 1);
+        const Upwind up((uint32_t)(ix >= L ? ix - L : ix), (uint32_t)(iy >= L ? iy - L : iy),
+                        (uint32_t)(iz >= L ? iz - L : iz), (uint32_t)L);
+        gather_pre<R, false>(a, up, dn[k]);
+    }
+    double own[NK];
+#pragma unroll
+    for (int k = 0; k < NK; ++k) {
+        double rho = 0.0;
+        for (int i = 0; i < 19; ++i) rho += (double)dn[k][i];
+        own[k] = rho + rho0;
+    }
+#pragma unroll
+    for (int k = 0; k < 8; ++k) rho_k[k] = __shfl(own[k / T8], k % T8, T);
+}
+
 // add dJ/dv(end of step) and reverse the chain's substeps of one LB step; one
 // workgroup per chain (at most 256 beads), thread per bead.
 struct AdjChainArgs {
@@ -2408,9 +2437,10 @@ __global__ __launch_bounds__(256) void k_adj_couple(const BoxDev* __restrict__ b
     double rho_k[8];
     uint32_t cnode[8];
     double cuk[8][3];
+    double la[8][3];           // tau * lam_dp at the stencil's nodes
     bool have = false;
     const R* pb = P + bx.pop_off;
-    auto flush = [&]() {       // node velocity adjoint -> population adjoint at the stencil nodes
+    auto flush = [&]() __attribute__((always_inline)) {   // node velocity adjoint -> population adjoint at the stencil nodes
 #pragma unroll
         for (int k = 0; k < 8; ++k) {
             const double ir = 1.0 / (rho_k[k] * tau);
@@ -2422,15 +2452,23 @@ __global__ __launch_bounds__(256) void k_adj_couple(const BoxDev* __restrict__ b
             }
         }
     };
+    // tape record of substep s, loaded one substep ahead
+    double nx1[3] = {0, 0, 0}, nv1[3] = {0, 0, 0}, nfc[3] = {0, 0, 0}, nfr[3] = {0, 0, 0}, ni0[3] = {0, 0, 0};
+    auto load_rec = [&](int s) __attribute__((always_inline)) {
+        const double* tq = aa.tape + ((uint64_t)s * aa.total_beads + g) * TAPE_REC;
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            nx1[c] = tq[c]; nv1[c] = tq[3 + c]; nfc[c] = tq[6 + c]; ni0[c] = tq[9 + c]; nfr[c] = tq[12 + c];
+        }
+    };
+    if (act) load_rec(S - 1);
     for (int s = S - 1; s >= 0; --s) {
         const double* tp = aa.tape + ((uint64_t)s * aa.total_beads + g) * TAPE_REC;
-        double x1[3] = {0, 0, 0}, v1[3] = {0, 0, 0}, fc[3] = {0, 0, 0}, fr[3] = {0, 0, 0};
-        int i0[3] = {0, 0, 0};
-        if (act)
+        double x1[3], v1[3], fc[3], fr[3];
+        int i0[3];
 #pragma unroll
-            for (int c = 0; c < 3; ++c) {
-                x1[c] = tp[c]; v1[c] = tp[3 + c]; fc[c] = tp[6 + c]; i0[c] = (int)tp[9 + c]; fr[c] = tp[12 + c];
-            }
+        for (int c = 0; c < 3; ++c) { x1[c] = nx1[c]; v1[c] = nv1[c]; fc[c] = nfc[c]; i0[c] = (int)ni0[c]; fr[c] = nfr[c]; }
+        if (act && s > 0) load_rec(s - 1);
         // v' = v1 + f' h and f' = F_c + fc
         double lft[3], lv1[3], lfc[3];
 #pragma unroll
@@ -2445,32 +2483,50 @@ __global__ __launch_bounds__(256) void k_adj_couple(const BoxDev* __restrict__ b
             // stencil of this substep
             if (i0[0] != cb[0] || i0[1] != cb[1] || i0[2] != cb[2]) {
                 if (have && lane == 0) flush();
-                // the densities of the 8 nodes: all population loads of a
-                // batch are issued before any is summed
-                constexpr int NB = sizeof(R) == 4 ? 8 : 4;
 #pragma unroll
-                for (int k0 = 0; k0 < 8; k0 += NB) {
-                    R dn[NB][19];
+                for (int k = 0; k < 8; ++k) {
+                    const int ix = i0[0] + (k & 1), iy = i0[1] + ((k >> 1) & 1), iz = i0[2] + ((k >> 2) & 1);
+                    const uint32_t nx = ix >= L ? ix - L : ix, ny = iy >= L ? iy - L : iy, nz = iz >= L ? iz - L : iz;
+                    cnode[k] = nx + (uint32_t)L * (ny + (uint32_t)L * nz);
+                }
+                // the densities of the 8 nodes, gathered by the bead's lanes
+                // together (T is uniform over the workgroup)
+                if (T >= 8) adj_densities<R, 1>(pb, i0, L, bx.rho0, lane, T, rho_k);
+                else if (T == 4) adj_densities<R, 2>(pb, i0, L, bx.rho0, lane, T, rho_k);
+                else if (T == 2) adj_densities<R, 4>(pb, i0, L, bx.rho0, lane, T, rho_k);
+                else {
+                    // one lane per bead: all eight, in batches whose loads are
+                    // issued before any is summed
+                    constexpr int NB = sizeof(R) == 4 ? 8 : 4;
 #pragma unroll
-                    for (int kk = 0; kk < NB; ++kk) {
-                        const int k = k0 + kk;
-                        const int ix = i0[0] + (k & 1), iy = i0[1] + ((k >> 1) & 1), iz = i0[2] + ((k >> 2) & 1);
-                        const uint32_t nx = ix >= L ? ix - L : ix, ny = iy >= L ? iy - L : iy, nz = iz >= L ? iz - L : iz;
-                        cnode[k] = nx + (uint32_t)L * (ny + (uint32_t)L * nz);
-                        const Upwind up(nx, ny, nz, (uint32_t)L);
-                        gather_pre<R, false>(pb, up, dn[kk]);
-                    }
+                    for (int k0 = 0; k0 < 8; k0 += NB) {
+                        R dn[NB][19];
 #pragma unroll
-                    for (int kk = 0; kk < NB; ++kk) {
-                        double rho = 0.0;
-                        for (int i = 0; i < 19; ++i) rho += (double)dn[kk][i];
-                        rho_k[k0 + kk] = rho + bx.rho0;
+                        for (int kk = 0; kk < NB; ++kk) {
+                            const int k = k0 + kk;
+                            const int ix = i0[0] + (k & 1), iy = i0[1] + ((k >> 1) & 1), iz = i0[2] + ((k >> 2) & 1);
+                            const Upwind up((uint32_t)(ix >= L ? ix - L : ix), (uint32_t)(iy >= L ? iy - L : iy),
+                                            (uint32_t)(iz >= L ? iz - L : iz), (uint32_t)L);
+                            gather_pre<R, false>(pb, up, dn[kk]);
+                        }
+#pragma unroll
+                        for (int kk = 0; kk < NB; ++kk) {
+                            double rho = 0.0;
+                            for (int i = 0; i < 19; ++i) rho += (double)dn[kk][i];
+                            rho_k[k0 + kk] = rho + bx.rho0;
+                        }
                     }
                 }
 #pragma unroll
-                for (int k = 0; k < 8; ++k)
+                for (int k = 0; k < 8; ++k) {
+                    const uint64_t gn = bx.node_off + cnode[k];
 #pragma unroll
-                    for (int c = 0; c < 3; ++c) { cuk[k][c] = tp[15 + 3 * k + c]; lcu[k][c] = 0.0; }
+                    for (int c = 0; c < 3; ++c) {
+                        cuk[k][c] = tp[15 + 3 * k + c];
+                        lcu[k][c] = 0.0;
+                        la[k][c] = tau * aa.lam_dp[c * aa.nodes + gn];
+                    }
+                }
                 cb[0] = i0[0]; cb[1] = i0[1]; cb[2] = i0[2];
                 have = true;
             }
@@ -2485,9 +2541,7 @@ __global__ __launch_bounds__(256) void k_adj_couple(const BoxDev* __restrict__ b
             double lw[8];
 #pragma unroll
             for (int k = 0; k < 8; ++k) {
-                const uint64_t gn = bx.node_off + cnode[k];
-                const double la0 = tau * aa.lam_dp[gn], la1 = tau * aa.lam_dp[aa.nodes + gn],
-                             la2 = tau * aa.lam_dp[2 * aa.nodes + gn];
+                const double la0 = la[k][0], la1 = la[k][1], la2 = la[k][2];
                 lfc[0] -= dt * wt[k] * la0; lfc[1] -= dt * wt[k] * la1; lfc[2] -= dt * wt[k] * la2;
                 lw[k] = -dt * (fc[0] * la0 + fc[1] * la1 + fc[2] * la2);
             }
