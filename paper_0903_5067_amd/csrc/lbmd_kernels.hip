@@ -2571,33 +2571,50 @@ __global__ __launch_bounds__(256) void k_adj_couple(const BoxDev* __restrict__ b
                 lx1[1] += lw[k] * (((k >> 1) & 1) ? 1.0 : -1.0) * g0 * g2;
                 lx1[2] += lw[k] * (((k >> 2) & 1) ? 1.0 : -1.0) * g0 * g1;
             }
-            // conservative forces at x1: lam_x1_b += sum_j K_bj (lam_F_b - lam_F_j),
-            // this lane's share of the partners, summed over the lanes
+            // conservative forces at x1: lam_x1_b += sum_j K_bj (lam_F_b - lam_F_j).
+            // The repulsive LJ pairs: this lane's share of the partners, four
+            // at a time (their terms are computed side by side, then added in
+            // ascending j), summed over the lanes
             double lp[3] = {0, 0, 0};
-            for (int j = lane; j < N; j += T) {
-                if (j == b) continue;
-                const double dl[3] = {lft[0] - lF[3 * j], lft[1] - lF[3 * j + 1], lft[2] - lF[3 * j + 2]};
-                if ((j == b - 1 || j == b + 1) && j >= sp.lo && j <= sp.hi) {
-                    const double d[3] = {x1[0] - xs[3 * j], x1[1] - xs[3 * j + 1], x1[2] - xs[3 * j + 2]};
-                    const double r2 = d[0] * d[0] + d[1] * d[1] + d[2] * d[2];
-                    const double den = 1.0 - r2 * bx.inv_r0sq;
-                    const double gfe = -bx.k_fene / den;
-                    const double gpe = -bx.k_fene * bx.inv_r0sq / (den * den);
-                    pair_kernel(d, gfe, gpe, dl, lp);
+            for (int j0 = lane; j0 < N; j0 += 4 * T) {
+                double d[4][3], dl[4][3], gw[4], gpw[4];
+                bool hit[4];
+#pragma unroll
+                for (int u = 0; u < 4; ++u) {
+                    const int jj = j0 + u * T;
+                    const int j = jj < N ? jj : b;   // past the end: the bead itself, masked
+#pragma unroll
+                    for (int c = 0; c < 3; ++c) {
+                        dl[u][c] = lft[c] - lF[3 * j + c];
+                        d[u][c] = x1[c] - xs[3 * j + c];
+                        d[u][c] -= Ld * rint(d[u][c] * iL);
+                    }
+                    const double q = d[u][0] * d[u][0] + d[u][1] * d[u][1] + d[u][2] * d[u][2];
+                    hit[u] = j != b && q < bx.rc2;
+                    const double iq = 1.0 / (hit[u] ? q : 1.0), iq4 = iq * iq * iq * iq, iq7 = iq4 * iq * iq * iq;
+                    gw[u] = eps24 * (2.0 * s12c * iq7 - s6c * iq4);
+                    gpw[u] = eps24 * (-14.0 * s12c * iq7 * iq + 4.0 * s6c * iq4 * iq);
                 }
-                double d[3] = {x1[0] - xs[3 * j], x1[1] - xs[3 * j + 1], x1[2] - xs[3 * j + 2]};
-                d[0] -= Ld * rint(d[0] * iL); d[1] -= Ld * rint(d[1] * iL); d[2] -= Ld * rint(d[2] * iL);
-                const double q = d[0] * d[0] + d[1] * d[1] + d[2] * d[2];
-                if (q < bx.rc2) {
-                    const double iq = 1.0 / q, iq4 = iq * iq * iq * iq, iq7 = iq4 * iq * iq * iq;
-                    const double gw = eps24 * (2.0 * s12c * iq7 - s6c * iq4);
-                    const double gpw = eps24 * (-14.0 * s12c * iq7 * iq + 4.0 * s6c * iq4 * iq);
-                    pair_kernel(d, gw, gpw, dl, lp);
-                }
+#pragma unroll
+                for (int u = 0; u < 4; ++u)
+                    if (hit[u]) pair_kernel(d[u], gw[u], gpw[u], dl[u], lp);
             }
             for (int o = 1; o < T; o <<= 1) {
 #pragma unroll
                 for (int c = 0; c < 3; ++c) lp[c] += __shfl_xor(lp[c], o, T);
+            }
+            // the bonds (FENE) to b - 1 and b + 1, the same in every lane
+#pragma unroll
+            for (int side = 0; side < 2; ++side) {
+                const int j = side ? b + 1 : b - 1;
+                if (j < sp.lo || j > sp.hi) continue;
+                const double dl[3] = {lft[0] - lF[3 * j], lft[1] - lF[3 * j + 1], lft[2] - lF[3 * j + 2]};
+                const double d[3] = {x1[0] - xs[3 * j], x1[1] - xs[3 * j + 1], x1[2] - xs[3 * j + 2]};
+                const double r2 = d[0] * d[0] + d[1] * d[1] + d[2] * d[2];
+                const double den = 1.0 - r2 * bx.inv_r0sq;
+                const double gfe = -bx.k_fene / den;
+                const double gpe = -bx.k_fene * bx.inv_r0sq / (den * den);
+                pair_kernel(d, gfe, gpe, dl, lp);
             }
             lx1[0] += lp[0]; lx1[1] += lp[1]; lx1[2] += lp[2];
         }
