@@ -712,12 +712,24 @@ __global__ __launch_bounds__(256) void k_node_field(const BoxDev* __restrict__ b
     o[0] = u[0]; o[1] = u[1]; o[2] = u[2];
 }
 
+// the box fields a fix-up uses, read once
+struct FixBox {
+    int L;
+    uint32_t seed, box_id;
+    uint64_t pop_off, node_off;
+    double inv_L;
+};
+__device__ __forceinline__ FixBox fix_box(const BoxDev& bx)
+{
+    return FixBox{bx.L, bx.seed, bx.box_id, bx.pop_off, bx.node_off, bx.inv_L};
+}
+
 // fix-up of one node after the plain collide: defined with the fix-up kernels
 template <typename R>
-__device__ __forceinline__ void fixup_node(const BoxDev& bx, const CollideConst<R>* __restrict__ ccs, int bi,
-                                           uint32_t r, unsigned long long* __restrict__ imp,
-                                           uint32_t* __restrict__ claim, const R* __restrict__ A, R* __restrict__ B,
-                                           Ctrl* __restrict__ ctrl, uint32_t t, int keep_imp);
+__device__ __forceinline__ void fixup_node(const FixBox& bx, const CollideConst<R>& cc, uint32_t r,
+                                           unsigned long long* __restrict__ imp, uint32_t* __restrict__ claim,
+                                           const R* __restrict__ A, R* __restrict__ B, Ctrl* __restrict__ ctrl,
+                                           uint32_t t, int keep_imp);
 
 // the same fix-up (impulses left in the field), the node claimed before its
 // populations are read: fewer live registers, for a rare path inside a
@@ -769,7 +781,7 @@ __device__ __forceinline__ void near_work(const BoxDev* __restrict__ boxes, cons
             const uint64_t g = ca.ovf[2 * (uint64_t)e];
             const uint32_t r = ca.ovf[2 * (uint64_t)e + 1];
             const int bi = bead_box[g];
-            fixup_node<R>(boxes[bi], ccs, bi, r, ca.imp, claim, Aprev, A, ctrl, t - 1u, 1);
+            fixup_node<R>(fix_box(boxes[bi]), ccs[bi], r, ca.imp, claim, Aprev, A, ctrl, t - 1u, 1);
         }
     }
     // one_box >= 0: the launch covers that box alone, its descriptor passed by
@@ -1526,10 +1538,10 @@ __global__ __launch_bounds__(256) void k_gather_imp(const BoxDev* __restrict__ b
 // and step do it: the populations and the impulse are loaded before the
 // claim returns, so the three latencies overlap.
 template <typename R>
-__device__ __forceinline__ void fixup_node(const BoxDev& bx, const CollideConst<R>* __restrict__ ccs, int bi,
-                                           uint32_t r, unsigned long long* __restrict__ imp,
-                                           uint32_t* __restrict__ claim, const R* __restrict__ A,
-                                           R* __restrict__ B, Ctrl* __restrict__ ctrl, uint32_t t, int keep_imp)
+__device__ __forceinline__ void fixup_node(const FixBox& bx, const CollideConst<R>& cc, uint32_t r,
+                                           unsigned long long* __restrict__ imp, uint32_t* __restrict__ claim,
+                                           const R* __restrict__ A, R* __restrict__ B, Ctrl* __restrict__ ctrl,
+                                           uint32_t t, int keep_imp)
 {
     const uint64_t node = bx.node_off + r;
     const Upwind up = upwind_of(r, bx.L, bx.inv_L);
@@ -1539,7 +1551,6 @@ __device__ __forceinline__ void fixup_node(const BoxDev& bx, const CollideConst<
     const unsigned long long q0 = q[0], q1 = q[1], q2 = q[2];
     if (atomicExch(&claim[node], t + 1u) == t + 1u) return;   // another caller took this node
     if (!keep_imp) { q[0] = 0ull; q[1] = 0ull; q[2] = 0ull; }
-    const CollideConst<R> cc = ccs[bi];
     const R fx = (R)((double)(long long)q0 * IMP_INV_SCALE), fy = (R)((double)(long long)q1 * IMP_INV_SCALE),
             fz = (R)((double)(long long)q2 * IMP_INV_SCALE);
     R o[19];
@@ -1569,18 +1580,24 @@ __global__ __launch_bounds__(256) void k_fixup(const BoxDev* __restrict__ boxes,
     const uint64_t g = bead0 + e / (uint32_t)FIX_LANES;
     const int j = (int)(e % (uint32_t)FIX_LANES);
     // independent loads together: the slot count, the box, the first slot
-    // (read for every thread, used below the count) and the step
+    // (read for every thread, used below the count) and the step; then, in
+    // one more round, every field of the box and its collision constants
     const int cnt = ca.touched_cnt[g];
     const int bi = bead_box[g];
     const uint32_t r0 = ca.touched[g * ca.touch_cap + j];
     const uint32_t t = ctrl->step + s_off;
-    if (j >= cnt) return;
     const BoxDev& bx = boxes[bi];
-    if (bx.dense) return;   // its collide takes the impulses itself
-    if (skip_big && bx.N > BIG_CHAIN) return;
-    fixup_node<R>(bx, ccs, bi, r0, ca.imp, claim, A, B, ctrl, t, keep_imp);
+    const FixBox fb = fix_box(bx);
+    const int dense = bx.dense, nb = bx.N;
+    const CollideConst<R> cc = ccs[bi];
+    // a dense box's collide takes the impulses itself
+    // (one test, so that no load waits for another's branch; the empty asm
+    // keeps the box fields' loads above it, beside the tested ones)
+    asm volatile("" ::"v"(fb.L), "v"(fb.pop_off), "v"(fb.node_off), "v"(fb.inv_L), "v"(fb.seed), "v"(fb.box_id));
+    if ((j >= cnt) | (dense != 0) | ((skip_big != 0) & (nb > BIG_CHAIN))) return;
+    fixup_node<R>(fb, cc, r0, ca.imp, claim, A, B, ctrl, t, keep_imp);
     for (int k = j + FIX_LANES; k < cnt; k += FIX_LANES)
-        fixup_node<R>(bx, ccs, bi, ca.touched[g * ca.touch_cap + k], ca.imp, claim, A, B, ctrl, t, keep_imp);
+        fixup_node<R>(fb, cc, ca.touched[g * ca.touch_cap + k], ca.imp, claim, A, B, ctrl, t, keep_imp);
 }
 
 // End of a step that deferred tiles (one workgroup): fix the listed nodes
@@ -1601,7 +1618,7 @@ __global__ __launch_bounds__(256) void k_overflow(const BoxDev* __restrict__ box
         const uint64_t g = ca.ovf[2 * (uint64_t)e];
         const uint32_t r = ca.ovf[2 * (uint64_t)e + 1];
         const int bi = bead_box[g];
-        fixup_node<R>(boxes[bi], ccs, bi, r, ca.imp, claim, A, B, ctrl, t, 0);
+        fixup_node<R>(fix_box(boxes[bi]), ccs[bi], r, ca.imp, claim, A, B, ctrl, t, 0);
     }
     __syncthreads();   // every thread has read the count and the step
     if (threadIdx.x == 0) {
