@@ -2422,9 +2422,11 @@ __device__ __forceinline__ void pair_kernel(const double d[3], double g, double 
 // Reverse sweep of one LB step's substeps for chains of at most 256 beads.
 // Thread layout as in the forward kernel: T lanes per bead (T a function of
 // N only), bead b = tid / T.  All lanes of a bead carry identical copies of
-// the bead's adjoint; the pair loop of the force Hessian is split over the
-// lanes (partners j = lane mod T) and combined by a butterfly, which gives
-// every lane the same bits; lane 0 writes and performs the atomics.
+// the bead's adjoint; the repulsive-LJ pairs of the force Hessian are split
+// over the lanes (partners j = lane mod T) and combined by a butterfly, which
+// gives every lane the same bits, and every lane adds the two bonds' terms;
+// the lanes share the stencil's density gathers; lane 0 writes and performs
+// the atomics.
 template <typename R>
 __global__ __launch_bounds__(256) void k_adj_couple(const BoxDev* __restrict__ boxes,
                                                     const int32_t* __restrict__ couple_list, const R* __restrict__ P,
