@@ -82,13 +82,14 @@ def test_couple_matches_oracle(orc, prec):
     assert max_rel_pop_err(ng, o.n, orc) < (1e-12 if prec == FP64 else 1e-5)
 
 
-@pytest.mark.parametrize("N", [16, 64, 128])
+@pytest.mark.parametrize("N", [16, 64, 128, 256])
 def test_couple_partner_lists_rebuilt_within_a_step(orc, N):
     """A hot chain whose beads move more than half the list skin (0.25)
     within one LB step: the one-workgroup coupling kernel rebuilds its
     per-lane partner lists inside the step, and ten steps still match the
-    oracle's all-pairs forces (FP64).  N = 16, 64, 128 run with 16, 4 and 2
-    lanes per bead."""
+    oracle's all-pairs forces (FP64).  N = 16, 64, 128, 256 run with 16, 4, 2
+    and 1 lanes per bead (the stencil refill split over 8, 4, 2 lanes and
+    done by one)."""
     say("partner lists rebuilt within a step", N)
     hot = dict(kT=1.0, therm=0, md_dt=0.01, md_substeps=25, tau_lb=0.25, zeta=1.0, k_fene=7.0, r0_fene=2.0)
     p = params(L=12, N=N, seed=3, **hot)
