@@ -433,8 +433,8 @@ def test_deferred_tiles_equal_fixup_after_collide_bitwise(prec, graph_steps):
 @pytest.mark.parametrize("prec,graph_steps,resident",
                          [(FP64, 0, True), (FP32, 0, True), (FP64, 4, True), (FP32, 6, True),
                           (FP32, 0, False), (FP32, 6, False)])
-@pytest.mark.parametrize("small", [True, False])
-def test_two_queue_runs_equal_fixup_after_collide_bitwise(prec, graph_steps, resident, small):
+@pytest.mark.parametrize("batch", ["small chain", "large chains", "one large chain"])
+def test_two_queue_runs_equal_fixup_after_collide_bitwise(prec, graph_steps, resident, batch):
     """With no dense box, a run of batched steps puts the chain work of step k
     right behind the collide of step k-1, where the previous step's impulses
     outside its deferred tiles are re-collided too.  With a small chain in
@@ -445,22 +445,27 @@ def test_two_queue_runs_equal_fixup_after_collide_bitwise(prec, graph_steps, res
     steps) give the bits of twelve steps with the chains' nodes re-collided
     after each collide; the hot box's beads leave their node tables within
     the twelve steps.  Launch mode 3 (resident=False) keeps the node tables in
-    a kernel of their own, with the same bits."""
-    say("two-queue runs vs fix-up", prec, graph_steps, "small chain" if small else "large chains only",
-        "resident" if resident else "no resident wait")
+    a kernel of their own, with the same bits.  The batches hold a small
+    chain beside two large ones, two large chains, or one large chain."""
+    say("two-queue runs vs fix-up", prec, graph_steps, batch, "resident" if resident else "no resident wait")
     hot = dict(kT=1.0, therm=0, md_dt=0.01, md_substeps=25, tau_lb=0.25, zeta=1.0, k_fene=7.0, r0_fene=2.0)
-    boxes = [params(L=40, N=300, kT=1e-2, seed=7, box_id=0),
-             params(L=40, N=300, seed=7, box_id=1, **hot)]
-    if small:
+    if batch == "one large chain":
+        boxes = [params(L=48, N=300, seed=7, box_id=0, **hot)]
+    else:
+        boxes = [params(L=40, N=300, kT=1e-2, seed=7, box_id=0),
+                 params(L=40, N=300, seed=7, box_id=1, **hot)]
+    if batch == "small chain":
         boxes.append(params(L=12, N=16, kT=1e-2, seed=7, box_id=2))
+    hot_box = len(boxes) - 1 if batch == "one large chain" else 1
+    lo, hi = 300 * hot_box, 300 * hot_box + 300
     xs = [chain(b) for b in boxes]
     ref = gpu_system(boxes, prec, xs=xs)
     ref.set_launch(batched=True, graph_steps=0, overlap=False)
     left = 0
     for _ in range(12):
-        x_a = ref.bead_positions()[300:600]
+        x_a = ref.bead_positions()[lo:hi]
         ref.step(1)
-        left += int(_left_table(x_a, ref.bead_positions()[300:600], 40).sum())
+        left += int(_left_table(x_a, ref.bead_positions()[lo:hi], int(boxes[hot_box]["L"])).sum())
     assert left > 0
     assert all(o["health"] == 0 for o in ref.observables())
     want = ref.export_state()["boxes"]
