@@ -269,7 +269,10 @@ lb_status lb_set_launch(lb_handle* h, int32_t batched, int32_t graph_steps);
  * the noise from Philox, and rebuilds forward states from checkpoints taken
  * every k steps.  Chains of at most 256 beads.  The workspace d_ws is device
  * memory owned by the caller, lb_window_bytes(h, T, k) bytes, 256-aligned,
- * kept unchanged between the forward and backward calls. */
+ * kept unchanged between the forward and backward calls.  It holds the
+ * checkpoints and two tapes of k steps each, so that the backward replays one
+ * segment on the handle's stream while it reverses the one after it on a
+ * second stream of its own. */
 size_t lb_window_bytes(const lb_handle* h, int32_t T, int32_t k);
 /* Run T steps (the lb_step of Sec. II.B) from the current state,
  * checkpointing every k steps into d_ws; bead velocities after each step go to

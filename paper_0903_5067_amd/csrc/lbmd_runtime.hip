@@ -333,7 +333,7 @@ lb_status fail(lb_handle* h, lb_status s, const std::string& msg)
 // zero every per-node and per-tile step stamp and the step-tagged control
 // words (after the step count is set back), on the handle's stream, then
 // wait for it; outside any graph
-hipError_t clear_step_stamps(lb_handle* h)
+hipError_t clear_step_stamps(lb_handle* h, bool sync = true)
 {
     const Layout& lo = h->lo;
     if (!lo.total_beads) return hipSuccess;
@@ -350,7 +350,7 @@ hipError_t clear_step_stamps(lb_handle* h)
         if (e == hipSuccess)
             e = hipMemsetAsync(h->scratch + lo.sc_ovm, 0, lo.total_nodes * sizeof(uint32_t), h->stream);
     }
-    if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
+    if (e == hipSuccess && sync) e = hipStreamSynchronize(h->stream);
     return e;
 }
 
@@ -1220,9 +1220,12 @@ lb_status lb_set_launch(lb_handle* h, int32_t batched, int32_t graph_steps)
 // ------------------------------------------------------------ adjoint window
 namespace {
 
+// Two tape sets (populations, impulses, substep records, starting beads of
+// each step of a segment): the backward replays one segment into one set
+// while it reverses the previously replayed segment from the other.
 struct WinLayout {
-    size_t ck_pop, ck_beads, tape_pop, tape_imp, tape_sub, tape_beads, vh, dj, lam_a, lam_b, lam_dp, lbeads, gpart,
-        gz, bytes;
+    size_t ck_pop, ck_beads, tape_pop[2], tape_imp[2], tape_sub[2], tape_beads[2], vh, dj, lam_a, lam_b, lam_dp,
+        lbeads, gpart, gz, bytes;
     size_t bspan;   // bytes of the state's x, v, f arrays, gaps included
     int nc;
 };
@@ -1239,11 +1242,13 @@ WinLayout win_layout(const lb_handle* h, int T, int k)
     size_t o = 0;
     w.ck_pop = o; o = align256(o + (size_t)(w.nc + 1) * popb);
     w.ck_beads = o; o = align256(o + (size_t)(w.nc + 1) * 12 * nb * sizeof(double));
-    w.tape_pop = o; o = align256(o + (size_t)(k + 1) * popb);
-    w.tape_imp = o; o = align256(o + (size_t)k * 3 * nodes * sizeof(unsigned long long));
-    w.tape_sub = o; o = align256(o + (size_t)k * smax * nb * TAPE_REC * sizeof(double));
     w.bspan = lo.st_fc - lo.st_x;   // x, v, f of the state, with their alignment gaps
-    w.tape_beads = o; o = align256(o + (size_t)k * w.bspan);
+    for (int b = 0; b < 2; ++b) {
+        w.tape_pop[b] = o; o = align256(o + (size_t)(k + 1) * popb);
+        w.tape_imp[b] = o; o = align256(o + (size_t)k * 3 * nodes * sizeof(unsigned long long));
+        w.tape_sub[b] = o; o = align256(o + (size_t)k * smax * nb * TAPE_REC * sizeof(double));
+        w.tape_beads[b] = o; o = align256(o + (size_t)k * w.bspan);
+    }
     w.vh = o; o = align256(o + (size_t)T * 3 * nb * sizeof(double));
     w.dj = o; o = align256(o + (size_t)T * 3 * nb * sizeof(double));
     w.lam_a = o; o = align256(o + 19 * nodes * sizeof(double));
@@ -1269,21 +1274,39 @@ lb_status ck_save(lb_handle* h, char* ws, const WinLayout& w, int j)
     return LB_OK;
 }
 
-lb_status ck_restore(lb_handle* h, char* ws, const WinLayout& w, int j, uint64_t step)
+// enqueue on the main stream the copy of slot j's beads into the state
+lb_status ck_restore_beads(lb_handle* h, char* ws, const WinLayout& w, int j)
 {
     const Layout& lo = h->lo;
-    const size_t popb = lo.pop_elems * lo.esz, bb = 3 * std::max<uint64_t>(lo.total_beads, 1) * sizeof(double);
-    h->cur = 0;
-    HIPCHK(h, hipMemcpyAsync(h->pop(0), ws + w.ck_pop + j * popb, popb, hipMemcpyDeviceToDevice, h->stream));
+    const size_t bb = 3 * std::max<uint64_t>(lo.total_beads, 1) * sizeof(double);
     const char* src = ws + w.ck_beads + (size_t)j * 4 * bb;
     const size_t arrs[4] = {lo.st_x, lo.st_v, lo.st_f, lo.st_fc};
     for (int a = 0; a < 4; ++a)
         HIPCHK(h, hipMemcpyAsync(h->state + arrs[a], src + a * bb, bb, hipMemcpyDeviceToDevice, h->stream));
+    return LB_OK;
+}
+
+// set the device step counter (the main stream is drained first)
+lb_status set_device_step(lb_handle* h, uint64_t step)
+{
+    const Layout& lo = h->lo;
     HIPCHK(h, hipStreamSynchronize(h->stream));
     Ctrl ctrl;
     HIPCHK(h, hipMemcpy(&ctrl, h->scratch + lo.sc_ctrl, sizeof ctrl, hipMemcpyDeviceToHost));
     ctrl.step = (uint32_t)step;
     HIPCHK(h, hipMemcpy(h->scratch + lo.sc_ctrl, &ctrl, sizeof ctrl, hipMemcpyHostToDevice));
+    return LB_OK;
+}
+
+lb_status ck_restore(lb_handle* h, char* ws, const WinLayout& w, int j, uint64_t step)
+{
+    const Layout& lo = h->lo;
+    const size_t popb = lo.pop_elems * lo.esz;
+    h->cur = 0;
+    HIPCHK(h, hipMemcpyAsync(h->pop(0), ws + w.ck_pop + j * popb, popb, hipMemcpyDeviceToDevice, h->stream));
+    lb_status s = ck_restore_beads(h, ws, w, j);
+    if (s == LB_OK) s = set_device_step(h, step);
+    if (s != LB_OK) return s;
     HIPCHK(h, clear_step_stamps(h));
     h->step = step;
     return LB_OK;
@@ -1436,57 +1459,85 @@ lb_status lb_window_backward(lb_handle* h, void* d_ws, size_t bytes, const doubl
         HIPCHK(h, hipMemcpy(h->ccd, cc.data(), cc.size() * sizeof(cc[0]), hipMemcpyHostToDevice));
     }
     HIPCHK(h, hipStreamSynchronize(h->stream));
+    HIPCHK(h, hipStreamSynchronize(h->stream2));
     // keep the end-of-window state, restored at the end
     lb_status st = ck_save(h, ws, w, w.nc);
     if (st != LB_OK) return st;
     const uint64_t step_end = h->step;
     const int cur_end = h->cur;
-    HIPCHK(h, hipMemcpyAsync(ws + w.dj, dj_host, (size_t)T * nb3 * sizeof(double), hipMemcpyHostToDevice, h->stream));
-    HIPCHK(h, hipMemsetAsync(ws + w.lam_a, 0, 19 * nodes * sizeof(double), h->stream));
-    HIPCHK(h, hipMemsetAsync(ws + w.lam_b, 0, 19 * nodes * sizeof(double), h->stream));
-    HIPCHK(h, hipMemsetAsync(ws + w.lbeads, 0, 9 * nbx * sizeof(double), h->stream));
-    HIPCHK(h, hipMemsetAsync(ws + w.gpart, 0, 2 * lo.total_tiles * sizeof(double), h->stream));
-    HIPCHK(h, hipMemsetAsync(ws + w.gz, 0, h->n_boxes * sizeof(double), h->stream));
+    // The segments are replayed on the main stream and reversed on the second
+    // one: the replay of segment s - 1 (into one tape set) runs while segment
+    // s is reversed (from the other).  The reverse kernels read only the tape,
+    // the adjoint fields and the box tables, never the live state the replay
+    // advances.
+    hipStream_t rs = h->stream2;
+    LaunchCtx rc = h->ctx2;
+    struct Events {
+        hipEvent_t e[4] = {};
+        ~Events() { for (hipEvent_t x : e) if (x) (void)hipEventDestroy(x); }
+    } ev;
+    for (hipEvent_t& x : ev.e) HIPCHK(h, hipEventCreateWithFlags(&x, hipEventDisableTiming));
+    hipEvent_t* replayed = ev.e;      // per tape set: its segment is recorded
+    hipEvent_t* reversed = ev.e + 2;  // per tape set: its segment is reversed, the set is free
+    bool in_use[2] = {false, false};
+    HIPCHK(h, hipMemcpyAsync(ws + w.dj, dj_host, (size_t)T * nb3 * sizeof(double), hipMemcpyHostToDevice, rs));
+    HIPCHK(h, hipMemsetAsync(ws + w.lam_a, 0, 19 * nodes * sizeof(double), rs));
+    HIPCHK(h, hipMemsetAsync(ws + w.lam_b, 0, 19 * nodes * sizeof(double), rs));
+    HIPCHK(h, hipMemsetAsync(ws + w.lbeads, 0, 9 * nbx * sizeof(double), rs));
+    HIPCHK(h, hipMemsetAsync(ws + w.gpart, 0, 2 * lo.total_tiles * sizeof(double), rs));
+    HIPCHK(h, hipMemsetAsync(ws + w.gz, 0, h->n_boxes * sizeof(double), rs));
     double* lam_next = (double*)(ws + w.lam_a);
     double* lam_cur = (double*)(ws + w.lam_b);
     double* lb = (double*)(ws + w.lbeads);
+    // the device step counter stays at the window's first step; each replayed
+    // step passes its offset in the window
+    st = set_device_step(h, h->win_step0);
+    if (st != LB_OK) return st;
     for (int seg = w.nc - 1; seg >= 0; --seg) {
-        const int t0 = seg * k, t1 = std::min(T, t0 + k);
-        st = ck_restore(h, ws, w, seg, h->win_step0 + t0);
+        const int t0 = seg * k, t1 = std::min(T, t0 + k), tb = seg & 1;
+        char* tpop = ws + w.tape_pop[tb];
+        char* timp = ws + w.tape_imp[tb];
+        char* tsub = ws + w.tape_sub[tb];
+        char* tbeads = ws + w.tape_beads[tb];
+        st = ck_restore_beads(h, ws, w, seg);
         if (st != LB_OK) return st;
+        HIPCHK(h, clear_step_stamps(h, false));
+        // the set was last read by the reverse of segment seg + 2
+        if (in_use[tb]) HIPCHK(h, hipStreamWaitEvent(h->stream, reversed[tb], 0));
         // replay the segment, recording what the reverse sweep needs: step j
         // reads tape slot j and writes slot j + 1, and adds its impulses into
         // its own zeroed impulse slot
-        HIPCHK(h, hipMemcpyAsync(ws + w.tape_pop, h->pop(h->cur), popb, hipMemcpyDeviceToDevice, h->stream));
-        HIPCHK(h, hipMemsetAsync(ws + w.tape_imp, 0, (size_t)(t1 - t0) * 3 * nodes * 8, h->stream));
+        HIPCHK(h, hipMemcpyAsync(tpop, ws + w.ck_pop + seg * popb, popb, hipMemcpyDeviceToDevice, h->stream));
+        HIPCHK(h, hipMemsetAsync(timp, 0, (size_t)(t1 - t0) * 3 * nodes * 8, h->stream));
         for (int t = t0; t < t1; ++t) {
             const int j = t - t0;
             // the coupling kernel records the step's starting beads in slot j
-            st = window_step(h, ws + w.tape_pop + j * popb, ws + w.tape_pop + (j + 1) * popb,
-                             (unsigned long long*)(ws + w.tape_imp + (size_t)j * 3 * nodes * 8),
-                             (double*)(ws + w.tape_sub + (size_t)j * smax * nbx * TAPE_REC * sizeof(double)),
-                             (double*)(ws + w.tape_beads + (size_t)j * w.bspan), nullptr, 0, (uint32_t)j);
+            st = window_step(h, tpop + j * popb, tpop + (j + 1) * popb,
+                             (unsigned long long*)(timp + (size_t)j * 3 * nodes * 8),
+                             (double*)(tsub + (size_t)j * smax * nbx * TAPE_REC * sizeof(double)),
+                             (double*)(tbeads + (size_t)j * w.bspan), nullptr, 0, (uint32_t)t);
             if (st != LB_OK) return st;
         }
-        HIPCHK(h, launch_advance(h->ctx, (uint32_t)(t1 - t0)));
+        HIPCHK(h, hipEventRecord(replayed[tb], h->stream));
+        HIPCHK(h, hipStreamWaitEvent(rs, replayed[tb], 0));
         // reverse the segment's steps
         for (int t = t1 - 1; t >= t0; --t) {
             const int j = t - t0;
             const uint32_t stepv = (uint32_t)(h->win_step0 + t);
-            const char* P = ws + w.tape_pop + j * popb;
-            const unsigned long long* imp = (const unsigned long long*)(ws + w.tape_imp + (size_t)j * 3 * nodes * 8);
-            HIPCHK(h, f64 ? launch_adj_collide<double>(h->ctx, h->ccd, P, imp, lam_next, lam_cur,
+            const char* P = tpop + j * popb;
+            const unsigned long long* imp = (const unsigned long long*)(timp + (size_t)j * 3 * nodes * 8);
+            HIPCHK(h, f64 ? launch_adj_collide<double>(rc, h->ccd, P, imp, lam_next, lam_cur,
                                                        (double*)(ws + w.lam_dp), (double*)(ws + w.gpart), nodes,
                                                        (uint32_t)lo.total_tiles, stepv)
-                          : launch_adj_collide<float>(h->ctx, h->ccd, P, imp, lam_next, lam_cur,
+                          : launch_adj_collide<float>(rc, h->ccd, P, imp, lam_next, lam_cur,
                                                       (double*)(ws + w.lam_dp), (double*)(ws + w.gpart), nodes,
                                                       (uint32_t)lo.total_tiles, stepv));
             AdjArgsHost a;
-            const char* tb = ws + w.tape_beads + (size_t)j * w.bspan;   // x, v, f as laid out in the state
-            a.x0 = (const double*)tb;
-            a.v0 = (const double*)(tb + (lo.st_v - lo.st_x));
-            a.f0 = (const double*)(tb + (lo.st_f - lo.st_x));
-            a.tape = (const double*)(ws + w.tape_sub + (size_t)j * smax * nbx * TAPE_REC * sizeof(double));
+            const char* bj = tbeads + (size_t)j * w.bspan;   // x, v, f as laid out in the state
+            a.x0 = (const double*)bj;
+            a.v0 = (const double*)(bj + (lo.st_v - lo.st_x));
+            a.f0 = (const double*)(bj + (lo.st_f - lo.st_x));
+            a.tape = (const double*)(tsub + (size_t)j * smax * nbx * TAPE_REC * sizeof(double));
             a.dj = (const double*)(ws + w.dj) + (size_t)t * nb3;
             a.lx = lb; a.lv = lb + nb3; a.lf = lb + 2 * nb3;
             a.lam_n = lam_cur;
@@ -1494,15 +1545,17 @@ lb_status lb_window_backward(lb_handle* h, void* d_ws, size_t bytes, const doubl
             a.gz = (double*)(ws + w.gz);
             a.nodes = nodes;
             const int nc = (int)h->couple_host.size();
-            HIPCHK(h, f64 ? launch_adj_couple<double>(h->ctx, h->couple_list, nc, lo.couple_block, P, a, stepv)
-                          : launch_adj_couple<float>(h->ctx, h->couple_list, nc, lo.couple_block, P, a, stepv));
+            HIPCHK(h, f64 ? launch_adj_couple<double>(rc, h->couple_list, nc, lo.couple_block, P, a, stepv)
+                          : launch_adj_couple<float>(rc, h->couple_list, nc, lo.couple_block, P, a, stepv));
             std::swap(lam_next, lam_cur);
         }
+        HIPCHK(h, hipEventRecord(reversed[tb], rs));
+        in_use[tb] = true;
     }
     std::vector<double> gpart(2 * lo.total_tiles), gz(h->n_boxes);
-    HIPCHK(h, hipMemcpyAsync(gpart.data(), ws + w.gpart, gpart.size() * sizeof(double), hipMemcpyDeviceToHost,
-                             h->stream));
-    HIPCHK(h, hipMemcpyAsync(gz.data(), ws + w.gz, gz.size() * sizeof(double), hipMemcpyDeviceToHost, h->stream));
+    HIPCHK(h, hipMemcpyAsync(gpart.data(), ws + w.gpart, gpart.size() * sizeof(double), hipMemcpyDeviceToHost, rs));
+    HIPCHK(h, hipMemcpyAsync(gz.data(), ws + w.gz, gz.size() * sizeof(double), hipMemcpyDeviceToHost, rs));
+    HIPCHK(h, hipStreamSynchronize(rs));
     HIPCHK(h, hipStreamSynchronize(h->stream));
     for (int i = 0; i < h->n_boxes; ++i) {
         double gs = 0.0, gb = 0.0;
