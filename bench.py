@@ -109,6 +109,21 @@ def copy_calibration():
                                            "gb_per_s": round(2 * a.numel() * 4 / us / 1e3, 1)}}))
 
 
+def settle(s, seconds):
+    """Untimed steps, 20 at a time, until the GPU has been busy `seconds` in
+    a row; returns how many ran.  The GPU's clocks drop while it idles (on
+    host work, between the autotuner's launches) and take about 0.1 s of load
+    to come back, so a short window timed right after an idle spell sees
+    them ramping up instead of the sustained rate."""
+    n = 0
+    t0 = time.perf_counter()
+    while time.perf_counter() - t0 < seconds:
+        s.step(20)
+        s.synchronize()
+        n += 20
+    return n
+
+
 def time_steps(s, steps, warmup):
     import torch
     s.step(warmup)
@@ -397,6 +412,9 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--graph-steps", type=int, default=20)
     ap.add_argument("--no-autotune", action="store_true")
+    ap.add_argument("--settle", type=float, default=0.25,
+                    help="seconds of untimed steps before the warm-up steps, so that the timed steps "
+                         "run at sustained clocks (0: --warmup steps only)")
     ap.add_argument("--variant", type=int, default=-1,
                     help="force this collide launch shape instead of autotuning")
     ap.add_argument("--collide-launches", type=int, default=0,
@@ -457,6 +475,7 @@ def main():
                 "us_per_variant": [round(t, 2) for t in times]}
         log("autotune", json.dumps(tune))
     obs0 = s.observables()[0]
+    n_settle = settle(s, args.settle)
     t_ev, t_wall = time_steps(s, args.steps, args.warmup)
     obs1 = s.observables()[0]
     ms = 1e3 * t_ev / args.steps
@@ -474,6 +493,7 @@ def main():
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
+        "settle_steps": n_settle,
         "ms_per_step": round(ms, 5),
         "higher_is_better": True,
         "scaling": "weak",

@@ -241,7 +241,12 @@ lb_status lb_bead_positions(lb_handle* h, double* host_out, size_t bytes);
  * steps the 64-node segments around chains above 256 beads in boxes they do
  * not cover densely are collided beside the other nodes once the chain's
  * impulses are in; batched = 2 re-collides the chain's nodes after the
- * collide instead.  All forms compute the same bits.
+ * collide instead.  Batched steps launched directly (graph_steps = 0) of
+ * boxes with chains of at most 256 beads only, no dense box and at most 2^20
+ * nodes in all run each step's coupling and the re-collision of its nodes
+ * on one queue, the collide beside them on the other (batched = 2, and graph
+ * replays, keep the re-collision behind the collide on the handle's
+ * stream).  All forms compute the same bits.
  * graph_steps > 0 records that many LB steps (rounded up to even) in a HIP
  * graph and replays it; 0 launches kernels directly.  The graphs of both
  * buffer parities are recorded and instantiated here, before returning

@@ -290,6 +290,7 @@ struct lb_handle {
     // collide kernel of the same step (both only read the current state)
     hipStream_t stream2 = nullptr;
     hipEvent_t ev_fork = nullptr, ev_join = nullptr, ev_table = nullptr, ev_head = nullptr, ev_def = nullptr;
+    hipEvent_t ev_coll = nullptr;     // chain-bound runs: this step's collide is done
     LaunchCtx ctx{};
     LaunchCtx ctx2{};
     int32_t* couple_list = nullptr;   // device: boxes on the one-workgroup path (chains <= 256 beads)
@@ -528,6 +529,59 @@ lb_status enqueue_headed_run(lb_handle* h, int from, uint32_t n)
 // tools that run one kernel at a time, such as hardware counter collection:
 // there the waiting chain kernel can hold the GPU while the collide it waits
 // for has not started.
+// Batched coupled steps whose boxes hold chains of at most BIG_CHAIN beads
+// and no dense box, with so few nodes that the collide (~30 us per million
+// nodes in FP32) is shorter than the coupling kernel (a few us per MD
+// substep): the chain's queue sets the step time.
+constexpr uint64_t CHAIN_BOUND_NODES = 1ull << 20;
+bool chain_bound_steps(const lb_handle* h)
+{
+    const Layout& lo = h->lo;
+    return h->batched && h->overlap && !h->couple_host.empty() && lo.big_list.empty() && lo.field_nodes == 0 &&
+           !h->ctx.keep_imp && !h->ctx.tape && lo.total_nodes <= CHAIN_BOUND_NODES;
+}
+
+// A run of n chain-bound steps from buffer `from` (step offsets 0..n-1),
+// launched directly.  The second stream holds the chain work of one step
+// after another: step k's coupling, then, once step k's collide is done, its
+// fix-up.  The handle's stream holds the collides; step k's collide waits
+// for step k-1's fix-up.  So the coupling kernels follow each other's
+// fix-ups on one queue, and the collide beside each of them waits off that
+// path (in the per-step form a coupling kernel waits for the previous
+// fix-up on the other queue, and the fix-up for the coupling kernel).  A
+// replayed graph maps its kernels onto queues of its own choosing, where
+// the per-step form was measured faster, so a stream under capture takes
+// that form.  Every node gets the same collide call with the same impulse
+// as in enqueue_step, so the bits are the same.
+lb_status enqueue_chain_run(lb_handle* h, int from, uint32_t n)
+{
+    const bool f64 = h->prec == LB_FP64;
+    const LaunchCtx& c1 = h->ctx;
+    const LaunchCtx& c2 = h->ctx2;
+    const int nc = (int)h->couple_host.size();
+    const uint32_t ts = (uint32_t)h->lo.tiles_sparse;
+    HIPCHK(h, hipEventRecord(h->ev_fork, h->stream));
+    HIPCHK(h, hipStreamWaitEvent(h->stream2, h->ev_fork, 0));
+    for (uint32_t k = 0; k < n; ++k) {
+        const int p = from ^ (int)(k & 1);
+        const void* A = h->pop(p);
+        void* B = h->pop(1 - p);
+        // step k-1's fix-up wrote into A and read B
+        if (k > 0) HIPCHK(h, hipStreamWaitEvent(h->stream, h->ev_join, 0));
+        HIPCHK(h, f64 ? launch_collide<double>(c1, A, B, -1, 0, ts, k) : launch_collide<float>(c1, A, B, -1, 0, ts, k));
+        HIPCHK(h, hipEventRecord(h->ev_coll, h->stream));
+        HIPCHK(h, f64 ? launch_couple<double>(c2, A, h->couple_list, nc, h->lo.couple_block, k)
+                      : launch_couple<float>(c2, A, h->couple_list, nc, h->lo.couple_block, k));
+        HIPCHK(h, hipStreamWaitEvent(h->stream2, h->ev_coll, 0));
+        if (h->lo.beads_sparse)
+            HIPCHK(h, f64 ? launch_fixup<double>(c2, A, B, 0, h->lo.total_beads, k)
+                          : launch_fixup<float>(c2, A, B, 0, h->lo.total_beads, k));
+        HIPCHK(h, hipEventRecord(h->ev_join, h->stream2));
+    }
+    HIPCHK(h, hipStreamWaitEvent(h->stream, h->ev_join, 0));
+    return LB_OK;
+}
+
 bool fused_steps(const lb_handle* h)
 {
     // the collide's node-table workgroups wait for each other, so they must
@@ -611,6 +665,9 @@ lb_status enqueue_steps(lb_handle* h, int from, uint32_t n)
     if (fused_steps(h) && !capturing(h->stream)) return enqueue_fused_run(h, from, n, n);
     if (headed_steps(h)) {
         const lb_status s = enqueue_headed_run(h, from, n);
+        if (s != LB_OK) return s;
+    } else if (chain_bound_steps(h) && !capturing(h->stream)) {
+        const lb_status s = enqueue_chain_run(h, from, n);
         if (s != LB_OK) return s;
     } else {
         for (uint32_t k = 0; k < n; ++k) {
@@ -845,6 +902,7 @@ lb_status lb_init(const lb_box_desc* boxes, int32_t n_boxes, int32_t precision, 
     if (e == hipSuccess) e = hipEventCreateWithFlags(&h->ev_table, hipEventDisableTiming);
     if (e == hipSuccess) e = hipEventCreateWithFlags(&h->ev_head, hipEventDisableTiming);
     if (e == hipSuccess) e = hipEventCreateWithFlags(&h->ev_def, hipEventDisableTiming);
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&h->ev_coll, hipEventDisableTiming);
     if (e != hipSuccess) {
         std::string msg = std::string("second stream: ") + hipGetErrorString(e);
         lb_free(h);
@@ -1672,6 +1730,7 @@ void lb_free(lb_handle* h)
     if (h->ev_table) (void)hipEventDestroy(h->ev_table);
     if (h->ev_head) (void)hipEventDestroy(h->ev_head);
     if (h->ev_def) (void)hipEventDestroy(h->ev_def);
+    if (h->ev_coll) (void)hipEventDestroy(h->ev_coll);
     if (h->stream2) (void)hipStreamDestroy(h->stream2);
     if (h->own_stream && h->stream) (void)hipStreamDestroy(h->stream);
     delete h;

@@ -482,6 +482,47 @@ def test_two_queue_runs_equal_fixup_after_collide_bitwise(prec, graph_steps, res
 
 
 @pytest.mark.parametrize("prec", [FP64, FP32])
+@pytest.mark.parametrize("graph_steps", [0, 4])
+@pytest.mark.parametrize("batch", ["one box", "three boxes"])
+def test_chain_bound_runs_equal_fixup_after_collide_bitwise(orc, prec, graph_steps, batch):
+    """Small boxes whose chains of at most 256 beads set the step time run
+    each step's coupling and the re-collision of its nodes on one queue, the
+    collide beside them on the other.  Twelve steps give the bits of the
+    single-queue form (the re-collision behind the collide).  The batches
+    hold one 24^3 box with a 64-bead chain, or three boxes of uneven L (one
+    with a hot 16-bead chain whose beads change cells, one with two chains);
+    the one box also matches the oracle."""
+    say("chain-bound runs vs fix-up", prec, graph_steps, batch)
+    hot = dict(kT=1.0, therm=0, md_dt=0.01, md_substeps=25, tau_lb=0.25, zeta=1.0, k_fene=7.0, r0_fene=2.0)
+    if batch == "one box":
+        boxes = [params(L=24, N=64, kT=1e-2, seed=13, box_id=0)]
+    else:
+        boxes = [params(L=24, N=64, kT=1e-2, seed=13, box_id=0),
+                 params(L=16, N=16, seed=13, box_id=1, **hot),
+                 params(L=12, N=20, chain_len=10, kT=1e-2, seed=13, box_id=2)]
+    xs = [chain(b) for b in boxes]
+    out = []
+    for overlap in (True, False):
+        s = gpu_system(boxes, prec, xs=xs)
+        s.set_launch(batched=True, graph_steps=graph_steps, overlap=overlap)
+        s.step(12)
+        assert all(o["health"] == 0 for o in s.observables())
+        out.append(s.export_state()["boxes"])
+        s.close()
+    for i in range(len(boxes)):
+        for k in ("n", "x", "v", "f", "fc"):
+            assert np.array_equal(out[0][i][k], out[1][i][k]), (i, k)
+    if batch == "one box":
+        o = oracle_state(orc, boxes[0], initial_pops(orc, boxes[0]), xs[0])
+        o.run(12)
+        if prec == FP64:
+            assert np.max(np.abs(out[0][0]["n"] - o.n)) < 1e-12
+            assert np.max(np.abs(out[0][0]["x"] - o.x)) < 1e-10
+        else:
+            assert max_rel_pop_err(out[0][0]["n"], o.n, orc) < 1e-5
+
+
+@pytest.mark.parametrize("prec", [FP64, FP32])
 def test_deferred_tiles_after_restoring_an_earlier_step(prec):
     """The deferral stamps of later steps must not survive an import that
     sets the step count back: steps 4..9 replayed from an imported step-3
